@@ -1,0 +1,228 @@
+/*
+ * Betweenness-centrality oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct CPU code used to check the GPU library.  Only
+ * the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code, header or table with the library under
+ * paper_1209_6007_amd/.
+ *
+ * Precision: IEEE binary64 throughout (the paper does not fix a precision).
+ * Scores are over ORDERED source/target pairs with no normalisation, as in the
+ * definition of Section 2.1, Eq. (1).
+ *
+ * Functions:
+ *   oracle_bc_plain     -- Algorithm 1 (Bc-Org, Brandes) on an undirected
+ *                          unweighted graph in CRS form, Section 2.1.
+ *   oracle_bc_weighted  -- Algorithm 2 (Bc-Reach, Section 3.2.1) extended by
+ *                          the identical-vertex rules of Section 3.3.3 (sigma
+ *                          update, dependency update and accumulation weighted
+ *                          by ident).  Returns bc' of the attributed graph.
+ *   oracle_single_source-- one source of the weighted algorithm, returning the
+ *                          BFS levels, path counts and dependencies.
+ *
+ * Threads split the source list into contiguous static blocks; each thread
+ * keeps private arrays and the per-thread scores are added in thread order,
+ * so a given (input, thread count) always produces the same bits.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *reach;   /* NULL => all ones */
+    const int32_t *ident;   /* NULL => all ones */
+    const int32_t *sources; /* NULL => 0..n-1 */
+    int64_t src_begin, src_end;
+    int weighted;
+    double *bc;             /* private accumulator, length n */
+    int status;
+} oracle_job;
+
+/* Workspace of one traversal: queue Q, stack S, predecessor lists P, and the
+ * arrays sigma, d, delta of Algorithm 1. */
+typedef struct {
+    int32_t *Q, *S, *Pcnt, *Pbuf, *d;
+    double *sigma, *delta;
+} oracle_ws;
+
+static int ws_alloc(oracle_ws *w, int32_t n, int64_t arcs) {
+    size_t nn = n > 0 ? (size_t)n : 1;
+    w->Q = malloc(nn * sizeof(int32_t));
+    w->S = malloc(nn * sizeof(int32_t));
+    w->Pcnt = malloc(nn * sizeof(int32_t));
+    w->Pbuf = malloc((arcs > 0 ? (size_t)arcs : 1) * sizeof(int32_t));
+    w->d = malloc(nn * sizeof(int32_t));
+    w->sigma = malloc(nn * sizeof(double));
+    w->delta = malloc(nn * sizeof(double));
+    return w->Q && w->S && w->Pcnt && w->Pbuf && w->d && w->sigma && w->delta;
+}
+
+static void ws_free(oracle_ws *w) {
+    free(w->Q); free(w->S); free(w->Pcnt); free(w->Pbuf); free(w->d);
+    free(w->sigma); free(w->delta);
+}
+
+/*
+ * One source s.  Phase 1 is the BFS of Algorithm 1: every vertex popped from
+ * Q is pushed on S; a neighbour w seen for the first time gets d[w] = d[v]+1
+ * and is queued; when d[w] = d[v]+1, v is a predecessor of w and sigma[w]
+ * grows by the number of shortest paths through v.  With identical-vertex
+ * weights that number is sigma[v]*ident[v] for v != s (Section 3.3.3).
+ *
+ * Phase 2 pops S (non-increasing distance) and pushes dependencies to the
+ * predecessors, Eq. (3):
+ *   delta[v] += sigma[v]/sigma[w] * (1 + delta[w])               (Alg. 1)
+ *   delta[v] += sigma[v]/sigma[w] * ident[w] * (1 + delta[w])     (Sec. 3.3.3)
+ * starting from delta[v] = reach[v]-1 (Alg. 2, initialisation line) or 0.
+ * A popped w != s adds delta[w] to bc[w], scaled by reach[s] (Alg. 2,
+ * accumulation line) and ident[s] (Sec. 3.3.3).
+ *
+ * The arrays d/sigma/delta are left holding this source's values.
+ */
+static void one_source(const oracle_job *J, oracle_ws *w, int32_t s, double *bc) {
+    const int32_t n = J->n;
+    const int32_t *rp = J->row_ptr, *col = J->col;
+    for (int32_t v = 0; v < n; ++v) {
+        w->Pcnt[v] = 0;
+        w->sigma[v] = 0.0;
+        w->d[v] = -1;
+    }
+    int32_t qh = 0, qt = 0, sp = 0;
+    w->Q[qt++] = s;
+    w->sigma[s] = 1.0;
+    w->d[s] = 0;
+    /* Phase 1: BFS from s. */
+    while (qh < qt) {
+        int32_t v = w->Q[qh++];
+        w->S[sp++] = v;
+        double paths_via_v = w->sigma[v];
+        if (J->weighted && J->ident && v != s) paths_via_v *= (double)J->ident[v];
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            int32_t x = col[e];
+            if (w->d[x] < 0) {
+                w->Q[qt++] = x;
+                w->d[x] = w->d[v] + 1;
+            }
+            if (w->d[x] == w->d[v] + 1) {
+                w->sigma[x] += paths_via_v;
+                w->Pbuf[rp[x] + w->Pcnt[x]++] = v;
+            }
+        }
+    }
+    /* Phase 2: back propagation. */
+    for (int32_t v = 0; v < n; ++v)
+        w->delta[v] = (J->weighted && J->reach) ? (double)(J->reach[v] - 1) : 0.0;
+    double src_weight = 1.0;
+    if (J->weighted) {
+        if (J->reach) src_weight *= (double)J->reach[s];
+        if (J->ident) src_weight *= (double)J->ident[s];
+    }
+    while (sp > 0) {
+        int32_t x = w->S[--sp];
+        double kx = (J->weighted && J->ident) ? (double)J->ident[x] : 1.0;
+        for (int32_t i = 0; i < w->Pcnt[x]; ++i) {
+            int32_t v = w->Pbuf[rp[x] + i];
+            w->delta[v] += w->sigma[v] / w->sigma[x] * kx * (1.0 + w->delta[x]);
+        }
+        if (x != s && bc) bc[x] += src_weight * w->delta[x];
+    }
+}
+
+static void *worker(void *arg) {
+    oracle_job *J = (oracle_job *)arg;
+    oracle_ws w;
+    if (!ws_alloc(&w, J->n, J->n > 0 ? J->row_ptr[J->n] : 0)) {
+        ws_free(&w);
+        J->status = -7;
+        return NULL;
+    }
+    for (int64_t i = J->src_begin; i < J->src_end; ++i) {
+        int32_t s = J->sources ? J->sources[i] : (int32_t)i;
+        one_source(J, &w, s, J->bc);
+    }
+    ws_free(&w);
+    J->status = 0;
+    return NULL;
+}
+
+static int run_threads(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
+                       const int32_t *ident, int weighted, int64_t nsrc, const int32_t *sources,
+                       int nthreads, double *bc_out) {
+    if (n < 0 || !row_ptr || (n > 0 && !col) || !bc_out) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nsrc < nthreads) nthreads = nsrc > 0 ? (int)nsrc : 1;
+    for (int32_t v = 0; v < n; ++v) bc_out[v] = 0.0;
+    if (nsrc == 0 || n == 0) return 0;
+    oracle_job *jobs = calloc((size_t)nthreads, sizeof(oracle_job));
+    pthread_t *tid = calloc((size_t)nthreads, sizeof(pthread_t));
+    double *acc = calloc((size_t)nthreads * (size_t)n, sizeof(double));
+    if (!jobs || !tid || !acc) {
+        free(jobs); free(tid); free(acc);
+        return -7;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        oracle_job *J = &jobs[t];
+        J->n = n; J->row_ptr = row_ptr; J->col = col;
+        J->reach = reach; J->ident = ident; J->sources = sources;
+        J->weighted = weighted;
+        J->src_begin = nsrc * t / nthreads;
+        J->src_end = nsrc * (t + 1) / nthreads;
+        J->bc = acc + (size_t)t * (size_t)n;
+        J->status = -1;
+    }
+    for (int t = 1; t < nthreads; ++t)
+        if (pthread_create(&tid[t], NULL, worker, &jobs[t]) != 0) jobs[t].status = -99;
+    worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t)
+        if (jobs[t].status != -99) pthread_join(tid[t], NULL);
+    int rc = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (jobs[t].status == -99) worker(&jobs[t]); /* thread creation failed: run inline */
+        if (jobs[t].status != 0) rc = jobs[t].status;
+    }
+    for (int t = 0; t < nthreads; ++t)
+        for (int32_t v = 0; v < n; ++v) bc_out[v] += acc[(size_t)t * (size_t)n + v];
+    free(jobs); free(tid); free(acc);
+    return rc;
+}
+
+/* Algorithm 1 over all sources (sources == NULL) or the listed ones. */
+int oracle_bc_plain(int32_t n, const int32_t *row_ptr, const int32_t *col, int64_t nsrc,
+                    const int32_t *sources, int nthreads, double *bc_out) {
+    if (!sources) nsrc = n;
+    return run_threads(n, row_ptr, col, NULL, NULL, 0, nsrc, sources, nthreads, bc_out);
+}
+
+/* Algorithm 2 with identical-vertex weights; reach/ident may be NULL (= 1). */
+int oracle_bc_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
+                       const int32_t *ident, int64_t nsrc, const int32_t *sources, int nthreads,
+                       double *bc_out) {
+    if (!sources) nsrc = n;
+    return run_threads(n, row_ptr, col, reach, ident, 1, nsrc, sources, nthreads, bc_out);
+}
+
+/* Levels (d, -1 when unreachable), path counts and dependencies of source s. */
+int oracle_single_source(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
+                         const int32_t *ident, int32_t s, int32_t *dist, double *sigma, double *delta) {
+    if (n <= 0 || s < 0 || s >= n || !row_ptr || !col) return -1;
+    oracle_job J;
+    memset(&J, 0, sizeof J);
+    J.n = n; J.row_ptr = row_ptr; J.col = col; J.reach = reach; J.ident = ident; J.weighted = 1;
+    oracle_ws w;
+    if (!ws_alloc(&w, n, row_ptr[n])) {
+        ws_free(&w);
+        return -7;
+    }
+    one_source(&J, &w, s, NULL);
+    for (int32_t v = 0; v < n; ++v) {
+        if (dist) dist[v] = w.d[v];
+        if (sigma) sigma[v] = w.sigma[v];
+        if (delta) delta[v] = w.delta[v];
+    }
+    ws_free(&w);
+    return 0;
+}

@@ -1,0 +1,129 @@
+"""Test-side helpers: graph expansions and closed forms (no library code)."""
+from __future__ import annotations
+
+import numpy as np
+
+import graphgen as gg
+
+
+def expand_attributed(n, row_ptr, col, reach, ident, twin_type):
+    """Build the ordinary graph an attributed piece stands for.
+
+    Vertex v of the piece becomes ident[v] copies; copies of adjacent vertices
+    are all adjacent; copies of v are pairwise adjacent when twin_type[v] == 2
+    (closed-neighbourhood twins) and pairwise non-adjacent when it is 1
+    (open-neighbourhood twins).  Each copy then gets reach[v]-1 pendant leaves,
+    the vertices it represents that hang off it through it alone.
+
+    Returns (Graph, first_copy) with first_copy[v] = id of v's first copy.
+    """
+    reach = np.asarray(reach, dtype=np.int64)
+    ident = np.asarray(ident, dtype=np.int64)
+    copy_off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(ident, out=copy_off[1:])
+    nc = int(copy_off[-1])
+    us, vs = [], []
+    rp = np.asarray(row_ptr)
+    for v in range(n):
+        cv = range(copy_off[v], copy_off[v + 1])
+        for e in range(rp[v], rp[v + 1]):
+            u = int(col[e])
+            if u < v:
+                continue
+            for a in cv:
+                for b in range(copy_off[u], copy_off[u + 1]):
+                    us.append(a)
+                    vs.append(b)
+        if twin_type[v] == 2:
+            cl = list(cv)
+            for i in range(len(cl)):
+                for j in range(i + 1, len(cl)):
+                    us.append(cl[i])
+                    vs.append(cl[j])
+    nxt = nc
+    for v in range(n):
+        for a in range(copy_off[v], copy_off[v + 1]):
+            for _ in range(int(reach[v]) - 1):
+                us.append(a)
+                vs.append(nxt)
+                nxt += 1
+    g = gg.csr_from_edges(nxt, np.array(us, dtype=np.int64), np.array(vs, dtype=np.int64), "expanded")
+    return g, copy_off[:-1]
+
+
+def twin_corrections(n, row_ptr, col, reach, ident, twin_type):
+    """Per-member score the merged traversal cannot see (derived from Sec. 3.3.3).
+
+    (i)  every member of a class of k >= 2 members with reach r gets
+         (k-1)*r*(r-1): pairs from a class-mate's group to targets hanging
+         below this member;
+    (ii) an open-neighbourhood class spreads its k(k-1)*r^2 member-to-member
+         paths evenly over the D = sum of ident over its neighbours, so each
+         member of a neighbour class gets k(k-1)r^2/D.
+    """
+    rp = np.asarray(row_ptr)
+    corr = np.zeros(n, dtype=np.float64)
+    for v in range(n):
+        k, r = int(ident[v]), int(reach[v])
+        if k < 2:
+            continue
+        corr[v] += (k - 1) * r * (r - 1)
+        if twin_type[v] == 1:
+            nb = col[rp[v]:rp[v + 1]]
+            D = int(np.sum(np.asarray(ident)[nb]))
+            if D > 0:
+                for x in nb:
+                    corr[int(x)] += k * (k - 1) * r * r / D
+    return corr
+
+
+def tree_closed_form(g: gg.Graph) -> np.ndarray:
+    """Ordered-pair BC of a tree: (n-1)^2 - sum of squared branch sizes at v."""
+    n = g.n
+    rp, col = g.row_ptr, g.col
+    parent = np.full(n, -1)
+    order = []
+    seen = np.zeros(n, dtype=bool)
+    out = np.zeros(n)
+    for root in range(n):
+        if seen[root]:
+            continue
+        comp = []
+        stack = [root]
+        seen[root] = True
+        while stack:
+            v = stack.pop()
+            comp.append(v)
+            for w in col[rp[v]:rp[v + 1]]:
+                if not seen[w]:
+                    seen[w] = True
+                    parent[w] = v
+                    stack.append(w)
+        size = {v: 1 for v in comp}
+        for v in reversed(comp):
+            if parent[v] >= 0:
+                size[parent[v]] += size[v]
+        N = len(comp)
+        for v in comp:
+            br = [size[w] for w in col[rp[v]:rp[v + 1]] if parent[w] == v]
+            if parent[v] >= 0:
+                br.append(N - size[v])
+            out[v] = (N - 1) ** 2 - sum(b * b for b in br)
+        order += comp
+    return out
+
+
+def assert_bc_close(got, want, rtol=1e-9, what=""):
+    """Per-vertex |g - o| <= rtol*|o|, and g == 0 exactly where o == 0."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    zero = want == 0
+    bad_zero = np.flatnonzero(zero & (got != 0))
+    assert bad_zero.size == 0, f"{what}: nonzero where exact value is 0 at {bad_zero[:10]} -> {got[bad_zero[:10]]}"
+    err = np.abs(got - want)
+    tol = rtol * np.abs(want)
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, (f"{what}: {bad.size} vertices off; worst rel "
+                           f"{np.max(err[~zero] / np.abs(want[~zero])) if (~zero).any() else 0:.3e} at "
+                           f"{bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}")
