@@ -1,0 +1,261 @@
+/*
+ * shatterbc -- exact betweenness centrality on AMD Instinct MI355X (gfx950)
+ * with the shattering and compression method of Sariyuce, Saule, Kaya and
+ * Catalyurek, "Shattering and Compressing Networks for Centrality Analysis".
+ *
+ * Problem (Section 2): an undirected, unweighted, loop-free graph G=(V,E) in
+ * compressed row storage with 32-bit indices (Section 4).  Output: for every
+ * vertex v, bc[v] = sum over ordered pairs s != v != t of sigma_st(v)/sigma_st
+ * (Eq. (1), Section 2.1), unnormalised.  SBC_UNORDERED halves it (unordered
+ * pairs); the halving is exact in binary64.
+ *
+ * Conventions for every call:
+ *   - Return value: SBC_OK (0) or a negative sbc_status.  Nothing throws across
+ *     this interface.  sbc_last_error() gives a message for the calling thread.
+ *   - Host buffers are owned by the caller; the library copies what it needs
+ *     before returning and keeps no caller pointer.
+ *   - Device memory the library allocates is owned by the object that
+ *     allocated it and freed by the matching *_destroy call.
+ *   - "host" / "device" on a pointer says where it must point.
+ *   - The compute path runs only on the GPU; without a usable gfx950 device
+ *     every compute call returns SBC_E_NO_DEVICE (there is no CPU fallback).
+ *     Graph creation and preprocessing are host-only and work without a GPU.
+ */
+#ifndef SHATTERBC_H
+#define SHATTERBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sbc_status;
+#define SBC_OK 0
+#define SBC_E_INVALID_ARG (-1)     /* NULL pointer, bad size, bad mode or option */
+#define SBC_E_NOT_SYMMETRIC (-2)   /* an arc u->v without v->u */
+#define SBC_E_SELF_LOOP (-3)       /* arc v->v (the paper assumes loop-free graphs, Section 2) */
+#define SBC_E_DUP_EDGE (-4)        /* the same arc twice in one row */
+#define SBC_E_INDEX_RANGE (-5)     /* a column index outside [0, n) */
+#define SBC_E_TOO_LARGE (-6)       /* 2^31 or more arcs / packed vertices */
+#define SBC_E_OOM (-7)             /* host or device allocation failed, or over the memory budget */
+#define SBC_E_DEVICE (-8)          /* a HIP runtime call failed */
+#define SBC_E_SIGMA_OVERFLOW (-9)  /* a path count exceeded the binary64 range */
+#define SBC_E_CANCELLED (-10)
+#define SBC_E_NOT_READY (-11)      /* job not finished yet (sbc_job_poll) */
+#define SBC_E_NO_DEVICE (-12)      /* no usable gfx950 GPU */
+
+/* sbc_graph_create flags */
+#define SBC_SANITIZE 1u /* symmetrise, drop self loops and duplicate arcs instead of failing */
+
+/* run modes (bit flags) */
+#define SBC_PLAIN 0u         /* Algorithm 1 on the whole graph, no preprocessing */
+#define SBC_COMPRESSED 1u    /* preprocess (default "dai" unless the graph was preprocessed) */
+#define SBC_UNORDERED 2u     /* report unordered-pair scores (Eq. (1) halved) */
+
+typedef struct sbc_context_s* sbc_context;
+typedef struct sbc_graph_s* sbc_graph;
+typedef struct sbc_plan_s* sbc_plan;
+typedef struct sbc_server_s* sbc_server;
+typedef struct sbc_job_s* sbc_job;
+
+/* Preprocessing statistics (Section 3; Section 4.2 names the letters). */
+typedef struct {
+  int64_t n, m;             /* input vertices and undirected edges */
+  int64_t components;       /* connected components of the input */
+  int64_t stripped;         /* degree-1 vertices removed (Section 3.3.1) */
+  int64_t blocks;           /* biconnected components (Sections 3.2.1, 3.4) */
+  int64_t bridges;          /* two-vertex blocks, done in closed form (Section 3.2.2) */
+  int64_t twin_classes;     /* identical-vertex classes with >= 2 members (Section 3.3.3) */
+  int64_t twins_merged;     /* vertices removed by merging */
+  int64_t tiny_pieces;      /* pieces of <= 2 vertices after merging, closed form */
+  int64_t pieces;           /* pieces left for the GPU */
+  int64_t piece_vertices;   /* sum of piece vertex counts */
+  int64_t piece_arcs;       /* sum of piece arc counts (2 x edges) */
+  double work_teps;         /* sum over pieces of vertices x edges */
+  double ms_degree1, ms_shatter, ms_twins, ms_pack; /* host wall time per stage */
+} sbc_prep_stats;
+
+/* Statistics of one execution. */
+typedef struct {
+  double ms_device;          /* device time from first to last kernel of the run (HIP events) */
+  double ms_traverse;        /* device time of the traversal kernels (forward + backward sweeps) */
+  double ms_mapback;         /* device time of the Eq. (5) gather */
+  double ms_host;            /* host wall time of the call */
+  double teps;               /* sources x edges traversed, summed over pieces */
+  double algo_bytes;         /* streaming-model bytes: per (source, piece) 8*arcs + 56*vertices */
+  int64_t items;             /* work items drained from the device queue */
+  int64_t batched_sources;   /* sources run by the 64-lane multi-source kernel */
+  int64_t lds_sources;       /* sources run by the LDS-resident kernel */
+  int64_t global_sources;    /* sources run by the one-source-per-workgroup global kernel */
+  int32_t overflow;          /* nonzero if a path count overflowed */
+  /* Per traversal kernel class: 0 one source per wavefront (LDS), 1 one source
+   * per workgroup (LDS), 2 64-source batches, 3 one source per workgroup
+   * (global memory).  Device time of the class's persistent launch, its
+   * streaming-model bytes, and its sources x edges. */
+  double ms_class[4];
+  double bytes_class[4];
+  double teps_class[4];
+  int32_t grid_class[4];      /* resident workgroups of the launch */
+  int32_t items_class[4];     /* work items of the launch */
+} sbc_run_stats;
+
+const char* sbc_status_string(sbc_status s);
+/* Message of the calling thread's last failing call ("" if none). */
+const char* sbc_last_error(void);
+/* Library version string. */
+const char* sbc_version(void);
+
+/* ---------------------------------------------------------------- context */
+
+/* Bind to GPU `device` (HIP ordinal).  Checks that it is gfx950.
+ * Errors: SBC_E_NO_DEVICE, SBC_E_DEVICE, SBC_E_INVALID_ARG (out NULL). */
+sbc_status sbc_context_create(int device, sbc_context* out);
+sbc_status sbc_context_destroy(sbc_context ctx);
+
+/* Tuning knobs, by name.  Known keys:
+ *   "lds_max_vertices"   largest piece run by the LDS-resident kernel
+ *   "wave_max_vertices"  largest piece run one-source-per-wavefront in LDS
+ *   "batch_min_vertices" smallest piece run by the 64-lane multi-source kernel
+ *   "batch_wg_waves"     wavefronts per workgroup of the multi-source kernel
+ *   "slots"              resident workgroups per traversal kernel (0 = auto)
+ *   "cluster_sources"    1: order batch sources by breadth-first balls
+ *   "plain_kernel"       plain mode: 0 automatic, 1 one source per workgroup
+ *   "mem_budget_mb"      traversal-state budget of a plan (0: 60% of free memory)
+ *   "lds_block", "lds_sources_per_item", "wave_sources_per_item"
+ * Read-only (get only): "cus" compute units, "lds_limit_bytes" LDS per workgroup.
+ * Errors: SBC_E_INVALID_ARG for an unknown key or out-of-range value. */
+sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value);
+sbc_status sbc_context_get_param(sbc_context ctx, const char* key, int64_t* value);
+/* Name of the bound device (e.g. "AMD Instinct MI355X"), NUL-terminated, at most len bytes. */
+sbc_status sbc_context_device_name(sbc_context ctx, char* buf, size_t len);
+
+/* ------------------------------------------------------------------ graph */
+
+/* Copy a CSR graph: row_ptr[n+1] and col[row_ptr[n]] (host), each undirected
+ * edge present as both arcs, no self loops, no duplicates (unless
+ * SBC_SANITIZE).  Host-only; needs no GPU.
+ * Errors: SBC_E_INVALID_ARG, SBC_E_INDEX_RANGE, SBC_E_SELF_LOOP,
+ * SBC_E_DUP_EDGE, SBC_E_NOT_SYMMETRIC, SBC_E_TOO_LARGE, SBC_E_OOM. */
+sbc_status sbc_graph_create(int32_t n, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
+                            sbc_graph* out);
+sbc_status sbc_graph_destroy(sbc_graph g);
+/* n and the number of arcs (2 x edges) of the stored graph. */
+sbc_status sbc_graph_info(sbc_graph g, int32_t* n, int64_t* arcs);
+
+/* Shatter and compress (Section 3), host-only.  ops holds letters applied in
+ * this order: 'd' degree-1 vertices (Section 3.3.1), 'a' articulation
+ * vertices via biconnected components, bridges included ('b' is accepted as
+ * the same step; Sections 3.2.1, 3.2.2, 3.4), 'i' identical vertices
+ * (Section 3.3.3).  "" keeps every connected component whole.  st may be NULL.
+ * Errors: SBC_E_INVALID_ARG for an unknown letter, SBC_E_TOO_LARGE. */
+sbc_status sbc_graph_preprocess(sbc_graph g, const char* ops, sbc_prep_stats* st);
+
+/* Sizes of the preprocessed problem: pieces P, piece vertices V, piece arcs A,
+ * map entries M (original vertex -> piece vertex links). */
+sbc_status sbc_graph_export_sizes(sbc_graph g, int64_t* P, int64_t* V, int64_t* A, int64_t* M);
+/* Copy the preprocessed problem out (host buffers sized by export_sizes; any
+ * may be NULL to skip it):
+ *   vtx_off[P+1]   piece p owns piece vertices [vtx_off[p], vtx_off[p+1])
+ *   row[V+1]       absolute arc offsets; col[A] local (piece-relative) ids
+ *   reach[V], ident[V]   Section 3.2 / 3.3.3 attributes
+ *   corr[V]        per-member terms added to each piece vertex's bc'
+ *   bcx[n]         per-original-vertex terms closed in form on the host
+ *   map_off[n+1], map_idx[M]   original v -> piece vertices (Eq. (5))
+ * bc[v] = bcx[v] + sum over j in map of (bc'[map_idx[j]] + corr[map_idx[j]]). */
+sbc_status sbc_graph_export(sbc_graph g, int32_t* vtx_off, int32_t* row, int32_t* col, int32_t* reach,
+                            int32_t* ident, double* corr, double* bcx, int32_t* map_off, int32_t* map_idx);
+
+/* ------------------------------------------------------------------- plan */
+
+/* Upload the problem of `mode` (SBC_PLAIN or SBC_COMPRESSED; SBC_COMPRESSED on
+ * a graph not yet preprocessed runs "dai" first) to the device, build the
+ * work queue and allocate traversal state.  The plan keeps everything
+ * resident, so repeated executions touch no host memory.
+ * Errors: SBC_E_NO_DEVICE, SBC_E_OOM, SBC_E_DEVICE, SBC_E_INVALID_ARG. */
+sbc_status sbc_plan_create(sbc_context ctx, sbc_graph g, uint32_t mode, sbc_plan* out);
+sbc_status sbc_plan_destroy(sbc_plan p);
+/* Run the whole path (every source of every piece, forward and backward
+ * sweeps, accumulation, Eq. (5) gather) on `stream` (a hipStream_t, NULL =
+ * the plan's own stream) and write bc (n doubles, device memory, or NULL to
+ * keep it inside the plan).  Asynchronous: returns after enqueueing; the
+ * output is valid once the stream reaches this point.
+ * Errors: SBC_E_DEVICE. */
+sbc_status sbc_plan_execute(sbc_plan p, double* bc_dev, void* stream);
+/* Wait for the last execution and return its statistics (and
+ * SBC_E_SIGMA_OVERFLOW if a path count overflowed). */
+sbc_status sbc_plan_sync(sbc_plan p, sbc_run_stats* st);
+/* Copy the plan's own result (n doubles) to host memory (waits). */
+sbc_status sbc_plan_result(sbc_plan p, double* bc_host);
+/* Capture one execution into a HIP graph and replay it on later executes
+ * (enable = 1) or go back to direct launches (enable = 0). */
+sbc_status sbc_plan_use_graph(sbc_plan p, int enable);
+
+/* --------------------------------------------------------- one-shot calls */
+
+/* Plan, execute, copy back and destroy: bc_host[n] (host).  st may be NULL. */
+sbc_status sbc_betweenness(sbc_context ctx, sbc_graph g, uint32_t mode, double* bc_host, sbc_run_stats* st);
+/* Same with the result left in device memory bc_dev[n] on `stream`;
+ * synchronises the stream before returning. */
+sbc_status sbc_betweenness_device(sbc_context ctx, sbc_graph g, uint32_t mode, double* bc_dev, void* stream,
+                                  sbc_run_stats* st);
+/* Algorithm 1 restricted to the listed sources (plain graph, ordered pairs):
+ * bc_host[v] = sum over s in sources of delta_s(v).  Sources must be distinct.
+ * Errors: SBC_E_INVALID_ARG, SBC_E_INDEX_RANGE. */
+sbc_status sbc_betweenness_sources(sbc_context ctx, sbc_graph g, int64_t nsrc, const int32_t* sources,
+                                   double* bc_host, sbc_run_stats* st);
+
+/* Algorithm 2 with identical-vertex weights (Sections 3.2.1, 3.3.3) on one
+ * attributed piece given in host CSR form (local ids, symmetric, loop-free):
+ * bc_host[v] = sum over sources s of ident[s]*reach[s]*delta_s(v), v != s,
+ * where sigma counts paths through v != s with weight ident[v] and delta
+ * starts at reach[v]-1.  reach/ident may be NULL (all ones).  `kernel` forces
+ * one traversal kernel: 0 automatic, 1 one-source-per-workgroup in global
+ * memory, 2 LDS-resident, 3 64-lane multi-source.
+ * Errors: SBC_E_INVALID_ARG (shape, or a piece too large for the forced kernel). */
+sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                        const int32_t* reach, const int32_t* ident, int kernel, double* bc_host,
+                        sbc_run_stats* st);
+
+/* One source of the same traversal, for verification: dist[n] (int32, -1
+ * unreachable), sigma[n], delta[n] (host).  Any output may be NULL. */
+sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist,
+                             double* sigma, double* delta);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A continuously batching request loop on one GPU.  Jobs are admitted while
+ * their device footprint fits in hbm_budget_bytes (0 = 80% of free memory)
+ * and a slot is free; admitted jobs run concurrently on `slots` streams, so a
+ * job that arrives while others run starts as soon as a slot and memory free
+ * up.  Graph data and scores stay resident until the job is released.
+ * Errors: SBC_E_INVALID_ARG, SBC_E_DEVICE. */
+sbc_status sbc_server_create(sbc_context ctx, int slots, size_t hbm_budget_bytes, sbc_server* out);
+/* Drains every submitted job, then stops the loop and frees the server. */
+sbc_status sbc_server_destroy(sbc_server s);
+
+typedef struct {
+  double submit_to_start_ms;  /* waiting for admission */
+  double start_to_done_ms;    /* preprocessing + device work + copy back */
+  double latency_ms;          /* submit to result on the host */
+  double teps;                /* sources x edges of the job */
+  int64_t footprint_bytes;    /* device bytes the job held */
+} sbc_job_stats;
+
+/* Queue a betweenness job on graph g (which must outlive the job and must
+ * not be used by another call until the job is released).  Thread-safe. */
+sbc_status sbc_server_submit(sbc_server s, sbc_graph g, uint32_t mode, sbc_job* out);
+/* *done = 1 when the job has finished (successfully or not). */
+sbc_status sbc_job_poll(sbc_job j, int* done);
+/* Block until the job finishes; copy bc (n doubles, host) and its stats
+ * (either may be NULL).  Returns the job's own status. */
+sbc_status sbc_job_wait(sbc_job j, double* bc_host, sbc_job_stats* st);
+sbc_status sbc_job_release(sbc_job j);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHATTERBC_H */

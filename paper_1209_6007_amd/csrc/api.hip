@@ -1,0 +1,425 @@
+// The C interface declared in include/shatterbc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "runtime.hpp"
+#include "shatterbc.h"
+
+namespace sbc {
+const std::string& last_error();
+}
+
+using namespace sbc;
+
+#define SBC_TRY(body)                                        \
+  try {                                                      \
+    body                                                     \
+  } catch (const std::bad_alloc&) {                          \
+    return fail(SBC_E_OOM, "host allocation failed");        \
+  } catch (const std::exception& ex) {                       \
+    return fail(SBC_E_INVALID_ARG, ex.what());               \
+  } catch (...) {                                            \
+    return fail(SBC_E_INVALID_ARG, "unexpected exception");  \
+  }
+
+extern "C" {
+
+const char* sbc_status_string(sbc_status s) {
+  switch (s) {
+    case SBC_OK: return "ok";
+    case SBC_E_INVALID_ARG: return "invalid argument";
+    case SBC_E_NOT_SYMMETRIC: return "graph is not symmetric";
+    case SBC_E_SELF_LOOP: return "graph has a self loop";
+    case SBC_E_DUP_EDGE: return "graph has a duplicate arc";
+    case SBC_E_INDEX_RANGE: return "index out of range";
+    case SBC_E_TOO_LARGE: return "problem too large";
+    case SBC_E_OOM: return "out of memory";
+    case SBC_E_DEVICE: return "device error";
+    case SBC_E_SIGMA_OVERFLOW: return "shortest-path count overflow";
+    case SBC_E_CANCELLED: return "cancelled";
+    case SBC_E_NOT_READY: return "not ready";
+    case SBC_E_NO_DEVICE: return "no usable gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+const char* sbc_last_error(void) { return sbc::last_error().c_str(); }
+
+const char* sbc_version(void) { return "shatterbc 0.1 (gfx950)"; }
+
+sbc_status sbc_context_create(int device, sbc_context* out) {
+  if (!out) return fail(SBC_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return fail(SBC_E_NO_DEVICE, "no HIP device visible");
+  }
+  if (device < 0 || device >= count) return fail(SBC_E_NO_DEVICE, "device ordinal out of range");
+  SBC_TRY({
+    std::unique_ptr<sbc_context_s> c(new sbc_context_s());
+    c->device = device;
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((e = hipGetDeviceProperties(&c->prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(c->prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(SBC_E_NO_DEVICE, std::string("device is ") + c->prop.gcnArchName + ", this library is built for gfx950");
+    c->cus = c->prop.multiProcessorCount;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+      c->lds_limit = std::min<size_t>((size_t)lds, kMaxLdsBytes);
+    (void)hipGetLastError();  // leave no stale error behind for later launch checks
+    *out = c.release();
+    return SBC_OK;
+  })
+}
+
+sbc_status sbc_context_destroy(sbc_context ctx) {
+  delete ctx;
+  return SBC_OK;
+}
+
+static int64_t* param_slot(Params& p, const char* key) {
+  const std::string k(key);
+  if (k == "wave_max_vertices") return &p.wave_max_vertices;
+  if (k == "lds_max_vertices") return &p.lds_max_vertices;
+  if (k == "batch_min_vertices") return &p.batch_min_vertices;
+  if (k == "batch_wg_waves") return &p.batch_wg_waves;
+  if (k == "lds_block") return &p.lds_block;
+  if (k == "lds_sources_per_item") return &p.lds_sources_per_item;
+  if (k == "wave_sources_per_item") return &p.wave_sources_per_item;
+  if (k == "slots") return &p.slots;
+  if (k == "cluster_sources") return &p.cluster_sources;
+  if (k == "plain_kernel") return &p.plain_kernel;
+  if (k == "mem_budget_mb") return &p.mem_budget_mb;
+  return nullptr;
+}
+
+sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value) {
+  if (!ctx || !key) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  int64_t* slot = param_slot(ctx->params, key);
+  if (!slot) return fail(SBC_E_INVALID_ARG, std::string("unknown parameter ") + key);
+  const std::string k(key);
+  bool ok = value >= 0;
+  if (k == "batch_wg_waves") ok = value == 4 || value == 8 || value == 16;
+  if (k == "lds_block") ok = value == 64 || value == 256 || value == 512 || value == 1024;
+  if (k == "lds_max_vertices") ok = value >= 1 && wg_lds_bytes((int32_t)value) <= ctx->lds_limit;
+  if (k == "wave_max_vertices") ok = value >= 1 && value <= 1024;
+  if (k == "lds_sources_per_item" || k == "wave_sources_per_item") ok = value >= 1 && value <= (1 << 20);
+  if (k == "batch_min_vertices") ok = value >= 2;
+  if (!ok) return fail(SBC_E_INVALID_ARG, std::string("value out of range for ") + key);
+  *slot = value;
+  return SBC_OK;
+}
+
+sbc_status sbc_context_get_param(sbc_context ctx, const char* key, int64_t* value) {
+  if (!ctx || !key || !value) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (std::string(key) == "cus") {
+    *value = ctx->cus;
+    return SBC_OK;
+  }
+  if (std::string(key) == "lds_limit_bytes") {
+    *value = (int64_t)ctx->lds_limit;
+    return SBC_OK;
+  }
+  int64_t* slot = param_slot(ctx->params, key);
+  if (!slot) return fail(SBC_E_INVALID_ARG, std::string("unknown parameter ") + key);
+  *value = *slot;
+  return SBC_OK;
+}
+
+sbc_status sbc_context_device_name(sbc_context ctx, char* buf, size_t len) {
+  if (!ctx || !buf || len == 0) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  std::strncpy(buf, ctx->prop.name, len - 1);
+  buf[len - 1] = 0;
+  return SBC_OK;
+}
+
+sbc_status sbc_graph_create(int32_t n, const int32_t* row_ptr, const int32_t* col, uint32_t flags, sbc_graph* out) {
+  if (!out) return fail(SBC_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (flags & ~SBC_SANITIZE) return fail(SBC_E_INVALID_ARG, "unknown flag");
+  SBC_TRY({
+    std::unique_ptr<sbc_graph_s> g(new sbc_graph_s());
+    std::string why;
+    int rc = validate_csr(n, row_ptr, col, (flags & SBC_SANITIZE) != 0, &g->g, &why);
+    if (rc != SBC_OK) return fail(rc, why);
+    *out = g.release();
+    return SBC_OK;
+  })
+}
+
+sbc_status sbc_graph_destroy(sbc_graph g) {
+  delete g;
+  return SBC_OK;
+}
+
+sbc_status sbc_graph_info(sbc_graph g, int32_t* n, int64_t* arcs) {
+  if (!g) return fail(SBC_E_INVALID_ARG, "graph is NULL");
+  if (n) *n = g->g.n;
+  if (arcs) *arcs = g->g.arcs();
+  return SBC_OK;
+}
+
+sbc_status sbc_graph_preprocess(sbc_graph g, const char* ops, sbc_prep_stats* st) {
+  if (!g || !ops) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  SBC_TRY({
+    PrepStats ps;
+    std::string why;
+    Prepared prep;
+    int rc = preprocess(g->g, ops, &prep, &ps, &why);
+    if (rc != SBC_OK) return fail(rc, why);
+    g->prep = std::move(prep);
+    g->prepared = true;
+    g->ops = ops;
+    sbc_prep_stats s{};
+    s.n = ps.n;
+    s.m = ps.m;
+    s.components = ps.components;
+    s.stripped = ps.stripped;
+    s.blocks = ps.blocks;
+    s.bridges = ps.bridges;
+    s.twin_classes = ps.twin_classes;
+    s.twins_merged = ps.twins_merged;
+    s.tiny_pieces = ps.tiny_pieces;
+    s.pieces = ps.pieces;
+    s.piece_vertices = ps.piece_vertices;
+    s.piece_arcs = ps.piece_arcs;
+    s.work_teps = ps.work_teps;
+    s.ms_degree1 = ps.ms_degree1;
+    s.ms_shatter = ps.ms_shatter;
+    s.ms_twins = ps.ms_twins;
+    s.ms_pack = ps.ms_pack;
+    g->stats = s;
+    if (st) *st = s;
+    return SBC_OK;
+  })
+}
+
+sbc_status sbc_graph_export_sizes(sbc_graph g, int64_t* P, int64_t* V, int64_t* A, int64_t* M) {
+  if (!g) return fail(SBC_E_INVALID_ARG, "graph is NULL");
+  if (!g->prepared) return fail(SBC_E_INVALID_ARG, "graph has not been preprocessed");
+  if (P) *P = g->prep.pieces();
+  if (V) *V = g->prep.V();
+  if (A) *A = g->prep.A();
+  if (M) *M = (int64_t)g->prep.map_idx.size();
+  return SBC_OK;
+}
+
+sbc_status sbc_graph_export(sbc_graph g, int32_t* vtx_off, int32_t* row, int32_t* col, int32_t* reach,
+                            int32_t* ident, double* corr, double* bcx, int32_t* map_off, int32_t* map_idx) {
+  if (!g) return fail(SBC_E_INVALID_ARG, "graph is NULL");
+  if (!g->prepared) return fail(SBC_E_INVALID_ARG, "graph has not been preprocessed");
+  const Prepared& p = g->prep;
+  auto cp = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  cp(vtx_off, p.vtx_off);
+  cp(row, p.row);
+  cp(col, p.col);
+  cp(reach, p.reach);
+  cp(ident, p.ident);
+  cp(corr, p.corr);
+  cp(bcx, p.bcx);
+  cp(map_off, p.map_off);
+  cp(map_idx, p.map_idx);
+  return SBC_OK;
+}
+
+static sbc_status ensure_problem(sbc_graph g, uint32_t mode, Prepared* plain_storage, const Prepared** out) {
+  if (mode & SBC_COMPRESSED) {
+    if (!g->prepared) {
+      sbc_status rc = sbc_graph_preprocess(g, "dai", nullptr);
+      if (rc != SBC_OK) return rc;
+    }
+    *out = &g->prep;
+  } else {
+    plain_problem(g->g, plain_storage);
+    *out = plain_storage;
+  }
+  return SBC_OK;
+}
+
+sbc_status sbc_plan_create(sbc_context ctx, sbc_graph g, uint32_t mode, sbc_plan* out) {
+  if (!ctx || !g || !out) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  if (mode & ~(SBC_COMPRESSED | SBC_UNORDERED)) return fail(SBC_E_INVALID_ARG, "unknown mode bit");
+  *out = nullptr;
+  SBC_TRY({
+    Prepared plain;
+    const Prepared* prob = nullptr;
+    sbc_status rc = ensure_problem(g, mode, &plain, &prob);
+    if (rc != SBC_OK) return rc;
+    std::unique_ptr<sbc_plan_s> p(new sbc_plan_s());
+    rc = p->plan.build(ctx, *prob, mode, PlanOptions());
+    if (rc != SBC_OK) return rc;
+    *out = p.release();
+    return SBC_OK;
+  })
+}
+
+sbc_status sbc_plan_destroy(sbc_plan p) {
+  if (p) {
+    (void)hipSetDevice(p->plan.ctx->device);
+    if (p->plan.ran) (void)hipEventSynchronize(p->plan.ev_end);
+  }
+  delete p;
+  return SBC_OK;
+}
+
+sbc_status sbc_plan_execute(sbc_plan p, double* bc_dev, void* stream) {
+  if (!p) return fail(SBC_E_INVALID_ARG, "plan is NULL");
+  SBC_TRY({ return p->plan.execute(bc_dev, (hipStream_t)stream); })
+}
+
+sbc_status sbc_plan_sync(sbc_plan p, sbc_run_stats* st) {
+  if (!p) return fail(SBC_E_INVALID_ARG, "plan is NULL");
+  SBC_TRY({ return p->plan.sync(st); })
+}
+
+sbc_status sbc_plan_result(sbc_plan p, double* bc_host) {
+  if (!p || !bc_host) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  sbc_status rc = p->plan.sync(nullptr);
+  if (rc != SBC_OK) return rc;
+  hipError_t e = hipMemcpy(bc_host, p->plan.d_out.p, sizeof(double) * p->plan.n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "copy result");
+  return SBC_OK;
+}
+
+sbc_status sbc_plan_use_graph(sbc_plan p, int enable) {
+  if (!p) return fail(SBC_E_INVALID_ARG, "plan is NULL");
+  if (p->plan.ran) (void)hipEventSynchronize(p->plan.ev_end);
+  p->plan.use_graph = enable != 0;
+  return SBC_OK;
+}
+
+sbc_status sbc_betweenness(sbc_context ctx, sbc_graph g, uint32_t mode, double* bc_host, sbc_run_stats* st) {
+  if (!ctx || !g || !bc_host) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  sbc_plan p = nullptr;
+  sbc_status rc = sbc_plan_create(ctx, g, mode, &p);
+  if (rc != SBC_OK) return rc;
+  rc = sbc_plan_execute(p, nullptr, nullptr);
+  if (rc == SBC_OK) rc = sbc_plan_sync(p, st);
+  if (rc == SBC_OK) rc = sbc_plan_result(p, bc_host);
+  sbc_plan_destroy(p);
+  return rc;
+}
+
+sbc_status sbc_betweenness_device(sbc_context ctx, sbc_graph g, uint32_t mode, double* bc_dev, void* stream,
+                                  sbc_run_stats* st) {
+  if (!ctx || !g || !bc_dev) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  sbc_plan p = nullptr;
+  sbc_status rc = sbc_plan_create(ctx, g, mode, &p);
+  if (rc != SBC_OK) return rc;
+  rc = sbc_plan_execute(p, bc_dev, stream);
+  if (rc == SBC_OK) rc = sbc_plan_sync(p, st);
+  sbc_plan_destroy(p);
+  return rc;
+}
+
+sbc_status sbc_betweenness_sources(sbc_context ctx, sbc_graph g, int64_t nsrc, const int32_t* sources,
+                                   double* bc_host, sbc_run_stats* st) {
+  if (!ctx || !g || !bc_host || (nsrc > 0 && !sources) || nsrc < 0)
+    return fail(SBC_E_INVALID_ARG, "NULL argument or negative count");
+  if (nsrc > g->g.n) return fail(SBC_E_INVALID_ARG, "more sources than vertices");
+  SBC_TRY({
+    if (nsrc == 0) {
+      std::memset(bc_host, 0, sizeof(double) * g->g.n);
+      return SBC_OK;
+    }
+    Prepared plain;
+    plain_problem(g->g, &plain);
+    PlanOptions opt;
+    opt.sources = sources;
+    opt.nsrc = nsrc;
+    Plan plan;
+    sbc_status rc = plan.build(ctx, plain, SBC_PLAIN, opt);
+    if (rc != SBC_OK) return rc;
+    if ((rc = plan.execute(nullptr, nullptr)) != SBC_OK) return rc;
+    if ((rc = plan.sync(st)) != SBC_OK) return rc;
+    hipError_t e = hipMemcpy(bc_host, plan.d_out.p, sizeof(double) * plan.n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy result");
+    return SBC_OK;
+  })
+}
+
+// One attributed piece as a single-piece problem.
+static sbc_status piece_problem(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* reach,
+                                const int32_t* ident, Prepared* out) {
+  HostGraph hg;
+  std::string why;
+  int rc = validate_csr(n, row_ptr, col, false, &hg, &why);
+  if (rc != SBC_OK) return fail(rc, why);
+  if (n < 1) return fail(SBC_E_INVALID_ARG, "empty piece");
+  plain_problem(hg, out);
+  for (int32_t v = 0; v < n; ++v) {
+    if (reach) {
+      if (reach[v] < 1) return fail(SBC_E_INVALID_ARG, "reach must be >= 1");
+      out->reach[v] = reach[v];
+      if (reach[v] > 1) out->weighted = true;
+    }
+    if (ident) {
+      if (ident[v] < 1) return fail(SBC_E_INVALID_ARG, "ident must be >= 1");
+      out->ident[v] = ident[v];
+      if (ident[v] > 1) out->has_ident = true;
+    }
+  }
+  return SBC_OK;
+}
+
+sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* reach,
+                        const int32_t* ident, int kernel, double* bc_host, sbc_run_stats* st) {
+  if (!ctx || !bc_host) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  if (kernel < 0 || kernel > 3) return fail(SBC_E_INVALID_ARG, "kernel must be 0..3");
+  SBC_TRY({
+    Prepared prob;
+    sbc_status rc = piece_problem(n, row_ptr, col, reach, ident, &prob);
+    if (rc != SBC_OK) return rc;
+    PlanOptions opt;
+    opt.force_kernel = kernel;
+    Plan plan;
+    // weighted single piece: compressed-mode kernels (REACH/IDENT picked from the data)
+    rc = plan.build(ctx, prob, SBC_COMPRESSED, opt);
+    if (rc != SBC_OK) return rc;
+    if ((rc = plan.execute(nullptr, nullptr)) != SBC_OK) return rc;
+    if ((rc = plan.sync(st)) != SBC_OK) return rc;
+    hipError_t e = hipMemcpy(bc_host, plan.d_bcp.p, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy result");
+    return SBC_OK;
+  })
+}
+
+sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist, double* sigma,
+                             double* delta) {
+  if (!ctx) return fail(SBC_E_INVALID_ARG, "NULL context");
+  if (s < 0 || s >= n) return fail(SBC_E_INDEX_RANGE, "source out of range");
+  SBC_TRY({
+    Prepared prob;
+    sbc_status rc = piece_problem(n, row_ptr, col, reach, ident, &prob);
+    if (rc != SBC_OK) return rc;
+    PlanOptions opt;
+    opt.force_kernel = 1;
+    opt.debug_single = true;
+    opt.debug_source = s;
+    Plan plan;
+    rc = plan.build(ctx, prob, SBC_COMPRESSED, opt);
+    if (rc != SBC_OK) return rc;
+    if ((rc = plan.execute(nullptr, nullptr)) != SBC_OK) return rc;
+    if ((rc = plan.sync(nullptr)) != SBC_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (dist && e == hipSuccess) e = hipMemcpy(dist, plan.dbg.dist, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (sigma && e == hipSuccess) e = hipMemcpy(sigma, plan.dbg.sigma, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (delta && e == hipSuccess) e = hipMemcpy(delta, plan.dbg.delta, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy result");
+    return SBC_OK;
+  })
+}
+
+}  // extern "C"

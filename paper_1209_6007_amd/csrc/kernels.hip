@@ -1,0 +1,163 @@
+// Host launchers of the traversal kernels (device code in kernels_dev.hpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+#ifndef SBC_DYNAMIC_LDS
+#define SBC_DYNAMIC_LDS(name) extern __shared__ __align__(16) unsigned char name[]
+#endif
+#include "kernels_dev.hpp"
+
+namespace sbc {
+
+namespace {
+
+using namespace dev;
+
+template <typename T>
+hipError_t fill(T* p, T v, int64_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+  (void)hipGetLastError();  // drop any stale error so the status below is this launch's own
+  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, stream, p, v, count);
+  return hipGetLastError();
+}
+
+template <int BLOCK, bool R, bool I, bool LDS>
+hipError_t launch_wg_t(const DevPieces& P, const QueueArgs& Q, int grid, int32_t max_np, const WgState& st,
+                       const DebugOut& dbg, hipStream_t stream) {
+  const size_t lds = LDS ? wg_lds_bytes(max_np) : 0;
+  if (LDS && lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)wg_kernel<BLOCK, R, I, LDS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((wg_kernel<BLOCK, R, I, LDS>), dim3(grid), dim3(BLOCK), lds, stream, P, Q, st, max_np, dbg);
+  return hipGetLastError();
+}
+
+template <int BLOCK, bool LDS>
+hipError_t launch_wg_b(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, int32_t max_np,
+                       const WgState& st, const DebugOut& dbg, hipStream_t stream) {
+  if (r && i) return launch_wg_t<BLOCK, true, true, LDS>(P, Q, grid, max_np, st, dbg, stream);
+  if (r) return launch_wg_t<BLOCK, true, false, LDS>(P, Q, grid, max_np, st, dbg, stream);
+  if (i) return launch_wg_t<BLOCK, false, true, LDS>(P, Q, grid, max_np, st, dbg, stream);
+  return launch_wg_t<BLOCK, false, false, LDS>(P, Q, grid, max_np, st, dbg, stream);
+}
+
+template <int WAVES>
+hipError_t launch_ms_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
+                       hipStream_t stream) {
+  (void)hipGetLastError();
+  if (r && i) hipLaunchKernelGGL((ms_kernel<WAVES, true, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  else if (r) hipLaunchKernelGGL((ms_kernel<WAVES, true, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  else if (i) hipLaunchKernelGGL((ms_kernel<WAVES, false, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  else hipLaunchKernelGGL((ms_kernel<WAVES, false, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  return hipGetLastError();
+}
+
+template <int BLOCK, bool LDS>
+int occ_wg_b(size_t dyn) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)wg_kernel<BLOCK, true, true, LDS>, BLOCK, dyn) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return nb > 0 ? nb : 1;
+}
+
+template <int WAVES>
+int occ_ms_w() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)ms_kernel<WAVES, true, true>, WAVES * 64, 0) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+size_t wg_lds_bytes(int32_t max_np) { return (size_t)max_np * 20 + 16; }
+
+int occupancy_wg(int block, bool lds, size_t dyn) {
+  switch (block) {
+    case 64: return lds ? occ_wg_b<64, true>(dyn) : occ_wg_b<64, false>(0);
+    case 256: return lds ? occ_wg_b<256, true>(dyn) : occ_wg_b<256, false>(0);
+    case 512: return lds ? occ_wg_b<512, true>(dyn) : occ_wg_b<512, false>(0);
+    case 1024: return lds ? occ_wg_b<1024, true>(dyn) : occ_wg_b<1024, false>(0);
+    default: return 1;
+  }
+}
+
+int occupancy_ms(int waves) {
+  switch (waves) {
+    case 4: return occ_ms_w<4>();
+    case 8: return occ_ms_w<8>();
+    case 16: return occ_ms_w<16>();
+    default: return 1;
+  }
+}
+
+hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, bool lds, int block, int grid,
+                     int32_t max_np, const WgState& st, const DebugOut* dbg, hipStream_t stream) {
+  DebugOut d{nullptr, nullptr, nullptr};
+  if (dbg) d = *dbg;
+  switch (block) {
+    case 64:
+      return lds ? launch_wg_b<64, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
+                 : launch_wg_b<64, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
+    case 256:
+      return lds ? launch_wg_b<256, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
+                 : launch_wg_b<256, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
+    case 512:
+      return lds ? launch_wg_b<512, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
+                 : launch_wg_b<512, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
+    case 1024:
+      return lds ? launch_wg_b<1024, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
+                 : launch_wg_b<1024, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
+                     const MsState& st, hipStream_t stream) {
+  switch (waves) {
+    case 4: return launch_ms_w<4>(P, Q, reach, ident, grid, st, stream);
+    case 8: return launch_ms_w<8>(P, Q, reach, ident, grid, st, stream);
+    case 16: return launch_ms_w<16>(P, Q, reach, ident, grid, st, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_mapback(int32_t n, const int32_t* map_off, const int32_t* map_idx, const double* bcp,
+                          const double* corr, const double* bcx, double scale, double* out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(mapback_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, map_off, map_idx, bcp, corr,
+                     bcx, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t stream) {
+  return fill<int32_t>(p, v, count, stream);
+}
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t stream) {
+  return fill<uint64_t>(p, v, count, stream);
+}
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t stream) {
+  return fill<double>(p, v, count, stream);
+}
+
+}  // namespace sbc

@@ -1,0 +1,34 @@
+// Device kernels of the traversal (Algorithm 2 with identical-vertex weights)
+// and their host-side launchers.  All launchers are asynchronous on `stream`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernel_types.hpp"
+
+namespace sbc {
+
+// Launchers.  `lds` selects LDS-resident state (max_np vertices per block)
+// or the global-memory state `st`.  `block` in {64, 256, 512, 1024}.
+hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, bool lds, int block,
+                     int grid, int32_t max_np, const WgState& st, const DebugOut* dbg, hipStream_t stream);
+hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
+                     const MsState& st, hipStream_t stream);
+hipError_t launch_mapback(int32_t n, const int32_t* map_off, const int32_t* map_idx, const double* bcp,
+                          const double* corr, const double* bcx, double scale, double* out, hipStream_t stream);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t stream);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t stream);
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t stream);
+
+// Resident workgroups per compute unit (from the HIP occupancy calculator).
+int occupancy_wg(int block, bool lds, size_t dyn_lds_bytes);
+int occupancy_ms(int waves);
+
+// LDS bytes the LDS-resident kernel needs for a piece of np vertices.
+size_t wg_lds_bytes(int32_t max_np);
+// Largest LDS allocation a block may use on this device.
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+}  // namespace sbc

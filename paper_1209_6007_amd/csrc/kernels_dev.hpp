@@ -1,0 +1,609 @@
+// Traversal kernels for gfx950 (CDNA4, wave64).
+//
+// Every kernel computes, for the sources of one piece, Algorithm 2 of the
+// paper (Bc-Reach, Section 3.2.1) with the identical-vertex weights of
+// Section 3.3.3:
+//   forward   d[s]=0, sigma[s]=1; for a vertex w first reached at level l,
+//             sigma[w] = sum over neighbours v at level l-1 of
+//             sigma[v] * (v == s ? 1 : ident[v])
+//   backward  delta[v] = (reach[v]-1)
+//                        + sigma[v] * sum over neighbours w at level d[v]+1 of
+//                          ident[w] * (1 + delta[w]) / sigma[w]
+//             (Eq. (3) in pull form: the stack of Algorithm 1 becomes a
+//             deepest-level-first sweep and the predecessor lists become a
+//             level test on the neighbours)
+//   accumulate bc'[v] += ident[s] * reach[s] * delta[v] for v != s.
+// The backward coefficient ident[w]*(1+delta[w])/sigma[w] overwrites
+// sigma[w]: once delta[w] is known no one needs sigma[w] again.
+//
+// Kernels are persistent: a grid of resident workgroups drains a device work
+// queue with an atomic counter, so thousands of uneven items share one launch.
+//
+// This header holds only device code.  It is compiled for gfx950 by
+// kernels.hip; SBC_DYNAMIC_LDS(name) must be defined by the includer to
+// declare the dynamic LDS array.
+#pragma once
+
+#include <cfloat>
+#include <cstdint>
+
+#include "kernel_types.hpp"
+
+namespace sbc {
+namespace dev {
+
+__device__ __forceinline__ void raise_flag(int32_t* flags, int32_t bit) {
+  __hip_atomic_fetch_or(flags, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int k) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), k);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over the block; returns the thread's prefix and the block total.
+// Contains two barriers; s_wtot holds one int per wave.
+template <int BLOCK>
+__device__ __forceinline__ int block_excl_scan(int x, int* s_wtot, int* total) {
+  constexpr int WAVES = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int incl = wave_incl_scan(x, lane);
+  if (lane == 63) s_wtot[wave] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    const int t = s_wtot[w];
+    before += (w < wave) ? t : 0;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+// ---------------------------------------------------------------------------
+// One source per workgroup.  State (levels, sigma/coefficient, BFS order,
+// level starts) lives in LDS for pieces that fit, else in a per-workgroup
+// slot of global memory.  Level-synchronous: one barrier per level.
+// ---------------------------------------------------------------------------
+template <int BLOCK, bool REACH, bool IDENT>
+__device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, const int32_t* __restrict__ col,
+                                           const int32_t* __restrict__ rch, const int32_t* __restrict__ idn,
+                                           const int32_t np, const int32_t s, int32_t* d, double* sig, int32_t* q,
+                                           int32_t* lvl, int* s_cnt, double* __restrict__ bcp, int32_t* flags,
+                                           const DebugOut& dbg) {
+  const int tid = threadIdx.x;
+  double wsrc = 1.0;
+  if (REACH) wsrc *= (double)rch[s];
+  if (IDENT) wsrc *= (double)idn[s];
+  if (tid == 0) {
+    d[s] = 0;
+    sig[s] = 1.0;
+    q[0] = s;
+    lvl[0] = 0;
+    lvl[1] = 1;
+    s_cnt[0] = 0;
+    s_cnt[1] = 0;
+    s_cnt[2] = 0;
+  }
+  __syncthreads();
+  int qs = 0, qe = 1, L = 0;
+  // Forward sweep: expand level L = q[qs, qe) into level L+1.
+  while (true) {
+    if (tid == 0) s_cnt[(L + 1) % 3] = 0;  // counter of level L+1; last read two levels ago
+    for (int i = qs + tid; i < qe; i += BLOCK) {
+      const int32_t u = q[i];
+      double su = sig[u];
+      if (IDENT && L > 0) su *= (double)idn[u];
+      const int32_t e1 = rowp[u + 1];
+      for (int32_t e = rowp[u]; e < e1; ++e) {
+        const int32_t w = col[e];
+        int32_t dw = __hip_atomic_load(&d[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (dw < 0) {
+          const int32_t old = atomicCAS(&d[w], -1, L + 1);
+          if (old == -1) {
+            const int pos = atomicAdd(&s_cnt[L % 3], 1);
+            q[qe + pos] = w;
+            dw = L + 1;
+          } else {
+            dw = old;
+          }
+        }
+        if (dw == L + 1) atomicAdd(&sig[w], su);
+      }
+    }
+    __syncthreads();
+    const int nt = qe + s_cnt[L % 3];
+    if (nt == qe) break;
+    qs = qe;
+    qe = nt;
+    ++L;
+    if (tid == 0) lvl[L + 1] = qe;
+  }
+  if (dbg.dist) {
+    for (int v = tid; v < np; v += BLOCK) {
+      dbg.dist[v] = d[v];
+      dbg.sigma[v] = sig[v];
+    }
+    __syncthreads();
+  }
+  // Backward sweep, deepest level first.
+  for (int l = L; l >= 1; --l) {
+    const int b = lvl[l], e = lvl[l + 1];
+    for (int i = b + tid; i < e; i += BLOCK) {
+      const int32_t v = q[i];
+      double acc = 0.0;
+      const int32_t e1 = rowp[v + 1];
+      for (int32_t x = rowp[v]; x < e1; ++x) {
+        const int32_t w = col[x];
+        if (d[w] == l + 1) acc += sig[w];
+      }
+      const double sv = sig[v];
+      const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+      const double coef = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+      sig[v] = coef;
+      atomicAdd(&bcp[v], wsrc * dv);
+      if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, 1);
+      if (dbg.delta) dbg.delta[v] = dv;
+    }
+    __syncthreads();
+  }
+  // Restore the untouched state (-1 / 0) for the next source.
+  for (int i = tid; i < qe; i += BLOCK) {
+    const int32_t v = q[i];
+    d[v] = -1;
+    sig[v] = 0.0;
+  }
+  __syncthreads();
+}
+
+template <int BLOCK, bool REACH, bool IDENT, bool LDS>
+__global__ __launch_bounds__(BLOCK) void wg_kernel(DevPieces P, QueueArgs Q, WgState st, int32_t max_np,
+                                                   DebugOut dbg) {
+  SBC_DYNAMIC_LDS(dyn);
+  __shared__ int s_item;
+  __shared__ int s_cnt[3];
+  const int tid = threadIdx.x;
+  double* sig;
+  int32_t *d, *q, *lvl;
+  if constexpr (LDS) {
+    sig = reinterpret_cast<double*>(dyn);
+    d = reinterpret_cast<int32_t*>(sig + max_np);
+    q = d + max_np;
+    lvl = q + max_np;
+  } else {
+    const size_t b = blockIdx.x;
+    sig = st.sig + b * st.stride;
+    d = st.d + b * st.stride;
+    q = st.q + b * st.stride;
+    lvl = st.lvl + b * (st.stride + 2);
+  }
+  while (true) {
+    if (tid == 0) s_item = atomicAdd(Q.head, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= Q.nitems) break;
+    const WorkItem W = Q.items[it];
+    const int32_t vb = P.vtx_off[W.piece];
+    const int32_t np = P.vtx_off[W.piece + 1] - vb;
+    const int32_t* rowp = P.row + vb;
+    const int32_t* rch = REACH ? P.reach + vb : nullptr;
+    const int32_t* idn = IDENT ? P.ident + vb : nullptr;
+    double* bcp = P.bcp + vb;
+    if constexpr (LDS) {
+      for (int v = tid; v < np; v += BLOCK) {
+        d[v] = -1;
+        sig[v] = 0.0;
+      }
+      __syncthreads();
+    }
+    for (int32_t k = W.s0; k < W.s1; ++k) {
+      const int32_t s = P.src_order[vb + k];
+      one_source<BLOCK, REACH, IDENT>(rowp, P.col, rch, idn, np, s, d, sig, q, lvl, s_cnt, bcp, Q.flags, dbg);
+    }
+    if (tid == 0) atomicAdd(Q.done, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 64 sources per workgroup, one per lane of every wavefront.
+//
+// Per vertex v and lane j the slot keeps sg[v*64+j] (sigma, later the
+// backward coefficient) so that the 64 sources' values of one vertex are one
+// contiguous 512-byte row: a neighbour visit reads one coalesced row for all
+// sources instead of 64 scattered words.  Reachability is tracked with 64-bit
+// lane masks (vis, frontier), and the BFS order is a list of (vertex, lanes)
+// entries: a vertex appears once for every distinct level its lanes reach it
+// at, so the backward sweep visits exactly the (vertex, level) pairs that
+// exist.
+// ---------------------------------------------------------------------------
+constexpr int kHubArcs = 1024;   // rows longer than this are split over all waves
+constexpr int kSliceArcs = kMsSliceArcs;  // arcs per split slice
+constexpr int kHeavyMax = kMsHeavyMax;   // split rows per level
+
+// Sum over the neighbours c of a vertex (arcs [e0, e1)) of sg[c*64+lane] for
+// the lanes in need & mk[c] (scaled by ident[c] when `scale` is set).
+__device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int32_t e0, int32_t e1,
+                                           const uint64_t* __restrict__ mk, const uint64_t need,
+                                           const double* __restrict__ sg, const int32_t* __restrict__ idn,
+                                           const bool scale, const int lane) {
+  double acc = 0.0;
+  for (int32_t eb = e0; eb < e1; eb += 64) {
+    const int32_t e = eb + lane;
+    int32_t c = 0;
+    uint64_t m = 0;
+    if (e < e1) {
+      c = col[e];
+      m = mk[c] & need;
+    }
+    uint64_t act = __ballot(m != 0);
+    while (act) {
+      const int k = __builtin_ctzll(act);
+      act &= act - 1;
+      const int32_t u = __builtin_amdgcn_readlane(c, k);
+      const uint64_t mu = readlane64(m, k);
+      if ((mu >> lane) & 1) {
+        double x = sg[(size_t)u * 64 + lane];
+        if (scale) x *= (double)idn[u];
+        acc += x;
+      }
+    }
+  }
+  return acc;
+}
+
+template <int WAVES, bool REACH, bool IDENT>
+__global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q, MsState st) {
+  constexpr int BLOCK = WAVES * 64;
+  __shared__ int s_item;
+  __shared__ int s_cnt[3];
+  __shared__ int s_wtot[WAVES];
+  __shared__ int s_scan[BLOCK];
+  __shared__ int s_e0[BLOCK];
+  __shared__ uint64_t s_f[BLOCK];
+  __shared__ int s_nheavy, s_nslices;
+  __shared__ int s_heavy[kHeavyMax];
+  __shared__ int s_hoff[kHeavyMax];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t slot = blockIdx.x;
+  double* sg = st.sg + slot * (size_t)st.stride * 64;
+  int32_t* q = st.q + slot * (size_t)st.stride * 64;
+  uint64_t* qm = st.qm + slot * (size_t)st.stride * 64;
+  uint64_t* vis = st.vis + slot * (size_t)st.stride;
+  uint64_t* bufa = st.fa + slot * (size_t)st.stride;
+  uint64_t* bufb = st.fb + slot * (size_t)st.stride;
+  uint64_t* bme = st.ba + slot * (size_t)st.stride;  // backward masks of even levels
+  uint64_t* bmo = st.bb + slot * (size_t)st.stride;  // backward masks of odd levels
+  int32_t* lvl = st.lvl + slot * (size_t)(st.stride + 3);
+  double* part = st.part + slot * (size_t)st.part_cap * 64;
+  const int64_t qcap = st.stride * 64;
+
+  while (true) {
+    if (tid == 0) s_item = atomicAdd(Q.head, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= Q.nitems) break;
+    const WorkItem W = Q.items[it];
+    const int32_t vb = P.vtx_off[W.piece];
+    const int32_t* rowp = P.row + vb;
+    const int32_t* col = P.col;
+    const int32_t* rch = REACH ? P.reach + vb : nullptr;
+    const int32_t* idn = IDENT ? P.ident + vb : nullptr;
+    double* bcp = P.bcp + vb;
+    const int nsrc = W.s1 - W.s0;  // 1..64
+
+    // Lane j runs source src_order[vb + s0 + j].
+    double wsrc = 0.0;
+    if (lane < nsrc) {
+      const int32_t s = P.src_order[vb + W.s0 + lane];
+      wsrc = 1.0;
+      if (REACH) wsrc *= (double)rch[s];
+      if (IDENT) wsrc *= (double)idn[s];
+      if (wave == 0) {
+        q[lane] = s;
+        qm[lane] = 1ull << lane;
+        bufa[s] = 1ull << lane;
+        vis[s] = 1ull << lane;
+        sg[(size_t)s * 64 + lane] = 1.0;
+      }
+    }
+    if (tid == 0) {
+      lvl[0] = 0;
+      lvl[1] = nsrc;
+      s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
+    }
+    __syncthreads();
+
+    uint64_t* fcur = bufa;
+    uint64_t* fnxt = bufb;
+    int qs = 0, qe = nsrc, L = 0;
+    bool ok = true;
+    // ---------------- forward sweep ----------------
+    while (true) {
+      if (tid == 0) {
+        s_cnt[(L + 1) % 3] = 0;
+        s_nheavy = 0;
+        s_nslices = 0;
+      }
+      // Phase A: discover the (vertex, new lanes) pairs of level L+1 with the
+      // arcs of level L spread evenly over the whole workgroup.
+      for (int cb = qs; cb < qe; cb += BLOCK) {
+        const int i = cb + tid;
+        int e0 = 0, deg = 0;
+        uint64_t fu = 0;
+        if (i < qe) {
+          const int32_t u = q[i];
+          e0 = rowp[u];
+          deg = rowp[u + 1] - e0;
+          fu = qm[i];
+        }
+        int total;
+        const int ex = block_excl_scan<BLOCK>(deg, s_wtot, &total);
+        s_scan[tid] = ex;
+        s_e0[tid] = e0;
+        s_f[tid] = fu;
+        __syncthreads();
+        const int nv = min(BLOCK, qe - cb);
+        for (int t = tid; t < total; t += BLOCK) {
+          int lo = 0, hi = nv - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_scan[mid] <= t) lo = mid;
+            else hi = mid - 1;
+          }
+          const int32_t w = col[s_e0[lo] + (t - s_scan[lo])];
+          const uint64_t nw = s_f[lo] & ~vis[w];
+          if (nw) {
+            const uint64_t old = atomicOr((unsigned long long*)&fnxt[w], (unsigned long long)nw);
+            if (old == 0) {
+              const int pos = atomicAdd(&s_cnt[L % 3], 1);
+              if (qe + pos < qcap) q[qe + pos] = w;
+              else raise_flag(Q.flags, 4);
+            }
+          }
+        }
+        __syncthreads();
+      }
+      int nt = qe + s_cnt[L % 3];
+      if (nt > qcap) {
+        nt = (int)qcap;
+        ok = false;
+      }
+      if (nt == qe || !ok) break;
+      // Phase B: sigma of the new lanes, one wave per vertex, pulling from the
+      // neighbours on level L (their frontier masks); long rows are deferred.
+      const bool scale = IDENT && L > 0;
+      for (int i = qe + wave; i < nt; i += WAVES) {
+        const int32_t w = q[i];
+        const uint64_t need = fnxt[w];
+        const int32_t e0 = rowp[w], e1 = rowp[w + 1];
+        if (e1 - e0 > kHubArcs) {
+          int reg = 0;
+          if (lane == 0) {
+            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+            const int h = atomicAdd(&s_nheavy, 1);
+            const int o = atomicAdd(&s_nslices, ns);
+            if (h < kHeavyMax && o + ns <= st.part_cap) {
+              s_heavy[h] = i;
+              s_hoff[h] = o;
+              reg = 1;
+            } else if (h < kHeavyMax) {
+              s_heavy[h] = -1;
+            }
+          }
+          if (__builtin_amdgcn_readfirstlane(reg)) continue;
+        }
+        const double acc = pull_row(col, e0, e1, fcur, need, sg, idn, scale, lane);
+        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+        if (lane == 0) {
+          vis[w] |= need;
+          qm[i] = need;
+        }
+      }
+      __syncthreads();
+      const int nh = min(s_nheavy, kHeavyMax);
+      if (nh > 0) {
+        for (int h = 0; h < nh; ++h) {
+          const int i = s_heavy[h];
+          if (i < 0) continue;
+          const int32_t w = q[i];
+          const uint64_t need = fnxt[w];
+          const int32_t e0 = rowp[w], e1 = rowp[w + 1];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          for (int sl = wave; sl < ns; sl += WAVES) {
+            const int32_t a = e0 + sl * kSliceArcs;
+            const int32_t b = min(e1, a + kSliceArcs);
+            part[(size_t)(s_hoff[h] + sl) * 64 + lane] = pull_row(col, a, b, fcur, need, sg, idn, scale, lane);
+          }
+        }
+        __syncthreads();
+        for (int h = wave; h < nh; h += WAVES) {
+          const int i = s_heavy[h];
+          if (i < 0) continue;
+          const int32_t w = q[i];
+          const uint64_t need = fnxt[w];
+          const int32_t e0 = rowp[w], e1 = rowp[w + 1];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          double acc = 0.0;
+          for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
+          if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+          if (lane == 0) {
+            vis[w] |= need;
+            qm[i] = need;
+          }
+        }
+        __syncthreads();
+      }
+      // Phase C: retire level L's frontier masks; level L+1 becomes current.
+      for (int i = qs + tid; i < qe; i += BLOCK) fcur[q[i]] = 0;
+      if (tid == 0) lvl[L + 2] = nt;
+      __syncthreads();
+      uint64_t* t = fcur;
+      fcur = fnxt;
+      fnxt = t;
+      qs = qe;
+      qe = nt;
+      ++L;
+    }
+    for (int i = qs + tid; i < qe; i += BLOCK) fcur[q[i]] = 0;
+    __syncthreads();
+    const int total = qe;
+    const int Lmax = L;
+
+    // ---------------- backward sweep ----------------
+    if (ok) {
+      for (int l = Lmax; l >= 1; --l) {
+        uint64_t* bw = (l & 1) ? bmo : bme;  // masks of level l, written now
+        uint64_t* br = (l & 1) ? bme : bmo;  // masks of level l+1, read now
+        if (l + 2 <= Lmax)
+          for (int i = lvl[l + 2] + tid; i < lvl[l + 3]; i += BLOCK) bw[q[i]] = 0;
+        if (tid == 0) {
+          s_nheavy = 0;
+          s_nslices = 0;
+        }
+        __syncthreads();
+        const int b = lvl[l], e = lvl[l + 1];
+        for (int i = b + wave; i < e; i += WAVES) {
+          const int32_t v = q[i];
+          const uint64_t amask = qm[i];
+          const int32_t e0 = rowp[v], e1 = rowp[v + 1];
+          if (e1 - e0 > kHubArcs) {
+            int reg = 0;
+            if (lane == 0) {
+              const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+              const int h = atomicAdd(&s_nheavy, 1);
+              const int o = atomicAdd(&s_nslices, ns);
+              if (h < kHeavyMax && o + ns <= st.part_cap) {
+                s_heavy[h] = i;
+                s_hoff[h] = o;
+                reg = 1;
+              } else if (h < kHeavyMax) {
+                s_heavy[h] = -1;
+              }
+            }
+            if (__builtin_amdgcn_readfirstlane(reg)) continue;
+          }
+          const double acc = pull_row(col, e0, e1, br, amask, sg, idn, false, lane);
+          double contrib = 0.0;
+          if ((amask >> lane) & 1) {
+            const size_t at = (size_t)v * 64 + lane;
+            const double sv = sg[at];
+            const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+            sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+            contrib = wsrc * dv;
+            if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, 1);
+          }
+          contrib = wave_sum(contrib);
+          if (lane == 0) {
+            atomicAdd(&bcp[v], contrib);
+            bw[v] = amask;
+          }
+        }
+        __syncthreads();
+        const int nh = min(s_nheavy, kHeavyMax);
+        if (nh > 0) {
+          for (int h = 0; h < nh; ++h) {
+            const int i = s_heavy[h];
+            if (i < 0) continue;
+            const int32_t v = q[i];
+            const uint64_t amask = qm[i];
+            const int32_t e0 = rowp[v], e1 = rowp[v + 1];
+            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+            for (int sl = wave; sl < ns; sl += WAVES) {
+              const int32_t a = e0 + sl * kSliceArcs;
+              const int32_t bnd = min(e1, a + kSliceArcs);
+              part[(size_t)(s_hoff[h] + sl) * 64 + lane] = pull_row(col, a, bnd, br, amask, sg, idn, false, lane);
+            }
+          }
+          __syncthreads();
+          for (int h = wave; h < nh; h += WAVES) {
+            const int i = s_heavy[h];
+            if (i < 0) continue;
+            const int32_t v = q[i];
+            const uint64_t amask = qm[i];
+            const int32_t e0 = rowp[v], e1 = rowp[v + 1];
+            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+            double acc = 0.0;
+            for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
+            double contrib = 0.0;
+            if ((amask >> lane) & 1) {
+              const size_t at = (size_t)v * 64 + lane;
+              const double sv = sg[at];
+              const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+              sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+              contrib = wsrc * dv;
+              if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, 1);
+            }
+            contrib = wave_sum(contrib);
+            if (lane == 0) {
+              atomicAdd(&bcp[v], contrib);
+              bw[v] = amask;
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // Restore the slot: clear the backward masks of the two lowest levels and
+    // the visit masks of every entry.
+    for (int l = 1; l <= 2 && l <= Lmax; ++l) {
+      uint64_t* bw = (l & 1) ? bmo : bme;
+      for (int i = lvl[l] + tid; i < lvl[l + 1]; i += BLOCK) bw[q[i]] = 0;
+    }
+    if (!ok) {
+      // a failed batch may have left masks anywhere its queue reached
+      for (int i = tid; i < total; i += BLOCK) {
+        const int32_t v = q[i];
+        bme[v] = 0;
+        bmo[v] = 0;
+        bufa[v] = 0;
+        bufb[v] = 0;
+      }
+    }
+    for (int i = tid; i < total; i += BLOCK) vis[q[i]] = 0;
+    __syncthreads();
+    if (tid == 0) atomicAdd(Q.done, 1);
+  }
+}
+
+__global__ void mapback_kernel(int32_t n, const int32_t* __restrict__ map_off, const int32_t* __restrict__ map_idx,
+                               const double* __restrict__ bcp, const double* __restrict__ corr,
+                               const double* __restrict__ bcx, double scale, double* __restrict__ out) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double acc = bcx ? bcx[v] : 0.0;
+  for (int32_t j = map_off[v]; j < map_off[v + 1]; ++j) {
+    const int32_t x = map_idx[j];
+    acc += bcp[x] + (corr ? corr[x] : 0.0);
+  }
+  out[v] = acc * scale;
+}
+
+template <typename T>
+__global__ void fill_kernel(T* p, T v, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+}  // namespace dev
+}  // namespace sbc

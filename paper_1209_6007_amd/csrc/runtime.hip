@@ -1,0 +1,493 @@
+// Plan construction and execution: uploads a prepared problem, sorts pieces
+// into kernel classes, builds the device work queues, sizes the per-workgroup
+// traversal state, and runs every class concurrently on its own stream.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+namespace sbc {
+
+namespace {
+thread_local std::string g_last_error;
+
+double wall_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v) {
+  size_t bytes = std::max<size_t>(v.size() * sizeof(T), sizeof(T));
+  hipError_t e = b.alloc(bytes);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const std::string& last_error() { return g_last_error; }
+
+sbc_status fail(sbc_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+sbc_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? SBC_E_OOM : SBC_E_DEVICE;
+}
+
+hipError_t DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) b = 8;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return e;
+  }
+  bytes = b;
+  return hipSuccess;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void Plan::quiesce() {
+  if (own) (void)hipStreamSynchronize(own);
+  for (int c = 0; c < KC_COUNT; ++c)
+    if (side[c]) (void)hipStreamSynchronize(side[c]);
+  if (graph_stream) (void)hipStreamSynchronize(graph_stream);
+  if (last_stream) (void)hipStreamSynchronize(last_stream);
+  (void)hipGetLastError();
+}
+
+Plan::~Plan() {
+  // Device buffers are freed by the members' destructors after this body:
+  // nothing the plan launched may still be running then.
+  if (ctx) {
+    (void)hipSetDevice(ctx->device);
+    quiesce();
+  }
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  for (auto e : {ev_start, ev_trav, ev_end, ev_fork})
+    if (e) (void)hipEventDestroy(e);
+  for (int c = 0; c < KC_COUNT; ++c) {
+    if (ev_kc_start[c]) (void)hipEventDestroy(ev_kc_start[c]);
+    if (ev_kc_end[c]) (void)hipEventDestroy(ev_kc_end[c]);
+    if (side[c]) (void)hipStreamDestroy(side[c]);
+  }
+  if (own) (void)hipStreamDestroy(own);
+  if (h_ctl) (void)hipHostFree(h_ctl);
+}
+
+size_t Plan::device_bytes() const {
+  size_t t = 0;
+  for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
+                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &ms_sg, &ms_q, &ms_qm, &ms_vis, &ms_fa, &ms_fb,
+                          &ms_ba, &ms_bb, &ms_lvl, &ms_part, &wg_d, &wg_sig, &wg_q, &wg_lvl})
+    t += b->bytes;
+  for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes;
+  return t;
+}
+
+namespace {
+
+// Per-slot bytes of the 64-source batch kernel for pieces of up to `stride`
+// vertices and `arcs` arcs.
+size_t ms_slot_bytes(int64_t stride, int64_t part_cap) {
+  return (size_t)stride * 64 * (8 + 4 + 8) + (size_t)stride * 8 * 5 + (size_t)(stride + 3) * 4 +
+         (size_t)part_cap * 64 * 8;
+}
+size_t wg_slot_bytes(int64_t stride) { return (size_t)stride * 16 + (size_t)(stride + 2) * 4; }
+
+int classify(const Params& pr, int32_t np, bool plain, int force) {
+  if (force == 1) return KC_GLOBAL;
+  if (force == 2) return np <= pr.wave_max_vertices ? KC_WAVE : KC_LDS;
+  if (force == 3) return KC_BATCH;
+  if (plain && pr.plain_kernel == 1) return KC_GLOBAL;
+  if (np >= pr.batch_min_vertices) return KC_BATCH;
+  if (np <= pr.wave_max_vertices) return KC_WAVE;
+  if (np <= pr.lds_max_vertices) return KC_LDS;
+  return KC_GLOBAL;
+}
+
+}  // namespace
+
+size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
+  size_t t = (size_t)prob.V() * (4 * 4 + 8 * 2) + prob.A() * 4 + (size_t)prob.n * (8 * 2 + 4) +
+             prob.map_idx.size() * 4 + (size_t)prob.pieces() * 4;
+  int64_t max_batch = 0, max_batch_arcs = 0, max_glob = 0;
+  for (int32_t p = 0; p < prob.pieces(); ++p) {
+    int32_t np = prob.vtx_off[p + 1] - prob.vtx_off[p];
+    int k = classify(c->params, np, false, 0);
+    if (k == KC_BATCH) {
+      max_batch = std::max<int64_t>(max_batch, np);
+      max_batch_arcs = std::max<int64_t>(max_batch_arcs, prob.row[prob.vtx_off[p + 1]] - prob.row[prob.vtx_off[p]]);
+    }
+    if (k == KC_GLOBAL) max_glob = std::max<int64_t>(max_glob, np);
+  }
+  if (max_batch) t += ms_slot_bytes(max_batch, max_batch_arcs / kMsSliceArcs + 2 * kMsHeavyMax) * 4;
+  if (max_glob) t += wg_slot_bytes(max_glob) * 16;
+  return t;
+}
+
+sbc_status Plan::build(sbc_context c, const Prepared& prob, uint32_t mode, const PlanOptions& opt) {
+  const sbc_status rc = build_impl(c, prob, mode, opt);
+  if (rc != SBC_OK) quiesce();  // an early return must not leave set-up kernels running
+  return rc;
+}
+
+sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mode, const PlanOptions& opt) {
+  ctx = c;
+  const Params& pr = c->params;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // Streams and events first: every set-up kernel runs on `own`, so any
+  // return path can wait for it before buffers are released.
+  if ((e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  for (int k = 0; k < KC_COUNT; ++k)
+    if ((e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  for (hipEvent_t* ev : {&ev_start, &ev_trav, &ev_end})
+    if ((e = hipEventCreate(ev)) != hipSuccess) return hip_fail(e, "event");
+  if ((e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+  for (int k = 0; k < KC_COUNT; ++k) {
+    if ((e = hipEventCreate(&ev_kc_start[k])) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreate(&ev_kc_end[k])) != hipSuccess) return hip_fail(e, "event");
+  }
+  const bool plain = !(mode & SBC_COMPRESSED);
+  const Prepared* probp = &prob_in;
+  Prepared local;
+  if (opt.sources || opt.debug_single || (pr.cluster_sources && prob_in.pieces() > 0)) {
+    local = prob_in;
+    probp = &local;
+    if (pr.cluster_sources && !opt.sources && !opt.debug_single) cluster_sources(&local, 64);
+    if (opt.sources) {
+      // plain graph, one piece: the listed sources first
+      std::vector<uint8_t> seen(local.n, 0);
+      for (int64_t i = 0; i < opt.nsrc; ++i) {
+        int32_t s = opt.sources[i];
+        if (s < 0 || s >= local.n) return fail(SBC_E_INDEX_RANGE, "source out of range");
+        if (seen[s]) return fail(SBC_E_INVALID_ARG, "sources must be distinct");
+        seen[s] = 1;
+        local.src_order[i] = s;
+      }
+      int64_t k = opt.nsrc;
+      for (int32_t v = 0; v < local.n; ++v)
+        if (!seen[v]) local.src_order[k++] = v;
+    }
+    if (opt.debug_single) local.src_order[0] = opt.debug_source;
+  }
+  const Prepared& prob = *probp;
+  n = prob.n;
+  P = prob.pieces();
+  V = prob.V();
+  A = prob.A();
+  reach = prob.weighted;
+  ident = prob.has_ident;
+  scale = (mode & SBC_UNORDERED) ? 0.5 : 1.0;
+
+  // Work items by kernel class.
+  std::vector<WorkItem> items[KC_COUNT];
+  std::vector<int> piece_class(P, -1);
+  teps = 0;
+  algo_bytes = 0;
+  for (int32_t p = 0; p < P; ++p) {
+    const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
+    const int64_t arcs = (int64_t)prob.row[vb + np] - prob.row[vb];
+    int k = classify(pr, np, plain, opt.force_kernel);
+    if (k == KC_LDS || k == KC_WAVE) {
+      if (wg_lds_bytes(np) > c->lds_limit) {
+        if (opt.force_kernel == 2) return fail(SBC_E_INVALID_ARG, "piece too large for the LDS kernel");
+        k = (np >= 64) ? KC_BATCH : KC_GLOBAL;
+      }
+    }
+    piece_class[p] = k;
+    int32_t nsrc = np;
+    if (opt.sources) nsrc = (int32_t)opt.nsrc;
+    if (opt.debug_single) nsrc = 1;
+    if (nsrc <= 0) continue;
+    int32_t chunk = 1;
+    if (k == KC_WAVE) chunk = (int32_t)pr.wave_sources_per_item;
+    if (k == KC_LDS) chunk = (int32_t)pr.lds_sources_per_item;
+    if (k == KC_BATCH) chunk = 64;
+    for (int32_t s0 = 0; s0 < nsrc; s0 += chunk) items[k].push_back({p, s0, std::min(nsrc, s0 + chunk), k});
+    max_np[k] = std::max(max_np[k], np);
+    sources_in[k] += nsrc;
+    teps += (double)nsrc * (double)arcs * 0.5;
+    const double per = 8.0 * arcs + (plain ? 48.0 : (reach || ident ? 56.0 : 48.0)) * np;
+    algo_bytes += (double)nsrc * per;
+    teps_k[k] += (double)nsrc * (double)arcs * 0.5;
+    bytes_k[k] += (double)nsrc * per;
+  }
+  total_items = 0;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    nitems[k] = (int32_t)items[k].size();
+    total_items += nitems[k];
+  }
+
+  // Upload the problem.
+  if ((e = upload(d_vtx_off, prob.vtx_off)) != hipSuccess) return hip_fail(e, "upload vtx_off");
+  if ((e = upload(d_row, prob.row)) != hipSuccess) return hip_fail(e, "upload row");
+  if ((e = upload(d_col, prob.col)) != hipSuccess) return hip_fail(e, "upload col");
+  if (reach && (e = upload(d_reach, prob.reach)) != hipSuccess) return hip_fail(e, "upload reach");
+  if (ident && (e = upload(d_ident, prob.ident)) != hipSuccess) return hip_fail(e, "upload ident");
+  if ((e = upload(d_src, prob.src_order)) != hipSuccess) return hip_fail(e, "upload src_order");
+  if ((e = d_bcp.alloc(std::max<int64_t>(V, 1) * sizeof(double))) != hipSuccess) return hip_fail(e, "alloc bcp");
+  has_map = !plain;
+  if ((e = upload(d_corr, prob.corr)) != hipSuccess) return hip_fail(e, "upload corr");
+  if ((e = upload(d_bcx, prob.bcx)) != hipSuccess) return hip_fail(e, "upload bcx");
+  if ((e = upload(d_map_off, prob.map_off)) != hipSuccess) return hip_fail(e, "upload map_off");
+  if ((e = upload(d_map_idx, prob.map_idx)) != hipSuccess) return hip_fail(e, "upload map_idx");
+  if ((e = d_out.alloc(std::max<int32_t>(n, 1) * sizeof(double))) != hipSuccess) return hip_fail(e, "alloc out");
+  for (int k = 0; k < KC_COUNT; ++k)
+    if ((e = upload(d_items[k], items[k])) != hipSuccess) return hip_fail(e, "upload items");
+  if ((e = d_ctl.alloc(sizeof(int32_t) * 16)) != hipSuccess) return hip_fail(e, "alloc ctl");
+  if ((e = hipHostMalloc((void**)&h_ctl, sizeof(int32_t) * 16, hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(e, "hipHostMalloc");
+  std::memset(h_ctl, 0, sizeof(int32_t) * 16);
+
+  // Traversal state, sized by occupancy and the memory budget.
+  size_t freeb = 0, totalb = 0;
+  (void)hipMemGetInfo(&freeb, &totalb);
+  size_t budget = pr.mem_budget_mb > 0 ? (size_t)pr.mem_budget_mb << 20 : (size_t)(freeb * 0.6);
+  const int cus = c->cus;
+  block[KC_WAVE] = 64;
+  block[KC_LDS] = (int)pr.lds_block;
+  block[KC_GLOBAL] = 256;
+  block[KC_BATCH] = (int)pr.batch_wg_waves * 64;
+  for (int k : {KC_WAVE, KC_LDS}) {
+    if (!nitems[k]) continue;
+    const int occ = occupancy_wg(block[k], true, wg_lds_bytes(max_np[k]));
+    int g = cus * occ;
+    if (pr.slots > 0) g = (int)pr.slots;
+    grid[k] = std::max(1, std::min(g, nitems[k]));
+  }
+  if (nitems[KC_GLOBAL]) {
+    const int64_t stride = max_np[KC_GLOBAL];
+    const int occ = occupancy_wg(block[KC_GLOBAL], false, 0);
+    int g = cus * occ;
+    if (pr.slots > 0) g = (int)pr.slots;
+    g = std::min<int64_t>(g, std::max<int64_t>(1, (int64_t)(budget / 2 / wg_slot_bytes(stride))));
+    g = std::max(1, std::min(g, nitems[KC_GLOBAL]));
+    grid[KC_GLOBAL] = g;
+    wg.stride = stride;
+    if ((e = wg_d.alloc((size_t)g * stride * 4)) != hipSuccess) return hip_fail(e, "alloc wg d");
+    if ((e = wg_sig.alloc((size_t)g * stride * 8)) != hipSuccess) return hip_fail(e, "alloc wg sig");
+    if ((e = wg_q.alloc((size_t)g * stride * 4)) != hipSuccess) return hip_fail(e, "alloc wg q");
+    if ((e = wg_lvl.alloc((size_t)g * (stride + 2) * 4)) != hipSuccess) return hip_fail(e, "alloc wg lvl");
+    wg.d = wg_d.as<int32_t>();
+    wg.sig = wg_sig.as<double>();
+    wg.q = wg_q.as<int32_t>();
+    wg.lvl = wg_lvl.as<int32_t>();
+    if ((e = launch_fill_i32(wg.d, -1, (int64_t)g * stride, own)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill_f64(wg.sig, 0.0, (int64_t)g * stride, own)) != hipSuccess) return hip_fail(e, "fill");
+  }
+  if (nitems[KC_BATCH]) {
+    const int64_t stride = max_np[KC_BATCH];
+    int64_t max_arcs = 0;
+    for (int32_t p = 0; p < P; ++p) {
+      const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
+      if (piece_class[p] == KC_BATCH)
+        max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
+    }
+    const int64_t part_cap = max_arcs / kMsSliceArcs + 2 * kMsHeavyMax;
+    const int occ = occupancy_ms((int)pr.batch_wg_waves);
+    int g = cus * occ;
+    if (pr.slots > 0) g = (int)pr.slots;
+    const size_t per = ms_slot_bytes(stride, part_cap);
+    g = std::min<int64_t>(g, std::max<int64_t>(1, (int64_t)(budget / per)));
+    g = std::max(1, std::min(g, nitems[KC_BATCH]));
+    grid[KC_BATCH] = g;
+    ms.stride = stride;
+    ms.part_cap = (int32_t)part_cap;
+    const size_t G = g;
+    if ((e = ms_sg.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms sg");
+    if ((e = ms_q.alloc(G * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc ms q");
+    if ((e = ms_qm.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms qm");
+    if ((e = ms_vis.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms vis");
+    if ((e = ms_fa.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms fa");
+    if ((e = ms_fb.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms fb");
+    if ((e = ms_ba.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms ba");
+    if ((e = ms_bb.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms bb");
+    if ((e = ms_lvl.alloc(G * (stride + 3) * 4)) != hipSuccess) return hip_fail(e, "alloc ms lvl");
+    if ((e = ms_part.alloc(G * part_cap * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms part");
+    ms.sg = ms_sg.as<double>();
+    ms.q = ms_q.as<int32_t>();
+    ms.qm = ms_qm.as<uint64_t>();
+    ms.vis = ms_vis.as<uint64_t>();
+    ms.fa = ms_fa.as<uint64_t>();
+    ms.fb = ms_fb.as<uint64_t>();
+    ms.ba = ms_ba.as<uint64_t>();
+    ms.bb = ms_bb.as<uint64_t>();
+    ms.lvl = ms_lvl.as<int32_t>();
+    ms.part = ms_part.as<double>();
+    for (uint64_t* p : {ms.vis, ms.fa, ms.fb, ms.ba, ms.bb})
+      if ((e = launch_fill_u64(p, 0, (int64_t)G * stride, own)) != hipSuccess) return hip_fail(e, "fill ms");
+  }
+  if (opt.debug_single) {
+    const int64_t np = V;
+    if ((e = dbg_dist.alloc(np * 4)) != hipSuccess) return hip_fail(e, "alloc dbg");
+    if ((e = dbg_sigma.alloc(np * 8)) != hipSuccess) return hip_fail(e, "alloc dbg");
+    if ((e = dbg_delta.alloc(np * 8)) != hipSuccess) return hip_fail(e, "alloc dbg");
+    dbg = {dbg_dist.as<int32_t>(), dbg_sigma.as<double>(), dbg_delta.as<double>()};
+    if ((e = launch_fill_f64(dbg.delta, 0.0, np, own)) != hipSuccess) return hip_fail(e, "fill dbg");
+  }
+  if ((e = hipStreamSynchronize(own)) != hipSuccess) return hip_fail(e, "plan setup");
+  return SBC_OK;
+}
+
+sbc_status Plan::enqueue(double* out, hipStream_t s) {
+  hipError_t e;
+  int32_t* ctl = d_ctl.as<int32_t>();
+  int32_t* heads = ctl;            // [0..3]
+  int32_t* done = ctl + 4;         // [4..7]
+  int32_t* flags = ctl + 8;        // [8]
+  if ((e = launch_fill_f64(d_bcp.as<double>(), 0.0, V, s)) != hipSuccess) return hip_fail(e, "fill bcp");
+  if ((e = launch_fill_i32(ctl, 0, 16, s)) != hipSuccess) return hip_fail(e, "fill ctl");
+  DevPieces dp{d_vtx_off.as<int32_t>(), d_row.as<int32_t>(), d_col.as<int32_t>(), d_reach.as<int32_t>(),
+               d_ident.as<int32_t>(), d_src.as<int32_t>(), d_bcp.as<double>()};
+  if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
+  // Largest classes first so the long multi-source items start early.
+  const int order[KC_COUNT] = {KC_BATCH, KC_GLOBAL, KC_LDS, KC_WAVE};
+  for (int k : order) {
+    if (!nitems[k]) continue;
+    hipStream_t ks = side[k];
+    if ((e = hipStreamWaitEvent(ks, ev_fork, 0)) != hipSuccess) return hip_fail(e, "wait");
+    if (!use_graph && (e = hipEventRecord(ev_kc_start[k], ks)) != hipSuccess) return hip_fail(e, "event");
+    QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], heads + k, flags, done + k};
+    if (k == KC_BATCH) {
+      e = launch_ms(dp, qa, reach, ident, block[k] / 64, grid[k], ms, ks);
+    } else {
+      const bool lds = (k == KC_WAVE || k == KC_LDS);
+      e = launch_wg(dp, qa, reach, ident, lds, block[k], grid[k], max_np[k], wg, dbg.dist ? &dbg : nullptr, ks);
+    }
+    if (e != hipSuccess) return hip_fail(e, "launch traversal");
+    if ((e = hipEventRecord(ev_kc_end[k], ks)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipStreamWaitEvent(s, ev_kc_end[k], 0)) != hipSuccess) return hip_fail(e, "wait");
+  }
+  if (!use_graph && (e = hipEventRecord(ev_trav, s)) != hipSuccess) return hip_fail(e, "event");
+  double* dst = out ? out : d_out.as<double>();
+  if (has_map) {
+    e = launch_mapback(n, d_map_off.as<int32_t>(), d_map_idx.as<int32_t>(), d_bcp.as<double>(),
+                       d_corr.as<double>(), d_bcx.as<double>(), scale, dst, s);
+  } else {
+    e = launch_mapback(n, d_map_off.as<int32_t>(), d_map_idx.as<int32_t>(), d_bcp.as<double>(), nullptr, nullptr,
+                       scale, dst, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "launch mapback");
+  if ((e = hipMemcpyAsync(h_ctl, ctl, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(e, "copy ctl");
+  return SBC_OK;
+}
+
+sbc_status Plan::execute(double* out, hipStream_t s) {
+  hipError_t e;
+  if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (!s) s = own;
+  last_stream = s;
+  const double t0 = wall_ms();
+  if ((e = hipEventRecord(ev_start, s)) != hipSuccess) return hip_fail(e, "event");
+  sbc_status rc = SBC_OK;
+  if (use_graph) {
+    if (graph_exec && (graph_stream != s || graph_out != out)) {
+      (void)hipGraphExecDestroy(graph_exec);
+      (void)hipGraphDestroy(graph);
+      graph_exec = nullptr;
+      graph = nullptr;
+    }
+    if (!graph_exec) {
+      hipStream_t cap = own;
+      if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "begin capture");
+      rc = enqueue(out, cap);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cap, &g);
+      if (rc != SBC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "end capture");
+      graph = g;
+      if ((e = hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(e, "graph instantiate");
+      graph_stream = s;
+      graph_out = out;
+    }
+    if ((e = hipGraphLaunch(graph_exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+  } else {
+    rc = enqueue(out, s);
+    if (rc != SBC_OK) return rc;
+  }
+  if ((e = hipEventRecord(ev_end, s)) != hipSuccess) return hip_fail(e, "event");
+  ran = true;
+  last_host_ms = wall_ms() - t0;
+  return SBC_OK;
+}
+
+sbc_status Plan::sync(sbc_run_stats* st) {
+  hipError_t e;
+  if (!ran) return fail(SBC_E_INVALID_ARG, "plan has not been executed");
+  const double t0 = wall_ms();
+  if ((e = hipEventSynchronize(ev_end)) != hipSuccess) return hip_fail(e, "sync");
+  float ms_all = 0, ms_tr = 0, ms_mb = 0;
+  double class_ms[KC_COUNT] = {0, 0, 0, 0};
+  (void)hipEventElapsedTime(&ms_all, ev_start, ev_end);
+  if (!use_graph) {
+    float a = 0, b = 0;
+    double first = 1e30, last = 0;
+    for (int k = 0; k < KC_COUNT; ++k) {
+      class_ms[k] = 0;
+      if (!nitems[k]) continue;
+      (void)hipEventElapsedTime(&a, ev_start, ev_kc_start[k]);
+      (void)hipEventElapsedTime(&b, ev_start, ev_kc_end[k]);
+      first = std::min<double>(first, a);
+      last = std::max<double>(last, b);
+      class_ms[k] = b - a;
+    }
+    ms_tr = (first < 1e29) ? (float)(last - first) : 0.f;
+    (void)hipEventElapsedTime(&ms_mb, ev_trav, ev_end);
+  } else {
+    ms_tr = ms_all;
+  }
+  const int32_t flags = h_ctl[8];
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->ms_device = ms_all;
+    st->ms_traverse = ms_tr;
+    st->ms_mapback = ms_mb;
+    st->ms_host = last_host_ms + (wall_ms() - t0);
+    st->teps = teps;
+    st->algo_bytes = algo_bytes;
+    st->items = total_items;
+    st->batched_sources = sources_in[KC_BATCH];
+    st->lds_sources = sources_in[KC_LDS] + sources_in[KC_WAVE];
+    st->global_sources = sources_in[KC_GLOBAL];
+    st->overflow = flags;
+    for (int k = 0; k < KC_COUNT; ++k) {
+      st->ms_class[k] = class_ms[k];
+      st->bytes_class[k] = bytes_k[k];
+      st->teps_class[k] = teps_k[k];
+      st->grid_class[k] = nitems[k] ? grid[k] : 0;
+      st->items_class[k] = nitems[k];
+    }
+  }
+  int32_t done_total = 0;
+  for (int k = 0; k < KC_COUNT; ++k) done_total += h_ctl[4 + k];
+  if (done_total != total_items)
+    return fail(SBC_E_DEVICE, "work queue drained " + std::to_string(done_total) + " of " +
+                                  std::to_string(total_items) + " items");
+  if (flags & 1) return fail(SBC_E_SIGMA_OVERFLOW, "a shortest-path count exceeded the binary64 range");
+  if (flags & 6) return fail(SBC_E_TOO_LARGE, "traversal state overflow");
+  return SBC_OK;
+}
+
+}  // namespace sbc

@@ -1,0 +1,143 @@
+// Runtime objects behind the C interface: context, graph, plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "prep.hpp"
+#include "shatterbc.h"
+
+namespace sbc {
+
+void set_error(const std::string& msg);
+sbc_status fail(sbc_status code, const std::string& msg);
+sbc_status hip_fail(hipError_t e, const char* what);
+
+// Device buffer owned by one object.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  hipError_t alloc(size_t b);
+  void release();
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct Params {
+  int64_t wave_max_vertices = 128;    // pieces up to this size: one source per wavefront, LDS state
+  int64_t lds_max_vertices = 4096;    // pieces up to this size: one source per workgroup, LDS state
+  int64_t batch_min_vertices = 4097;  // pieces from this size: 64-source batches
+  int64_t batch_wg_waves = 16;        // wavefronts per multi-source workgroup
+  int64_t lds_block = 256;            // threads per LDS workgroup
+  int64_t lds_sources_per_item = 32;  // sources per LDS work item
+  int64_t wave_sources_per_item = 64; // sources per wavefront work item
+  int64_t slots = 0;                  // resident workgroups per kernel (0: from occupancy)
+  int64_t cluster_sources = 1;        // breadth-first-ball source order for batches
+  int64_t plain_kernel = 0;           // plain mode: 0 automatic, 1 one source per workgroup (global)
+  int64_t mem_budget_mb = 0;          // traversal state budget (0: 60% of free memory)
+};
+
+}  // namespace sbc
+
+struct sbc_context_s {
+  int device = 0;
+  hipDeviceProp_t prop{};
+  int cus = 0;
+  size_t lds_limit = 64 * 1024;  // dynamic LDS one workgroup may use
+  sbc::Params params;
+  std::mutex mu;
+};
+
+struct sbc_graph_s {
+  sbc::HostGraph g;
+  bool prepared = false;
+  std::string ops;
+  sbc::Prepared prep;
+  sbc_prep_stats stats{};
+};
+
+namespace sbc {
+
+enum KernelClass { KC_WAVE = 0, KC_LDS = 1, KC_BATCH = 2, KC_GLOBAL = 3, KC_COUNT = 4 };
+
+struct PlanOptions {
+  int force_kernel = 0;                 // 0 automatic, 1 global, 2 LDS, 3 batch
+  const int32_t* sources = nullptr;     // plain-mode source subset (host), or null
+  int64_t nsrc = 0;
+  bool debug_single = false;            // one source, keep per-vertex outputs
+  int32_t debug_source = 0;
+};
+
+struct Plan {
+  sbc_context ctx = nullptr;
+  int32_t n = 0;            // output length (original vertices)
+  int32_t P = 0;            // pieces
+  int64_t V = 0, A = 0;
+  bool reach = false, ident = false;
+  double scale = 1.0;
+  bool has_map = true;
+  // device problem
+  DevBuf d_vtx_off, d_row, d_col, d_reach, d_ident, d_src, d_bcp, d_corr, d_bcx, d_map_off, d_map_idx, d_out;
+  DevBuf d_items[KC_COUNT];
+  DevBuf d_ctl;             // int32: heads[KC_COUNT], done[KC_COUNT], flags
+  int32_t* h_ctl = nullptr; // pinned copy of the control block
+  int32_t nitems[KC_COUNT] = {0, 0, 0, 0};
+  int32_t max_np[KC_COUNT] = {0, 0, 0, 0};
+  int grid[KC_COUNT] = {0, 0, 0, 0};
+  int block[KC_COUNT] = {64, 256, 1024, 256};
+  int64_t sources_in[KC_COUNT] = {0, 0, 0, 0};
+  // slot state
+  DevBuf ms_sg, ms_q, ms_qm, ms_vis, ms_fa, ms_fb, ms_ba, ms_bb, ms_lvl, ms_part;
+  MsState ms{};
+  DevBuf wg_d, wg_sig, wg_q, wg_lvl;
+  WgState wg{};
+  DebugOut dbg{nullptr, nullptr, nullptr};
+  DevBuf dbg_dist, dbg_sigma, dbg_delta;
+  // streams and timing
+  hipStream_t own = nullptr;
+  hipStream_t side[KC_COUNT] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_start = nullptr, ev_trav = nullptr, ev_end = nullptr;
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_kc_start[KC_COUNT] = {}, ev_kc_end[KC_COUNT] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool use_graph = false;
+  hipStream_t graph_stream = nullptr;
+  hipStream_t last_stream = nullptr;  // stream of the last execute (may be the caller's)
+  double* graph_out = nullptr;
+  bool ran = false;
+  double teps = 0, algo_bytes = 0;
+  double teps_k[KC_COUNT] = {0, 0, 0, 0}, bytes_k[KC_COUNT] = {0, 0, 0, 0};
+  int64_t total_items = 0;
+  double last_host_ms = 0;
+
+  ~Plan();
+  sbc_status build(sbc_context c, const Prepared& prob, uint32_t mode, const PlanOptions& opt);
+  sbc_status build_impl(sbc_context c, const Prepared& prob, uint32_t mode, const PlanOptions& opt);
+  // Wait for everything this plan enqueued; called before any buffer is freed.
+  void quiesce();
+  sbc_status enqueue(double* out, hipStream_t s);
+  sbc_status execute(double* out, hipStream_t s);
+  sbc_status sync(sbc_run_stats* st);
+  size_t device_bytes() const;
+};
+
+// Rough device footprint of a plan for admission control.
+size_t estimate_plan_bytes(sbc_context c, const Prepared& prob);
+
+}  // namespace sbc
+
+struct sbc_plan_s {
+  sbc::Plan plan;
+};

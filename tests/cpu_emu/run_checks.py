@@ -1,0 +1,114 @@
+"""Run parity checks against the CPU-emulated build of the library --
+TEST INFRASTRUCTURE.  Must run in a process started with libasan preloaded
+(see tests/test_cpu_emulation.py).  Exits nonzero on the first mismatch."""
+import ctypes
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import graphgen as gg  # noqa: E402
+import oracle  # noqa: E402
+import paper_1209_6007_amd as sbc  # noqa: E402
+from tests.helpers import assert_bc_close  # noqa: E402
+
+
+def use_emulated(path):
+    L = ctypes.CDLL(path)
+    for name, (args, res) in sbc._SIGS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    sbc._lib = L
+
+
+def check(name, fn):
+    print(f"-- {name}", flush=True)
+    fn()
+
+
+def main(which):
+    use_emulated(os.path.join(ROOT, "_build", "emu", "libshatterbc_emu.so"))
+    # one resident block per launch and 4-wave batch blocks keep the
+    # thread-per-lane emulation fast; the kernels' logic is the same
+    ctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4})
+    if "single" in which:
+        def single():
+            g = gg.decorated_random(40, 0.08, 10, 6, 3, 2000)
+            reach, ident = gg.random_attributes(g.n, 3000)
+            for r, k in ((None, None), (reach, ident)):
+                for s in (0, g.n // 2, g.n - 1):
+                    d, sg, dl = sbc.sbc_single_source(ctx.h, g.n, g.row_ptr, g.col, s, r, k)
+                    od, osg, odl = oracle.single_source(g.n, g.row_ptr, g.col, s, r, k)
+                    np.testing.assert_array_equal(d, od)
+                    np.testing.assert_array_equal(sg, osg)
+                    m = od > 0
+                    np.testing.assert_allclose(dl[m], odl[m], rtol=1e-9)
+        check("single source", single)
+    full = os.environ.get("SBC_EMU_FULL") == "1"
+    if "pieces" in which:
+        def pieces():
+            cases = [(5, 1), (5, 2), (5, 3), (65, 1), (65, 2), (70, 3), (130, 3)]
+            if full:
+                cases = [(n, k) for n in (3, 5, 64, 65, 130, 700) for k in (1, 2, 3)]
+            for n, kernel in cases:
+                r = gg.rng(n * 7 + kernel)
+                g = gg.erdos_renyi(n, min(0.9, 6.0 / max(n - 1, 1)), int(r.integers(1 << 30)))
+                reach, ident = gg.random_attributes(n, int(r.integers(1 << 30)), rmax=5, kmax=3)
+                for rr, kk in (((None, None), (reach, ident)) if full or n < 10 else ((reach, ident),)):
+                    want = oracle.bc_weighted(g.n, g.row_ptr, g.col, rr, kk)
+                    got = sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, rr, kk, kernel=kernel)
+                    assert_bc_close(got, want, 1e-9, f"piece n={n} kernel={kernel}")
+                print(f"   n={n} kernel={kernel} ok", flush=True)
+        check("piece kernels", pieces)
+    if "whole" in which:
+        def whole():
+            graphs = [("grid8", gg.grid_deleted(side=8, seed=9)), ("rmat6", gg.rmat_decorated(scale=6, seed=3)),
+                      ("decorated", gg.decorated_random(30, 0.1, 8, 5, 3, 11)),
+                      ("empty", gg.csr_from_edges(5, [], [])), ("path2", gg.path(2))]
+            if full:
+                graphs += [("ba2100", gg.ba_pendant_triangles()), ("grid16", gg.grid_deleted(side=16, seed=9)),
+                           ("rmat8", gg.rmat_decorated(scale=8, seed=3))]
+            for name, g in graphs:
+                want = oracle.bc(g)
+                for mode in ("plain", "compressed"):
+                    got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=ctx)
+                    assert_bc_close(got, want, 1e-9, f"{name}/{mode}")
+                print(f"   {name} n={g.n} ok", flush=True)
+        check("whole graphs", whole)
+    if "hubs" in which:
+        def hubs():
+            # a vertex with more arcs than the batch kernel's split threshold
+            n = 1300
+            r = gg.rng(5)
+            u = np.concatenate([np.zeros(1200, np.int64), r.integers(1, n, 600)])
+            v = np.concatenate([np.arange(1, 1201), r.integers(1, n, 600)])
+            g2 = gg.csr_from_edges(n, u, v)
+            src = np.arange(0, 70, dtype=np.int32)
+            want = oracle.bc_plain(g2.n, g2.row_ptr, g2.col, sources=src)
+            G = sbc.Graph(g2.n, g2.row_ptr, g2.col)
+            sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", 64)
+            got = sbc.sbc_betweenness_sources(ctx.h, G.h, src)
+            sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", 4097)
+            assert_bc_close(got, want, 1e-9, "hub rows")
+        check("split rows", hubs)
+    if "server" in which:
+        def server():
+            gs = [gg.rmat_decorated(scale=7, seed=s) for s in range(3)] + [gg.grid_deleted(side=10, seed=4)]
+            srv = sbc.sbc_server_create(ctx.h, 2, 0)
+            Gs = [sbc.Graph(g.n, g.row_ptr, g.col) for g in gs]
+            jobs = [sbc.sbc_server_submit(srv, G.h, sbc.SBC_COMPRESSED) for G in Gs]
+            for g, j in zip(gs, jobs):
+                got, st = sbc.sbc_job_wait(j, g.n)
+                assert_bc_close(got, oracle.bc(g), 1e-9, "server job")
+                sbc.sbc_job_release(j)
+            sbc.sbc_server_destroy(srv)
+        check("server", server)
+    print("ALL OK", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "server"])

@@ -1,0 +1,172 @@
+"""GPU parity: the HIP path, through the C interface, against the oracle.
+
+Bars: BFS levels bit-exact; path counts bit-exact (integer-valued, below 2^53);
+scores within 1e-9 relative per vertex, and exactly 0 where the oracle gives 0.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_1209_6007_amd as sbc
+from tests.helpers import assert_bc_close
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    oracle.build(force=False)
+    c = sbc.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, g, mode):
+    h = sbc.sbc_graph_create(g.n, g.row_ptr, g.col)
+    try:
+        if mode.startswith("compressed"):
+            sbc.sbc_graph_preprocess(h, "dai")
+        return sbc.sbc_betweenness(ctx.h, h, sbc._mode(mode))
+    finally:
+        sbc.sbc_graph_destroy(h)
+
+
+def test_device_is_gfx950(ctx):
+    name = sbc.sbc_context_device_name(ctx.h)
+    print("device:", name, "cus:", sbc.sbc_context_get_param(ctx.h, "cus"),
+          "lds_limit_bytes:", sbc.sbc_context_get_param(ctx.h, "lds_limit_bytes"), flush=True)
+    assert name
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_single_source_state(ctx, seed):
+    g = gg.decorated_random(40 + 20 * seed, 0.08, 10, 6, 3, 2000 + seed)
+    reach, ident = gg.random_attributes(g.n, 3000 + seed)
+    for weighted in (False, True):
+        r, k = (reach, ident) if weighted else (None, None)
+        for s in (0, g.n // 2, g.n - 1):
+            d, sg, dl = sbc.sbc_single_source(ctx.h, g.n, g.row_ptr, g.col, s, r, k)
+            od, osg, odl = oracle.single_source(g.n, g.row_ptr, g.col, s, r, k)
+            np.testing.assert_array_equal(d, od)
+            np.testing.assert_array_equal(sg, osg)
+            m = (od > 0)
+            np.testing.assert_allclose(dl[m], odl[m], rtol=RTOL, atol=0)
+
+
+PIECE_SIZES = [3, 5, 63, 64, 65, 130, 257, 700, 2100]
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("n", PIECE_SIZES)
+def test_piece_kernels_weighted(ctx, kernel, n):
+    """Each traversal kernel on an attributed piece vs Algorithm 2 + ident."""
+    r = gg.rng(n * 7 + kernel)
+    p = min(0.9, 6.0 / max(n - 1, 1))
+    g = gg.erdos_renyi(n, p, int(r.integers(1 << 30)))
+    reach, ident = gg.random_attributes(n, int(r.integers(1 << 30)), rmax=5, kmax=3)
+    print(f"piece n={n} m={g.m} kernel={kernel}", flush=True)
+    for rr, kk in ((None, None), (reach, None), (None, ident), (reach, ident)):
+        want = oracle.bc_weighted(g.n, g.row_ptr, g.col, rr, kk)
+        got = sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, rr, kk, kernel=kernel)
+        assert_bc_close(got, want, RTOL, f"n={n} kernel={kernel}")
+
+
+SMALL = {
+    "path1": lambda: gg.path(1),
+    "path2": lambda: gg.path(2),
+    "path50": lambda: gg.path(50),
+    "star40": lambda: gg.star(40),
+    "cycle33": lambda: gg.cycle(33),
+    "K12": lambda: gg.complete(12),
+    "K3,7": lambda: gg.complete_bipartite(3, 7),
+    "empty": lambda: gg.csr_from_edges(10, [], []),
+    "disconnected": lambda: gg.csr_from_edges(9, [0, 1, 3, 4, 5, 7], [1, 2, 4, 5, 3, 8]),
+    "tree500": lambda: gg.random_tree(500, 3),
+    "grid30": lambda: gg.grid_deleted(side=30, seed=9),
+    "blocks": lambda: gg.block_tree(n_pieces=120, max_size=600, seed=13),
+    "rmat11": lambda: gg.rmat_decorated(scale=11, seed=17),
+    "ba2100": lambda: gg.ba_pendant_triangles(),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("mode", ["plain", "compressed"])
+def test_whole_graph(ctx, name, mode):
+    g = SMALL[name]()
+    print(f"graph {name} n={g.n} m={g.m} mode={mode}", flush=True)
+    want = oracle.bc(g)
+    got = run(ctx, g, mode)
+    assert_bc_close(got, want, RTOL, f"{name}/{mode}")
+
+
+def test_unordered_halves(ctx):
+    g = gg.ba_pendant_triangles()
+    a = run(ctx, g, "compressed")
+    b = run(ctx, g, "compressed+unordered")
+    np.testing.assert_array_equal(b, a * 0.5)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_decorated_random(ctx, seed):
+    r = gg.rng(seed)
+    g = gg.decorated_random(int(r.integers(30, 300)), float(r.uniform(0.01, 0.2)), int(r.integers(0, 60)),
+                            int(r.integers(0, 40)), int(r.integers(0, 20)), 7000 + seed)
+    want = oracle.bc(g)
+    for mode in ("plain", "compressed"):
+        assert_bc_close(run(ctx, g, mode), want, RTOL, f"seed={seed}/{mode}")
+
+
+def test_source_subset(ctx):
+    g = gg.rmat_decorated(scale=12, seed=21)
+    src = gg.rng(5).choice(g.n, size=300, replace=False).astype(np.int32)
+    want = oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src)
+    got = sbc.sbc_betweenness_sources(ctx.h, sbc.Graph(g.n, g.row_ptr, g.col).h, src)
+    assert_bc_close(got, want, RTOL, "sources")
+
+
+def test_plan_reexecute_and_graph_replay(ctx):
+    g = gg.rmat_decorated(scale=11, seed=23)
+    want = oracle.bc(g)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("dai")
+    plan = sbc.sbc_plan_create(ctx.h, G.h, sbc.SBC_COMPRESSED)
+    try:
+        for rep in range(3):
+            sbc.sbc_plan_execute(plan)
+            sbc.sbc_plan_sync(plan)
+            assert_bc_close(sbc.sbc_plan_result(plan, g.n), want, RTOL, f"eager {rep}")
+        sbc.sbc_plan_use_graph(plan, True)
+        for rep in range(4):
+            sbc.sbc_plan_execute(plan)
+            sbc.sbc_plan_sync(plan)
+            assert_bc_close(sbc.sbc_plan_result(plan, g.n), want, RTOL, f"graph replay {rep}")
+            # eager work between replays
+            run(ctx, gg.path(20), "plain")
+    finally:
+        sbc.sbc_plan_destroy(plan)
+
+
+def test_device_output_torch(ctx):
+    import torch
+
+    g = gg.grid_deleted(side=20, seed=3)
+    out = sbc.betweenness_device(g.n, g.row_ptr, g.col, mode="compressed", ctx=ctx)
+    assert out.device.type == "cuda" and out.dtype == torch.float64
+    assert_bc_close(out.cpu().numpy(), oracle.bc(g), RTOL, "device")
+
+
+def test_sigma_overflow_is_reported(ctx):
+    """A chain of 1100 4-cycles doubles the path count at each one: 2^1100
+    overflows binary64, and the library reports it instead of returning inf."""
+    k = 1100
+    u, v = [], []
+    for i in range(k):
+        a, b, c, d = 3 * i, 3 * i + 1, 3 * i + 2, 3 * i + 3
+        u += [a, a, b, c]
+        v += [b, c, d, d]
+    g = gg.csr_from_edges(3 * k + 1, np.array(u), np.array(v))
+    with pytest.raises(sbc.SbcError) as ei:
+        run(ctx, g, "plain")
+    assert ei.value.status == -9
