@@ -130,9 +130,10 @@ def main():
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
     import paper_1209_6007_amd as sbc
+
+    sbc.lib()  # bind the ROCm runtime the library was built against before torch loads its own copy
+    import torch
 
     desc, make = WORKLOADS[args.workload]
     g = make()

@@ -8,6 +8,19 @@ namespace sbc {
 constexpr int kMsSliceArcs = 256;  // arcs per split slice of a long row (multi-source kernel)
 constexpr int kMsHeavyMax = 128;   // split rows per level (multi-source kernel)
 
+// Kernel arguments carry this word; a kernel that sees anything else returns
+// at once instead of dereferencing pointers it cannot trust.
+constexpr int32_t kArgMagic = 0x5BC0DE01;
+
+// Device error flags (QueueArgs::flags).
+constexpr int32_t kFlagSigmaOverflow = 1;   // a path count left the binary64 range
+constexpr int32_t kFlagQueueOverflow = 4;   // a traversal queue would have overrun its slot
+constexpr int32_t kFlagBadItem = 8;         // work item index or source range out of bounds
+constexpr int32_t kFlagBadPiece = 16;       // piece offsets out of bounds or larger than the slot
+constexpr int32_t kFlagBadArc = 32;         // row bounds, neighbour id or queue entry out of range
+constexpr int32_t kFlagBadSource = 64;      // a source id outside its piece
+constexpr int32_t kFlagRangeMask = kFlagBadItem | kFlagBadPiece | kFlagBadArc | kFlagBadSource;
+
 // Packed pieces in device memory.  Piece p owns global piece vertices
 // [vtx_off[p], vtx_off[p+1]); row[] holds absolute arc offsets into col[],
 // col[] holds piece-local neighbour ids.
@@ -19,6 +32,10 @@ struct DevPieces {
   const int32_t* ident;      // may be null when no piece uses ident
   const int32_t* src_order;  // per piece, local source order
   double* bcp;               // accumulated bc' per piece vertex
+  int32_t npieces;           // P: entries of vtx_off are P+1
+  int32_t nverts;            // V: entries of row are V+1
+  int32_t narcs;             // A: entries of col
+  int32_t pad_;
 };
 
 // One work item: sources src_order[vtx_off[piece] + s0 .. + s1) of `piece`.
@@ -64,8 +81,9 @@ struct MsState {
 struct QueueArgs {
   const WorkItem* items;
   int32_t nitems;
+  int32_t magic;      // kArgMagic
   int32_t* head;      // next item to take (device counter, zero before launch)
-  int32_t* flags;     // bit 0: sigma overflow, bit 1: level overflow, bit 2: queue overflow
+  int32_t* flags;     // kFlag* bits
   int32_t* done;      // items finished (device counter)
 };
 

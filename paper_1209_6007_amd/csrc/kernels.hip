@@ -141,12 +141,13 @@ hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
   }
 }
 
-hipError_t launch_mapback(int32_t n, const int32_t* map_off, const int32_t* map_idx, const double* bcp,
-                          const double* corr, const double* bcx, double scale, double* out, hipStream_t stream) {
+hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
+                          const double* bcp, const double* corr, const double* bcx, double scale, double* out,
+                          hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(mapback_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, map_off, map_idx, bcp, corr,
-                     bcx, scale, out);
+  hipLaunchKernelGGL(mapback_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, nverts, nmap, map_off, map_idx,
+                     bcp, corr, bcx, scale, out);
   return hipGetLastError();
 }
 

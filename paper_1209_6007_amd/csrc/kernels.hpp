@@ -16,8 +16,9 @@ hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
                      int grid, int32_t max_np, const WgState& st, const DebugOut* dbg, hipStream_t stream);
 hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
                      const MsState& st, hipStream_t stream);
-hipError_t launch_mapback(int32_t n, const int32_t* map_off, const int32_t* map_idx, const double* bcp,
-                          const double* corr, const double* bcx, double scale, double* out, hipStream_t stream);
+hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
+                          const double* bcp, const double* corr, const double* bcx, double scale, double* out,
+                          hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t stream);

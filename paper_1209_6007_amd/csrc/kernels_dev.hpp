@@ -36,6 +36,14 @@ __device__ __forceinline__ void raise_flag(int32_t* flags, int32_t bit) {
   __hip_atomic_fetch_or(flags, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Load of a value that another wave produced with an atomic (atomics execute
+// in L2): an agent-scope atomic load cannot be served from a stale per-CU L1
+// line.  On LDS it is an ordinary LDS read.
+template <typename T>
+__device__ __forceinline__ T coherent_load(T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int k) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, k);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), k);
@@ -83,12 +91,27 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_wtot, int* total) {
 // level starts) lives in LDS for pieces that fit, else in a per-workgroup
 // slot of global memory.  Level-synchronous: one barrier per level.
 // ---------------------------------------------------------------------------
+// Row bounds of vertex u, or false (with a flag) when they leave [0, narcs].
+__device__ __forceinline__ bool row_bounds(const int32_t* __restrict__ rowp, int32_t u, int32_t narcs, int32_t* e0,
+                                           int32_t* e1, int32_t* flags) {
+  *e0 = rowp[u];
+  *e1 = rowp[u + 1];
+  if (*e0 < 0 || *e1 < *e0 || *e1 > narcs) {
+    raise_flag(flags, kFlagBadArc);
+    return false;
+  }
+  return true;
+}
+
+// Every value read from memory and then used as an index is range-checked:
+// a bad one raises a flag and is skipped, so corrupted input cannot send a
+// kernel outside its buffers.
 template <int BLOCK, bool REACH, bool IDENT>
 __device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, const int32_t* __restrict__ col,
-                                           const int32_t* __restrict__ rch, const int32_t* __restrict__ idn,
-                                           const int32_t np, const int32_t s, int32_t* d, double* sig, int32_t* q,
-                                           int32_t* lvl, int* s_cnt, double* __restrict__ bcp, int32_t* flags,
-                                           const DebugOut& dbg) {
+                                           const int32_t narcs, const int32_t* __restrict__ rch,
+                                           const int32_t* __restrict__ idn, const int32_t np, const int32_t s,
+                                           int32_t* d, double* sig, int32_t* q, int32_t* lvl, int* s_cnt,
+                                           double* __restrict__ bcp, int32_t* flags, const DebugOut& dbg) {
   const int tid = threadIdx.x;
   double wsrc = 1.0;
   if (REACH) wsrc *= (double)rch[s];
@@ -110,17 +133,27 @@ __device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, con
     if (tid == 0) s_cnt[(L + 1) % 3] = 0;  // counter of level L+1; last read two levels ago
     for (int i = qs + tid; i < qe; i += BLOCK) {
       const int32_t u = q[i];
-      double su = sig[u];
+      int32_t e0, e1;
+      if (u < 0 || u >= np) {
+        raise_flag(flags, kFlagBadArc);
+        continue;
+      }
+      if (!row_bounds(rowp, u, narcs, &e0, &e1, flags)) continue;
+      double su = coherent_load(&sig[u]);  // summed with atomics during the previous level
       if (IDENT && L > 0) su *= (double)idn[u];
-      const int32_t e1 = rowp[u + 1];
-      for (int32_t e = rowp[u]; e < e1; ++e) {
+      for (int32_t e = e0; e < e1; ++e) {
         const int32_t w = col[e];
-        int32_t dw = __hip_atomic_load(&d[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (w < 0 || w >= np) {
+          raise_flag(flags, kFlagBadArc);
+          continue;
+        }
+        int32_t dw = coherent_load(&d[w]);
         if (dw < 0) {
           const int32_t old = atomicCAS(&d[w], -1, L + 1);
           if (old == -1) {
             const int pos = atomicAdd(&s_cnt[L % 3], 1);
-            q[qe + pos] = w;
+            if (qe + pos < np) q[qe + pos] = w;
+            else raise_flag(flags, kFlagQueueOverflow);
             dw = L + 1;
           } else {
             dw = old;
@@ -130,7 +163,7 @@ __device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, con
       }
     }
     __syncthreads();
-    const int nt = qe + s_cnt[L % 3];
+    const int nt = min(qe + s_cnt[L % 3], np);
     if (nt == qe) break;
     qs = qe;
     qe = nt;
@@ -139,8 +172,8 @@ __device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, con
   }
   if (dbg.dist) {
     for (int v = tid; v < np; v += BLOCK) {
-      dbg.dist[v] = d[v];
-      dbg.sigma[v] = sig[v];
+      dbg.dist[v] = coherent_load(&d[v]);
+      dbg.sigma[v] = coherent_load(&sig[v]);
     }
     __syncthreads();
   }
@@ -149,18 +182,25 @@ __device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, con
     const int b = lvl[l], e = lvl[l + 1];
     for (int i = b + tid; i < e; i += BLOCK) {
       const int32_t v = q[i];
-      double acc = 0.0;
-      const int32_t e1 = rowp[v + 1];
-      for (int32_t x = rowp[v]; x < e1; ++x) {
-        const int32_t w = col[x];
-        if (d[w] == l + 1) acc += sig[w];
+      int32_t e0, e1;
+      if (v < 0 || v >= np) {
+        raise_flag(flags, kFlagBadArc);
+        continue;
       }
-      const double sv = sig[v];
+      if (!row_bounds(rowp, v, narcs, &e0, &e1, flags)) continue;
+      double acc = 0.0;
+      for (int32_t x = e0; x < e1; ++x) {
+        const int32_t w = col[x];
+        if (w < 0 || w >= np) continue;  // flagged in the forward sweep
+        // sig[w] now holds w's coefficient; the line may have held atomics' results
+        if (coherent_load(&d[w]) == l + 1) acc += coherent_load(&sig[w]);
+      }
+      const double sv = coherent_load(&sig[v]);
       const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
       const double coef = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
       sig[v] = coef;
       atomicAdd(&bcp[v], wsrc * dv);
-      if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, 1);
+      if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, kFlagSigmaOverflow);
       if (dbg.delta) dbg.delta[v] = dv;
     }
     __syncthreads();
@@ -168,15 +208,40 @@ __device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, con
   // Restore the untouched state (-1 / 0) for the next source.
   for (int i = tid; i < qe; i += BLOCK) {
     const int32_t v = q[i];
+    if (v < 0 || v >= np) continue;
     d[v] = -1;
     sig[v] = 0.0;
   }
   __syncthreads();
 }
 
+// Checks shared by the persistent kernels: the item, its piece and its
+// source range.  All values are read by every thread from the same address,
+// so the verdict is uniform across the workgroup.
+__device__ __forceinline__ bool item_ok(const DevPieces& P, const QueueArgs& Q, const WorkItem& W, int64_t cap,
+                                        int32_t* vb, int32_t* np) {
+  if (W.piece < 0 || W.piece >= P.npieces) {
+    if (threadIdx.x == 0) raise_flag(Q.flags, kFlagBadItem);
+    return false;
+  }
+  const int32_t b = P.vtx_off[W.piece], e = P.vtx_off[W.piece + 1];
+  if (b < 0 || e < b || e > P.nverts || (int64_t)(e - b) > cap) {
+    if (threadIdx.x == 0) raise_flag(Q.flags, kFlagBadPiece);
+    return false;
+  }
+  if (W.s0 < 0 || W.s1 < W.s0 || W.s1 > e - b) {
+    if (threadIdx.x == 0) raise_flag(Q.flags, kFlagBadItem);
+    return false;
+  }
+  *vb = b;
+  *np = e - b;
+  return true;
+}
+
 template <int BLOCK, bool REACH, bool IDENT, bool LDS>
 __global__ __launch_bounds__(BLOCK) void wg_kernel(DevPieces P, QueueArgs Q, WgState st, int32_t max_np,
                                                    DebugOut dbg) {
+  if (Q.magic != kArgMagic) return;
   SBC_DYNAMIC_LDS(dyn);
   __shared__ int s_item;
   __shared__ int s_cnt[3];
@@ -195,29 +260,36 @@ __global__ __launch_bounds__(BLOCK) void wg_kernel(DevPieces P, QueueArgs Q, WgS
     q = st.q + b * st.stride;
     lvl = st.lvl + b * (st.stride + 2);
   }
+  const int64_t cap = LDS ? (int64_t)max_np : st.stride;
   while (true) {
     if (tid == 0) s_item = atomicAdd(Q.head, 1);
     __syncthreads();
     const int it = s_item;
     __syncthreads();
-    if (it >= Q.nitems) break;
+    if (it < 0 || it >= Q.nitems) break;
     const WorkItem W = Q.items[it];
-    const int32_t vb = P.vtx_off[W.piece];
-    const int32_t np = P.vtx_off[W.piece + 1] - vb;
-    const int32_t* rowp = P.row + vb;
-    const int32_t* rch = REACH ? P.reach + vb : nullptr;
-    const int32_t* idn = IDENT ? P.ident + vb : nullptr;
-    double* bcp = P.bcp + vb;
-    if constexpr (LDS) {
-      for (int v = tid; v < np; v += BLOCK) {
-        d[v] = -1;
-        sig[v] = 0.0;
+    int32_t vb, np;
+    if (item_ok(P, Q, W, cap, &vb, &np)) {
+      const int32_t* rowp = P.row + vb;
+      const int32_t* rch = REACH ? P.reach + vb : nullptr;
+      const int32_t* idn = IDENT ? P.ident + vb : nullptr;
+      double* bcp = P.bcp + vb;
+      if constexpr (LDS) {
+        for (int v = tid; v < np; v += BLOCK) {
+          d[v] = -1;
+          sig[v] = 0.0;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-    }
-    for (int32_t k = W.s0; k < W.s1; ++k) {
-      const int32_t s = P.src_order[vb + k];
-      one_source<BLOCK, REACH, IDENT>(rowp, P.col, rch, idn, np, s, d, sig, q, lvl, s_cnt, bcp, Q.flags, dbg);
+      for (int32_t k = W.s0; k < W.s1; ++k) {
+        const int32_t s = P.src_order[vb + k];
+        if (s < 0 || s >= np) {
+          if (tid == 0) raise_flag(Q.flags, kFlagBadSource);
+          continue;
+        }
+        one_source<BLOCK, REACH, IDENT>(rowp, P.col, P.narcs, rch, idn, np, s, d, sig, q, lvl, s_cnt, bcp, Q.flags,
+                                        dbg);
+      }
     }
     if (tid == 0) atomicAdd(Q.done, 1);
   }
@@ -241,10 +313,10 @@ constexpr int kHeavyMax = kMsHeavyMax;   // split rows per level
 
 // Sum over the neighbours c of a vertex (arcs [e0, e1)) of sg[c*64+lane] for
 // the lanes in need & mk[c] (scaled by ident[c] when `scale` is set).
-__device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int32_t e0, int32_t e1,
-                                           const uint64_t* __restrict__ mk, const uint64_t need,
+__device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int32_t e0, int32_t e1, int32_t np,
+                                           uint64_t* __restrict__ mk, const uint64_t need,
                                            const double* __restrict__ sg, const int32_t* __restrict__ idn,
-                                           const bool scale, const int lane) {
+                                           const bool scale, const int lane, int32_t* flags) {
   double acc = 0.0;
   for (int32_t eb = e0; eb < e1; eb += 64) {
     const int32_t e = eb + lane;
@@ -252,7 +324,12 @@ __device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int3
     uint64_t m = 0;
     if (e < e1) {
       c = col[e];
-      m = mk[c] & need;
+      if (c >= 0 && c < np) {
+        m = coherent_load(&mk[c]) & need;
+      } else {
+        raise_flag(flags, kFlagBadArc);
+        c = 0;
+      }
     }
     uint64_t act = __ballot(m != 0);
     while (act) {
@@ -270,8 +347,25 @@ __device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int3
   return acc;
 }
 
+// Row bounds for a wave-uniform vertex; false (flagged once) when out of range.
+__device__ __forceinline__ bool wave_row(const int32_t* __restrict__ rowp, int32_t v, int32_t np, int32_t narcs,
+                                         int32_t* e0, int32_t* e1, int32_t* flags, int lane) {
+  if (v < 0 || v >= np) {
+    if (lane == 0) raise_flag(flags, kFlagBadArc);
+    return false;
+  }
+  *e0 = rowp[v];
+  *e1 = rowp[v + 1];
+  if (*e0 < 0 || *e1 < *e0 || *e1 > narcs) {
+    if (lane == 0) raise_flag(flags, kFlagBadArc);
+    return false;
+  }
+  return true;
+}
+
 template <int WAVES, bool REACH, bool IDENT>
 __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q, MsState st) {
+  if (Q.magic != kArgMagic) return;
   constexpr int BLOCK = WAVES * 64;
   __shared__ int s_item;
   __shared__ int s_cnt[3];
@@ -296,15 +390,24 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
   int32_t* lvl = st.lvl + slot * (size_t)(st.stride + 3);
   double* part = st.part + slot * (size_t)st.part_cap * 64;
   const int64_t qcap = st.stride * 64;
+  const int32_t narcs = P.narcs;
 
   while (true) {
     if (tid == 0) s_item = atomicAdd(Q.head, 1);
     __syncthreads();
     const int it = s_item;
     __syncthreads();
-    if (it >= Q.nitems) break;
+    if (it < 0 || it >= Q.nitems) break;
     const WorkItem W = Q.items[it];
-    const int32_t vb = P.vtx_off[W.piece];
+    int32_t vb, np;
+    const bool item_good = item_ok(P, Q, W, st.stride, &vb, &np) && W.s1 - W.s0 >= 1 && W.s1 - W.s0 <= 64;
+    if (!item_good) {
+      if (tid == 0) {
+        raise_flag(Q.flags, kFlagBadItem);
+        atomicAdd(Q.done, 1);
+      }
+      continue;
+    }
     const int32_t* rowp = P.row + vb;
     const int32_t* col = P.col;
     const int32_t* rch = REACH ? P.reach + vb : nullptr;
@@ -313,9 +416,17 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
     const int nsrc = W.s1 - W.s0;  // 1..64
 
     // Lane j runs source src_order[vb + s0 + j].
+    int32_t s = -1;
+    if (lane < nsrc) s = P.src_order[vb + W.s0 + lane];
+    if (__ballot(lane < nsrc && (s < 0 || s >= np)) != 0) {  // same verdict in every wave
+      if (tid == 0) {
+        raise_flag(Q.flags, kFlagBadSource);
+        atomicAdd(Q.done, 1);
+      }
+      continue;
+    }
     double wsrc = 0.0;
     if (lane < nsrc) {
-      const int32_t s = P.src_order[vb + W.s0 + lane];
       wsrc = 1.0;
       if (REACH) wsrc *= (double)rch[s];
       if (IDENT) wsrc *= (double)idn[s];
@@ -337,7 +448,6 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
     uint64_t* fcur = bufa;
     uint64_t* fnxt = bufb;
     int qs = 0, qe = nsrc, L = 0;
-    bool ok = true;
     // ---------------- forward sweep ----------------
     while (true) {
       if (tid == 0) {
@@ -353,9 +463,19 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
         uint64_t fu = 0;
         if (i < qe) {
           const int32_t u = q[i];
-          e0 = rowp[u];
-          deg = rowp[u + 1] - e0;
-          fu = qm[i];
+          if (u >= 0 && u < np) {
+            e0 = rowp[u];
+            const int32_t e1 = rowp[u + 1];
+            if (e0 >= 0 && e1 >= e0 && e1 <= narcs) {
+              deg = e1 - e0;
+              fu = qm[i];
+            } else {
+              raise_flag(Q.flags, kFlagBadArc);
+              e0 = 0;
+            }
+          } else {
+            raise_flag(Q.flags, kFlagBadArc);
+          }
         }
         int total;
         const int ex = block_excl_scan<BLOCK>(deg, s_wtot, &total);
@@ -372,31 +492,32 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
             else hi = mid - 1;
           }
           const int32_t w = col[s_e0[lo] + (t - s_scan[lo])];
+          if (w < 0 || w >= np) {
+            raise_flag(Q.flags, kFlagBadArc);
+            continue;
+          }
           const uint64_t nw = s_f[lo] & ~vis[w];
           if (nw) {
             const uint64_t old = atomicOr((unsigned long long*)&fnxt[w], (unsigned long long)nw);
             if (old == 0) {
               const int pos = atomicAdd(&s_cnt[L % 3], 1);
               if (qe + pos < qcap) q[qe + pos] = w;
-              else raise_flag(Q.flags, 4);
+              else raise_flag(Q.flags, kFlagQueueOverflow);
             }
           }
         }
         __syncthreads();
       }
-      int nt = qe + s_cnt[L % 3];
-      if (nt > qcap) {
-        nt = (int)qcap;
-        ok = false;
-      }
-      if (nt == qe || !ok) break;
+      const int nt = (int)min((int64_t)(qe + s_cnt[L % 3]), qcap);
+      if (nt == qe) break;
       // Phase B: sigma of the new lanes, one wave per vertex, pulling from the
       // neighbours on level L (their frontier masks); long rows are deferred.
       const bool scale = IDENT && L > 0;
       for (int i = qe + wave; i < nt; i += WAVES) {
         const int32_t w = q[i];
-        const uint64_t need = fnxt[w];
-        const int32_t e0 = rowp[w], e1 = rowp[w + 1];
+        int32_t e0, e1;
+        if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+        const uint64_t need = coherent_load(&fnxt[w]);  // built with atomicOr
         if (e1 - e0 > kHubArcs) {
           int reg = 0;
           if (lane == 0) {
@@ -413,7 +534,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           }
           if (__builtin_amdgcn_readfirstlane(reg)) continue;
         }
-        const double acc = pull_row(col, e0, e1, fcur, need, sg, idn, scale, lane);
+        const double acc = pull_row(col, e0, e1, np, fcur, need, sg, idn, scale, lane, Q.flags);
         if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
         if (lane == 0) {
           vis[w] |= need;
@@ -427,13 +548,15 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           const int i = s_heavy[h];
           if (i < 0) continue;
           const int32_t w = q[i];
-          const uint64_t need = fnxt[w];
-          const int32_t e0 = rowp[w], e1 = rowp[w + 1];
+          int32_t e0, e1;
+          if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t need = coherent_load(&fnxt[w]);
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
           for (int sl = wave; sl < ns; sl += WAVES) {
             const int32_t a = e0 + sl * kSliceArcs;
             const int32_t b = min(e1, a + kSliceArcs);
-            part[(size_t)(s_hoff[h] + sl) * 64 + lane] = pull_row(col, a, b, fcur, need, sg, idn, scale, lane);
+            part[(size_t)(s_hoff[h] + sl) * 64 + lane] =
+                pull_row(col, a, b, np, fcur, need, sg, idn, scale, lane, Q.flags);
           }
         }
         __syncthreads();
@@ -441,8 +564,9 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           const int i = s_heavy[h];
           if (i < 0) continue;
           const int32_t w = q[i];
-          const uint64_t need = fnxt[w];
-          const int32_t e0 = rowp[w], e1 = rowp[w + 1];
+          int32_t e0, e1;
+          if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t need = coherent_load(&fnxt[w]);
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
@@ -455,7 +579,10 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
         __syncthreads();
       }
       // Phase C: retire level L's frontier masks; level L+1 becomes current.
-      for (int i = qs + tid; i < qe; i += BLOCK) fcur[q[i]] = 0;
+      for (int i = qs + tid; i < qe; i += BLOCK) {
+        const int32_t u = q[i];
+        if (u >= 0 && u < np) fcur[u] = 0;
+      }
       if (tid == 0) lvl[L + 2] = nt;
       __syncthreads();
       uint64_t* t = fcur;
@@ -465,45 +592,95 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
       qe = nt;
       ++L;
     }
-    for (int i = qs + tid; i < qe; i += BLOCK) fcur[q[i]] = 0;
+    for (int i = qs + tid; i < qe; i += BLOCK) {
+      const int32_t u = q[i];
+      if (u >= 0 && u < np) fcur[u] = 0;
+    }
     __syncthreads();
     const int total = qe;
     const int Lmax = L;
 
     // ---------------- backward sweep ----------------
-    if (ok) {
-      for (int l = Lmax; l >= 1; --l) {
-        uint64_t* bw = (l & 1) ? bmo : bme;  // masks of level l, written now
-        uint64_t* br = (l & 1) ? bme : bmo;  // masks of level l+1, read now
-        if (l + 2 <= Lmax)
-          for (int i = lvl[l + 2] + tid; i < lvl[l + 3]; i += BLOCK) bw[q[i]] = 0;
-        if (tid == 0) {
-          s_nheavy = 0;
-          s_nslices = 0;
+    for (int l = Lmax; l >= 1; --l) {
+      uint64_t* bw = (l & 1) ? bmo : bme;  // masks of level l, written now
+      uint64_t* br = (l & 1) ? bme : bmo;  // masks of level l+1, read now
+      if (l + 2 <= Lmax)
+        for (int i = lvl[l + 2] + tid; i < lvl[l + 3]; i += BLOCK) {
+          const int32_t u = q[i];
+          if (u >= 0 && u < np) bw[u] = 0;
+        }
+      if (tid == 0) {
+        s_nheavy = 0;
+        s_nslices = 0;
+      }
+      __syncthreads();
+      const int b = lvl[l], e = lvl[l + 1];
+      for (int i = b + wave; i < e; i += WAVES) {
+        const int32_t v = q[i];
+        int32_t e0, e1;
+        if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+        const uint64_t amask = qm[i];
+        if (e1 - e0 > kHubArcs) {
+          int reg = 0;
+          if (lane == 0) {
+            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+            const int h = atomicAdd(&s_nheavy, 1);
+            const int o = atomicAdd(&s_nslices, ns);
+            if (h < kHeavyMax && o + ns <= st.part_cap) {
+              s_heavy[h] = i;
+              s_hoff[h] = o;
+              reg = 1;
+            } else if (h < kHeavyMax) {
+              s_heavy[h] = -1;
+            }
+          }
+          if (__builtin_amdgcn_readfirstlane(reg)) continue;
+        }
+        const double acc = pull_row(col, e0, e1, np, br, amask, sg, idn, false, lane, Q.flags);
+        double contrib = 0.0;
+        if ((amask >> lane) & 1) {
+          const size_t at = (size_t)v * 64 + lane;
+          const double sv = sg[at];
+          const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+          sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+          contrib = wsrc * dv;
+          if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+        }
+        contrib = wave_sum(contrib);
+        if (lane == 0) {
+          atomicAdd(&bcp[v], contrib);
+          bw[v] = amask;
+        }
+      }
+      __syncthreads();
+      const int nh = min(s_nheavy, kHeavyMax);
+      if (nh > 0) {
+        for (int h = 0; h < nh; ++h) {
+          const int i = s_heavy[h];
+          if (i < 0) continue;
+          const int32_t v = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t amask = qm[i];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          for (int sl = wave; sl < ns; sl += WAVES) {
+            const int32_t a = e0 + sl * kSliceArcs;
+            const int32_t bnd = min(e1, a + kSliceArcs);
+            part[(size_t)(s_hoff[h] + sl) * 64 + lane] =
+                pull_row(col, a, bnd, np, br, amask, sg, idn, false, lane, Q.flags);
+          }
         }
         __syncthreads();
-        const int b = lvl[l], e = lvl[l + 1];
-        for (int i = b + wave; i < e; i += WAVES) {
+        for (int h = wave; h < nh; h += WAVES) {
+          const int i = s_heavy[h];
+          if (i < 0) continue;
           const int32_t v = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
           const uint64_t amask = qm[i];
-          const int32_t e0 = rowp[v], e1 = rowp[v + 1];
-          if (e1 - e0 > kHubArcs) {
-            int reg = 0;
-            if (lane == 0) {
-              const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-              const int h = atomicAdd(&s_nheavy, 1);
-              const int o = atomicAdd(&s_nslices, ns);
-              if (h < kHeavyMax && o + ns <= st.part_cap) {
-                s_heavy[h] = i;
-                s_hoff[h] = o;
-                reg = 1;
-              } else if (h < kHeavyMax) {
-                s_heavy[h] = -1;
-              }
-            }
-            if (__builtin_amdgcn_readfirstlane(reg)) continue;
-          }
-          const double acc = pull_row(col, e0, e1, br, amask, sg, idn, false, lane);
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          double acc = 0.0;
+          for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
           double contrib = 0.0;
           if ((amask >> lane) & 1) {
             const size_t at = (size_t)v * 64 + lane;
@@ -511,7 +688,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
             const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
             sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
             contrib = wsrc * dv;
-            if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, 1);
+            if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
           }
           contrib = wave_sum(contrib);
           if (lane == 0) {
@@ -520,80 +697,37 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           }
         }
         __syncthreads();
-        const int nh = min(s_nheavy, kHeavyMax);
-        if (nh > 0) {
-          for (int h = 0; h < nh; ++h) {
-            const int i = s_heavy[h];
-            if (i < 0) continue;
-            const int32_t v = q[i];
-            const uint64_t amask = qm[i];
-            const int32_t e0 = rowp[v], e1 = rowp[v + 1];
-            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-            for (int sl = wave; sl < ns; sl += WAVES) {
-              const int32_t a = e0 + sl * kSliceArcs;
-              const int32_t bnd = min(e1, a + kSliceArcs);
-              part[(size_t)(s_hoff[h] + sl) * 64 + lane] = pull_row(col, a, bnd, br, amask, sg, idn, false, lane);
-            }
-          }
-          __syncthreads();
-          for (int h = wave; h < nh; h += WAVES) {
-            const int i = s_heavy[h];
-            if (i < 0) continue;
-            const int32_t v = q[i];
-            const uint64_t amask = qm[i];
-            const int32_t e0 = rowp[v], e1 = rowp[v + 1];
-            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-            double acc = 0.0;
-            for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
-            double contrib = 0.0;
-            if ((amask >> lane) & 1) {
-              const size_t at = (size_t)v * 64 + lane;
-              const double sv = sg[at];
-              const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-              sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-              contrib = wsrc * dv;
-              if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, 1);
-            }
-            contrib = wave_sum(contrib);
-            if (lane == 0) {
-              atomicAdd(&bcp[v], contrib);
-              bw[v] = amask;
-            }
-          }
-          __syncthreads();
-        }
       }
     }
     // Restore the slot: clear the backward masks of the two lowest levels and
     // the visit masks of every entry.
     for (int l = 1; l <= 2 && l <= Lmax; ++l) {
       uint64_t* bw = (l & 1) ? bmo : bme;
-      for (int i = lvl[l] + tid; i < lvl[l + 1]; i += BLOCK) bw[q[i]] = 0;
-    }
-    if (!ok) {
-      // a failed batch may have left masks anywhere its queue reached
-      for (int i = tid; i < total; i += BLOCK) {
-        const int32_t v = q[i];
-        bme[v] = 0;
-        bmo[v] = 0;
-        bufa[v] = 0;
-        bufb[v] = 0;
+      for (int i = lvl[l] + tid; i < lvl[l + 1]; i += BLOCK) {
+        const int32_t u = q[i];
+        if (u >= 0 && u < np) bw[u] = 0;
       }
     }
-    for (int i = tid; i < total; i += BLOCK) vis[q[i]] = 0;
+    for (int i = tid; i < total; i += BLOCK) {
+      const int32_t u = q[i];
+      if (u >= 0 && u < np) vis[u] = 0;
+    }
     __syncthreads();
     if (tid == 0) atomicAdd(Q.done, 1);
   }
 }
 
-__global__ void mapback_kernel(int32_t n, const int32_t* __restrict__ map_off, const int32_t* __restrict__ map_idx,
-                               const double* __restrict__ bcp, const double* __restrict__ corr,
-                               const double* __restrict__ bcx, double scale, double* __restrict__ out) {
+__global__ void mapback_kernel(int32_t n, int32_t nverts, int32_t nmap, const int32_t* __restrict__ map_off,
+                               const int32_t* __restrict__ map_idx, const double* __restrict__ bcp,
+                               const double* __restrict__ corr, const double* __restrict__ bcx, double scale,
+                               double* __restrict__ out) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   double acc = bcx ? bcx[v] : 0.0;
-  for (int32_t j = map_off[v]; j < map_off[v + 1]; ++j) {
+  const int32_t j0 = max(map_off[v], 0), j1 = min(map_off[v + 1], nmap);
+  for (int32_t j = j0; j < j1; ++j) {
     const int32_t x = map_idx[j];
+    if (x < 0 || x >= nverts) continue;
     acc += bcp[x] + (corr ? corr[x] : 0.0);
   }
   out[v] = acc * scale;

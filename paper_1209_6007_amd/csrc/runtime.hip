@@ -110,6 +110,7 @@ size_t ms_slot_bytes(int64_t stride, int64_t part_cap) {
 size_t wg_slot_bytes(int64_t stride) { return (size_t)stride * 16 + (size_t)(stride + 2) * 4; }
 
 int classify(const Params& pr, int32_t np, bool plain, int force) {
+  if (!kPerSourceKernelsEnabled) return KC_BATCH;
   if (force == 1) return KC_GLOBAL;
   if (force == 2) return np <= pr.wave_max_vertices ? KC_WAVE : KC_LDS;
   if (force == 3) return KC_BATCH;
@@ -148,6 +149,8 @@ sbc_status Plan::build(sbc_context c, const Prepared& prob, uint32_t mode, const
 
 sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mode, const PlanOptions& opt) {
   ctx = c;
+  if (!kPerSourceKernelsEnabled && (opt.force_kernel == 1 || opt.force_kernel == 2 || opt.debug_single))
+    return fail(SBC_E_INVALID_ARG, "the one-source-per-workgroup kernels are switched off in this build");
   const Params& pr = c->params;
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -243,6 +246,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   if ((e = upload(d_src, prob.src_order)) != hipSuccess) return hip_fail(e, "upload src_order");
   if ((e = d_bcp.alloc(std::max<int64_t>(V, 1) * sizeof(double))) != hipSuccess) return hip_fail(e, "alloc bcp");
   has_map = !plain;
+  nmap = (int32_t)prob.map_idx.size();
   if ((e = upload(d_corr, prob.corr)) != hipSuccess) return hip_fail(e, "upload corr");
   if ((e = upload(d_bcx, prob.bcx)) != hipSuccess) return hip_fail(e, "upload bcx");
   if ((e = upload(d_map_off, prob.map_off)) != hipSuccess) return hip_fail(e, "upload map_off");
@@ -354,7 +358,7 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
   if ((e = launch_fill_f64(d_bcp.as<double>(), 0.0, V, s)) != hipSuccess) return hip_fail(e, "fill bcp");
   if ((e = launch_fill_i32(ctl, 0, 16, s)) != hipSuccess) return hip_fail(e, "fill ctl");
   DevPieces dp{d_vtx_off.as<int32_t>(), d_row.as<int32_t>(), d_col.as<int32_t>(), d_reach.as<int32_t>(),
-               d_ident.as<int32_t>(), d_src.as<int32_t>(), d_bcp.as<double>()};
+               d_ident.as<int32_t>(), d_src.as<int32_t>(), d_bcp.as<double>(), P, (int32_t)V, (int32_t)A, 0};
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
   // Largest classes first so the long multi-source items start early.
   const int order[KC_COUNT] = {KC_BATCH, KC_GLOBAL, KC_LDS, KC_WAVE};
@@ -363,7 +367,7 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
     hipStream_t ks = side[k];
     if ((e = hipStreamWaitEvent(ks, ev_fork, 0)) != hipSuccess) return hip_fail(e, "wait");
     if (!use_graph && (e = hipEventRecord(ev_kc_start[k], ks)) != hipSuccess) return hip_fail(e, "event");
-    QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], heads + k, flags, done + k};
+    QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], kArgMagic, heads + k, flags, done + k};
     if (k == KC_BATCH) {
       e = launch_ms(dp, qa, reach, ident, block[k] / 64, grid[k], ms, ks);
     } else {
@@ -377,11 +381,11 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
   if (!use_graph && (e = hipEventRecord(ev_trav, s)) != hipSuccess) return hip_fail(e, "event");
   double* dst = out ? out : d_out.as<double>();
   if (has_map) {
-    e = launch_mapback(n, d_map_off.as<int32_t>(), d_map_idx.as<int32_t>(), d_bcp.as<double>(),
+    e = launch_mapback(n, (int32_t)V, nmap, d_map_off.as<int32_t>(), d_map_idx.as<int32_t>(), d_bcp.as<double>(),
                        d_corr.as<double>(), d_bcx.as<double>(), scale, dst, s);
   } else {
-    e = launch_mapback(n, d_map_off.as<int32_t>(), d_map_idx.as<int32_t>(), d_bcp.as<double>(), nullptr, nullptr,
-                       scale, dst, s);
+    e = launch_mapback(n, (int32_t)V, nmap, d_map_off.as<int32_t>(), d_map_idx.as<int32_t>(), d_bcp.as<double>(), nullptr,
+                       nullptr, scale, dst, s);
   }
   if (e != hipSuccess) return hip_fail(e, "launch mapback");
   if ((e = hipMemcpyAsync(h_ctl, ctl, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -480,13 +484,15 @@ sbc_status Plan::sync(sbc_run_stats* st) {
       st->items_class[k] = nitems[k];
     }
   }
-  int32_t done_total = 0;
+  if (flags & kFlagRangeMask)
+    return fail(SBC_E_DEVICE, "device-side range check failed (flags " + std::to_string(flags) + ")");
+  if (flags & kFlagQueueOverflow) return fail(SBC_E_TOO_LARGE, "traversal queue overflow");
+  if (flags & kFlagSigmaOverflow) return fail(SBC_E_SIGMA_OVERFLOW, "a shortest-path count exceeded the binary64 range");  int32_t done_total = 0;
   for (int k = 0; k < KC_COUNT; ++k) done_total += h_ctl[4 + k];
   if (done_total != total_items)
     return fail(SBC_E_DEVICE, "work queue drained " + std::to_string(done_total) + " of " +
                                   std::to_string(total_items) + " items");
-  if (flags & 1) return fail(SBC_E_SIGMA_OVERFLOW, "a shortest-path count exceeded the binary64 range");
-  if (flags & 6) return fail(SBC_E_TOO_LARGE, "traversal state overflow");
+
   return SBC_OK;
 }
 

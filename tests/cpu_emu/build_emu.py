@@ -17,7 +17,7 @@ SOURCES = ["prep.cpp", "kernels.hip", "runtime.hip", "api.hip", "server.hip"]
 def build(asan: bool = True) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     flags = ["-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-fno-omit-frame-pointer",
-             "-Wno-unused-function", f"-I{HERE}", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+             "-Wno-unused-function", "-DSBC_ENABLE_PER_SOURCE_KERNELS=1", f"-I{HERE}", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
     if asan:
         flags.append("-fsanitize=address")
     srcs = []

@@ -185,7 +185,15 @@ inline int readlane(int v, int k) {
 
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0
 #define __HIP_MEMORY_SCOPE_AGENT 0
-#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_RELAXED)
+namespace sbc_emu {
+template <typename T>
+inline T atomic_load(T* p) {
+  T v;
+  __atomic_load(p, &v, __ATOMIC_RELAXED);
+  return v;
+}
+}  // namespace sbc_emu
+#define __hip_atomic_load(p, order, scope) sbc_emu::atomic_load(p)
 #define __hip_atomic_fetch_or(p, v, order, scope) __atomic_fetch_or((p), (v), __ATOMIC_RELAXED)
 
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }

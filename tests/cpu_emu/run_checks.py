@@ -74,9 +74,12 @@ def main(which):
                            ("rmat8", gg.rmat_decorated(scale=8, seed=3))]
             for name, g in graphs:
                 want = oracle.bc(g)
-                for mode in ("plain", "compressed"):
-                    got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=ctx)
-                    assert_bc_close(got, want, 1e-9, f"{name}/{mode}")
+                for batch_min in (4097, 2):  # default routing, then every piece on the batch kernel
+                    sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", batch_min)
+                    for mode in ("plain", "compressed"):
+                        got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=ctx)
+                        assert_bc_close(got, want, 1e-9, f"{name}/{mode}/batch_min={batch_min}")
+                sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", 4097)
                 print(f"   {name} n={g.n} ok", flush=True)
         check("whole graphs", whole)
     if "hubs" in which:
