@@ -137,7 +137,8 @@ sbc_status sbc_context_get_param(sbc_context ctx, const char* key, int64_t* valu
 
 sbc_status sbc_context_device_name(sbc_context ctx, char* buf, size_t len) {
   if (!ctx || !buf || len == 0) return fail(SBC_E_INVALID_ARG, "NULL argument");
-  std::strncpy(buf, ctx->prop.name, len - 1);
+  const char* nm = ctx->prop.name[0] ? ctx->prop.name : ctx->prop.gcnArchName;
+  std::strncpy(buf, nm, len - 1);
   buf[len - 1] = 0;
   return SBC_OK;
 }

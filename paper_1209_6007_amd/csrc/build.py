@@ -71,7 +71,23 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, OUT)
+    build_c_tests(hipcc)
     return OUT
+
+
+C_TESTS = [("tests/c_api/device_path.cpp", "tests/c_api/device_path")]
+
+
+def build_c_tests(hipcc: str) -> None:
+    """Small C++ consumers of the public header, linked against the library."""
+    for src, exe in C_TESTS:
+        s = os.path.join(ROOT, src)
+        if not os.path.exists(s):
+            continue
+        out = os.path.join(ROOT, exe)
+        _run([hipcc, f"--offload-arch={ARCH}", "-O2", "-std=c++17", f"-I{INCLUDE}", s, "-o", out + ".tmp",
+              f"-L{PKG}", "-lshatterbc", f"-Wl,-rpath,{PKG}", "-Wl,-rpath,$ORIGIN/../../paper_1209_6007_amd"])
+        os.replace(out + ".tmp", out)
 
 
 if __name__ == "__main__":

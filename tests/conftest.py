@@ -8,15 +8,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-# Load the HIP library before torch: it then binds to the ROCm runtime it was
-# built against instead of the older copy bundled with torch (both carry the
-# same soname, and the first one loaded serves the whole process).
+# The GPU tests talk to the library only (no torch in this process): the
+# library binds the ROCm runtime it was built against, and torch, which
+# bundles an older copy of the same libraries, would otherwise mix the two.
+_LIB_OK = False
+_HAVE_GPU = False
 try:
     import paper_1209_6007_amd as _sbc
 
     _sbc.lib()
-except Exception:  # pragma: no cover - a missing build is reported by the tests themselves
-    pass
+    _LIB_OK = True
+    try:
+        _c = _sbc.Context(0)
+        _c.close()
+        _HAVE_GPU = True
+    except Exception:
+        _HAVE_GPU = False
+except Exception:  # a missing build: GPU tests then fail loudly instead of being skipped
+    _LIB_OK = False
 
 
 def pytest_configure(config):
@@ -25,14 +34,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests are selected with -m gpu; without a visible GPU they are skipped
-    # rather than failing, so `-m "not gpu"` and a bare run both work on CPU.
-    try:
-        import torch
-        have_gpu = torch.cuda.is_available()
-    except Exception:  # pragma: no cover
-        have_gpu = False
-    if have_gpu:
+    if _HAVE_GPU or not _LIB_OK:
         return
     skip = pytest.mark.skip(reason="no GPU visible")
     for it in items:
