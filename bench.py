@@ -29,9 +29,9 @@ import graphgen as gg  # noqa: E402
 
 METRIC = "exact-BC GTEPS (sources×edges/s) + HBM roofline %, compressed-batched vs plain"
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["wave_lds", "wg_lds", "batch64", "wg_global"]
-KERNEL_SYMBOLS = {0: "wg_kernel<64,*,*,LDS>", 1: "wg_kernel<256,*,*,LDS>", 2: "ms_kernel<WAVES,*,*>",
-                  3: "wg_kernel<256,*,*,global>"}
+CLASS_NAMES = ["wave_lds", "wg_lds", "batch64", "wg_global", "team64"]
+KERNEL_SYMBOLS = {0: "wg_kernel<64,*,*,LDS>", 1: "wg_kernel<256,*,*,LDS>", 2: "ms_kernel<WAVES,EU,*,*>",
+                  3: "wg_kernel<256,*,*,global>", 4: "ms_team_kernel<WAVES,EU,*,*>"}
 
 WORKLOADS = {
     "rmat17": ("R-MAT scale 17 (131,072 labels), edge factor 8, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "
@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--param", action="append", default=[], help="key=value tuning knob")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--phases", action="store_true", help="one extra compressed run with in-kernel phase timers")
+    ap.add_argument("--calibrate", action="store_true", help="also time a plain streaming copy (1 GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split of the work items is "
@@ -195,6 +197,18 @@ def main():
                         if lp["ms_class"][kp] > 0 else 0.0}
         out["compressed_vs_plain"] = {"speedup": t_p / t_c, "max_rel_diff": rel,
                                       "zero_mismatch": int(np.sum((res_p == 0) != (res_c == 0)))}
+    if args.calibrate:
+        cb = sbc.sbc_copy_bandwidth(ctx.h, 1 << 30, 10)
+        out["roofline"]["copy_kernel_gbs"] = cb
+        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cb if cb > 0 else None
+    if args.phases:
+        pctx = sbc.Context(0, dict(params, profile_phases=1))
+        plan = sbc.sbc_plan_create(pctx.h, G.h, sbc.SBC_COMPRESSED)
+        sbc.sbc_plan_execute(plan)
+        pst = sbc.sbc_plan_sync(plan)
+        out["phases"] = dict(sbc.sbc_plan_phase_profile(plan), kernel_ms=pst["ms_traverse"])
+        sbc.sbc_plan_destroy(plan)
+        pctx.close()
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds, threads)

@@ -86,19 +86,20 @@ typedef struct {
   double teps;               /* sources x edges traversed, summed over pieces */
   double algo_bytes;         /* streaming-model bytes: per (source, piece) 8*arcs + 56*vertices */
   int64_t items;             /* work items drained from the device queue */
-  int64_t batched_sources;   /* sources run by the 64-lane multi-source kernel */
+  int64_t batched_sources;   /* sources run by the 64-lane multi-source kernels (batch and team) */
   int64_t lds_sources;       /* sources run by the LDS-resident kernel */
   int64_t global_sources;    /* sources run by the one-source-per-workgroup global kernel */
   int32_t overflow;          /* nonzero if a path count overflowed */
   /* Per traversal kernel class: 0 one source per wavefront (LDS), 1 one source
-   * per workgroup (LDS), 2 64-source batches, 3 one source per workgroup
-   * (global memory).  Device time of the class's persistent launch, its
-   * streaming-model bytes, and its sources x edges. */
-  double ms_class[4];
-  double bytes_class[4];
-  double teps_class[4];
-  int32_t grid_class[4];      /* resident workgroups of the launch */
-  int32_t items_class[4];     /* work items of the launch */
+   * per workgroup (LDS), 2 64-source batches (one workgroup per batch), 3 one
+   * source per workgroup (global memory), 4 64-source batches run by teams of
+   * workgroups (one team per XCD).  Device time of the class's persistent
+   * launch, its streaming-model bytes, and its sources x edges. */
+  double ms_class[5];
+  double bytes_class[5];
+  double teps_class[5];
+  int32_t grid_class[5];      /* resident workgroups of the launch */
+  int32_t items_class[5];     /* work items of the launch */
 } sbc_run_stats;
 
 const char* sbc_status_string(sbc_status s);
@@ -118,11 +119,23 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "lds_max_vertices"   largest piece run by the LDS-resident kernel
  *   "wave_max_vertices"  largest piece run one-source-per-wavefront in LDS
  *   "batch_min_vertices" smallest piece run by the 64-lane multi-source kernel
- *   "batch_wg_waves"     wavefronts per workgroup of the multi-source kernel
+ *   "batch_wg_waves"     wavefronts per workgroup of the multi-source kernel (4, 8, 16)
+ *   "batch_waves_per_eu" occupancy target of the multi-source kernel: 0 (compiler default), 6 or 8 waves per SIMD
  *   "slots"              resident workgroups per traversal kernel (0 = auto)
  *   "cluster_sources"    1: order batch sources by breadth-first balls
  *   "plain_kernel"       plain mode: 0 automatic, 1 one source per workgroup
  *   "mem_budget_mb"      traversal-state budget of a plan (0: 60% of free memory)
+ *   "profile_phases"     1: plans keep per-phase timers of the batch and team kernels
+ *   "order_plain"        1: plain plans run on the graph renumbered breadth-first
+ *                        from its highest-degree vertex (Section 4.1)
+ *   "team_min_vertices"  smallest piece run by the team kernel (0: never): all
+ *                        workgroups of one XCD share one 64-source batch
+ *   "team_count"         teams of the team kernel (default 8, one per XCD)
+ *   "team_waves_per_eu"  occupancy target of the team kernel: 0 or 8
+ *   "team_spin_ms"       bound of one team barrier wait; a longer wait aborts
+ *                        the launch with SBC_E_DEVICE instead of hanging
+ *                        (0: no waiting at all, which aborts any team of more
+ *                        than one workgroup: a test of the abort path)
  *   "lds_block", "lds_sources_per_item", "wave_sources_per_item"
  * Read-only (get only): "cus" compute units, "lds_limit_bytes" LDS per workgroup.
  * Errors: SBC_E_INVALID_ARG for an unknown key or out-of-range value. */
@@ -145,7 +158,9 @@ sbc_status sbc_graph_destroy(sbc_graph g);
 sbc_status sbc_graph_info(sbc_graph g, int32_t* n, int64_t* arcs);
 
 /* Shatter and compress (Section 3), host-only.  ops holds letters applied in
- * this order: 'd' degree-1 vertices (Section 3.3.1), 'a' articulation
+ * this order: 'o' orders each piece's vertices breadth-first from its
+ * highest-degree vertex (the ordering of Section 4.1, applied per piece after
+ * the other steps), 'd' degree-1 vertices (Section 3.3.1), 'a' articulation
  * vertices via biconnected components, bridges included ('b' is accepted as
  * the same step; Sections 3.2.1, 3.2.2, 3.4), 'i' identical vertices
  * (Section 3.3.3).  "" keeps every connected component whole.  st may be NULL.
@@ -188,6 +203,18 @@ sbc_status sbc_plan_execute(sbc_plan p, double* bc_dev, void* stream);
 sbc_status sbc_plan_sync(sbc_plan p, sbc_run_stats* st);
 /* Copy the plan's own result (n doubles) to host memory (waits). */
 sbc_status sbc_plan_result(sbc_plan p, double* bc_host);
+/* Phase timers of the last execution of the 64-source batch and team kernels, kept
+ * when the context parameter "profile_phases" was 1 at plan creation (the
+ * paper splits its times into a BFS phase and a back-propagation phase,
+ * Section 4.2).  out[0..7]: mean milliseconds per resident workgroup spent
+ * taking items, discovering the next level (forward), counting paths
+ * (forward), counting paths of split long rows, retiring frontiers, in the
+ * backward sweep, in split long rows of the backward sweep, and restoring
+ * state; out[8..10]: items, levels and (vertex, level) entries processed;
+ * out[11]: mean milliseconds per workgroup waiting at team barriers.
+ * count is the length of out (at most 12 values are written).
+ * Errors: SBC_E_INVALID_ARG if profiling was off for this plan. */
+sbc_status sbc_plan_phase_profile(sbc_plan p, double* out, int32_t count);
 /* Capture one execution into a HIP graph and replay it on later executes
  * (enable = 1) or go back to direct launches (enable = 0). */
 sbc_status sbc_plan_use_graph(sbc_plan p, int enable);
@@ -212,7 +239,8 @@ sbc_status sbc_betweenness_sources(sbc_context ctx, sbc_graph g, int64_t nsrc, c
  * where sigma counts paths through v != s with weight ident[v] and delta
  * starts at reach[v]-1.  reach/ident may be NULL (all ones).  `kernel` forces
  * one traversal kernel: 0 automatic, 1 one-source-per-workgroup in global
- * memory, 2 LDS-resident, 3 64-lane multi-source.
+ * memory, 2 LDS-resident, 3 64-lane multi-source, 4 64-lane multi-source run
+ * by teams of workgroups.
  * Errors: SBC_E_INVALID_ARG (shape, or a piece too large for the forced kernel). */
 sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
                         const int32_t* reach, const int32_t* ident, int kernel, double* bc_host,
@@ -223,6 +251,14 @@ sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, cons
 sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
                              const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist,
                              double* sigma, double* delta);
+
+/* Streaming copy of `bytes` (rounded down to 16) between two device buffers
+ * the library allocates, `reps` times after one warm-up: *gbps = (read +
+ * write bytes) / time.  It measures the bandwidth a plain streaming kernel
+ * reaches on this device, and gives a kernel of known traffic
+ * (copy_kernel) for scaling hardware byte counters.
+ * Errors: SBC_E_INVALID_ARG, SBC_E_OOM, SBC_E_DEVICE. */
+sbc_status sbc_copy_bandwidth(sbc_context ctx, size_t bytes, int reps, double* gbps);
 
 /* ---------------------------------------------------------------- serving */
 

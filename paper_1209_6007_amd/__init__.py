@@ -54,9 +54,9 @@ class RunStats(ctypes.Structure):
                 ("ms_host", ctypes.c_double), ("teps", ctypes.c_double), ("algo_bytes", ctypes.c_double),
                 ("items", ctypes.c_int64), ("batched_sources", ctypes.c_int64), ("lds_sources", ctypes.c_int64),
                 ("global_sources", ctypes.c_int64), ("overflow", ctypes.c_int32),
-                ("ms_class", ctypes.c_double * 4), ("bytes_class", ctypes.c_double * 4),
-                ("teps_class", ctypes.c_double * 4), ("grid_class", ctypes.c_int32 * 4),
-                ("items_class", ctypes.c_int32 * 4)]
+                ("ms_class", ctypes.c_double * 5), ("bytes_class", ctypes.c_double * 5),
+                ("teps_class", ctypes.c_double * 5), ("grid_class", ctypes.c_int32 * 5),
+                ("items_class", ctypes.c_int32 * 5)]
 
     def as_dict(self):
         out = {}
@@ -101,6 +101,7 @@ _SIGS = {
     "sbc_plan_sync": ([_vp, ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_plan_result": ([_vp, _f64p], ctypes.c_int32),
     "sbc_plan_use_graph": ([_vp, ctypes.c_int], ctypes.c_int32),
+    "sbc_plan_phase_profile": ([_vp, _f64p, ctypes.c_int32], ctypes.c_int32),
     "sbc_betweenness": ([_vp, _vp, ctypes.c_uint32, _f64p, ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_betweenness_device": ([_vp, _vp, ctypes.c_uint32, _vp, _vp, ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_betweenness_sources": ([_vp, _vp, ctypes.c_int64, _i32p, _f64p, ctypes.POINTER(RunStats)], ctypes.c_int32),
@@ -108,6 +109,7 @@ _SIGS = {
                       ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_single_source": ([_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p, _f64p, _f64p],
                           ctypes.c_int32),
+    "sbc_copy_bandwidth": ([_vp, ctypes.c_size_t, ctypes.c_int, _f64p], ctypes.c_int32),
     "sbc_server_create": ([_vp, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int32),
     "sbc_server_destroy": ([_vp], ctypes.c_int32),
     "sbc_server_submit": ([_vp, _vp, ctypes.c_uint32, ctypes.POINTER(_vp)], ctypes.c_int32),
@@ -261,6 +263,16 @@ def sbc_plan_result(plan, n: int) -> np.ndarray:
     return out[:n]
 
 
+PHASE_NAMES = ("fetch_ms", "fwd_discover_ms", "fwd_count_ms", "fwd_count_split_ms", "fwd_retire_ms",
+               "backward_ms", "backward_split_ms", "restore_ms", "items", "levels", "entries", "team_sync_ms")
+
+
+def sbc_plan_phase_profile(plan) -> dict:
+    out = np.zeros(len(PHASE_NAMES), np.float64)
+    _check(lib().sbc_plan_phase_profile(plan, out.ctypes.data_as(_f64p), len(PHASE_NAMES)))
+    return dict(zip(PHASE_NAMES, out.tolist()))
+
+
 def sbc_plan_use_graph(plan, enable: bool = True):
     _check(lib().sbc_plan_use_graph(plan, 1 if enable else 0))
 
@@ -312,6 +324,12 @@ def sbc_single_source(ctx, n, row_ptr, col, s: int, reach=None, ident=None):
     _check(lib().sbc_single_source(ctx, int(n), rpp, clp, rep, idp, int(s), dist.ctypes.data_as(_i32p),
                                    sig.ctypes.data_as(_f64p), dl.ctypes.data_as(_f64p)))
     return dist, sig, dl
+
+
+def sbc_copy_bandwidth(ctx, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    g = ctypes.c_double()
+    _check(lib().sbc_copy_bandwidth(ctx, int(nbytes), int(reps), ctypes.byref(g)))
+    return g.value
 
 
 def sbc_server_create(ctx, slots: int = 4, hbm_budget_bytes: int = 0):

@@ -73,6 +73,9 @@ sbc_status sbc_context_create(int device, sbc_context* out) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
       c->lds_limit = std::min<size_t>((size_t)lds, kMaxLdsBytes);
+    int wclk = 0;
+    if (hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, device) == hipSuccess && wclk > 0)
+      c->wall_khz = wclk;
     (void)hipGetLastError();  // leave no stale error behind for later launch checks
     *out = c.release();
     return SBC_OK;
@@ -90,6 +93,7 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "lds_max_vertices") return &p.lds_max_vertices;
   if (k == "batch_min_vertices") return &p.batch_min_vertices;
   if (k == "batch_wg_waves") return &p.batch_wg_waves;
+  if (k == "batch_waves_per_eu") return &p.batch_waves_per_eu;
   if (k == "lds_block") return &p.lds_block;
   if (k == "lds_sources_per_item") return &p.lds_sources_per_item;
   if (k == "wave_sources_per_item") return &p.wave_sources_per_item;
@@ -97,6 +101,12 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "cluster_sources") return &p.cluster_sources;
   if (k == "plain_kernel") return &p.plain_kernel;
   if (k == "mem_budget_mb") return &p.mem_budget_mb;
+  if (k == "profile_phases") return &p.profile_phases;
+  if (k == "order_plain") return &p.order_plain;
+  if (k == "team_min_vertices") return &p.team_min_vertices;
+  if (k == "team_count") return &p.team_count;
+  if (k == "team_waves_per_eu") return &p.team_waves_per_eu;
+  if (k == "team_spin_ms") return &p.team_spin_ms;
   return nullptr;
 }
 
@@ -108,6 +118,10 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   const std::string k(key);
   bool ok = value >= 0;
   if (k == "batch_wg_waves") ok = value == 4 || value == 8 || value == 16;
+  if (k == "batch_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
+  if (k == "team_waves_per_eu") ok = value == 0 || value == 8;
+  if (k == "team_count") ok = value >= 1 && value <= 64;
+  if (k == "team_spin_ms") ok = value <= 600000;
   if (k == "lds_block") ok = value == 64 || value == 256 || value == 512 || value == 1024;
   if (k == "lds_max_vertices") ok = value >= 1 && wg_lds_bytes((int32_t)value) <= ctx->lds_limit;
   if (k == "wave_max_vertices") ok = value >= 1 && value <= 1024;
@@ -234,7 +248,8 @@ sbc_status sbc_graph_export(sbc_graph g, int32_t* vtx_off, int32_t* row, int32_t
   return SBC_OK;
 }
 
-static sbc_status ensure_problem(sbc_graph g, uint32_t mode, Prepared* plain_storage, const Prepared** out) {
+static sbc_status ensure_problem(sbc_context ctx, sbc_graph g, uint32_t mode, Prepared* plain_storage,
+                                 const Prepared** out) {
   if (mode & SBC_COMPRESSED) {
     if (!g->prepared) {
       sbc_status rc = sbc_graph_preprocess(g, "dai", nullptr);
@@ -243,6 +258,7 @@ static sbc_status ensure_problem(sbc_graph g, uint32_t mode, Prepared* plain_sto
     *out = &g->prep;
   } else {
     plain_problem(g->g, plain_storage);
+    if (ctx->params.order_plain) order_pieces(plain_storage);
     *out = plain_storage;
   }
   return SBC_OK;
@@ -255,7 +271,7 @@ sbc_status sbc_plan_create(sbc_context ctx, sbc_graph g, uint32_t mode, sbc_plan
   SBC_TRY({
     Prepared plain;
     const Prepared* prob = nullptr;
-    sbc_status rc = ensure_problem(g, mode, &plain, &prob);
+    sbc_status rc = ensure_problem(ctx, g, mode, &plain, &prob);
     if (rc != SBC_OK) return rc;
     std::unique_ptr<sbc_plan_s> p(new sbc_plan_s());
     rc = p->plan.build(ctx, *prob, mode, PlanOptions());
@@ -293,11 +309,55 @@ sbc_status sbc_plan_result(sbc_plan p, double* bc_host) {
   return SBC_OK;
 }
 
+sbc_status sbc_plan_phase_profile(sbc_plan p, double* out, int32_t count) {
+  if (!p || !out || count < 0) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  const Plan& pl = p->plan;
+  if (pl.h_prof.empty()) return fail(SBC_E_INVALID_ARG, "the plan kept no phase timers");
+  const double slots = pl.prof_slots > 0 ? (double)pl.prof_slots : 1.0;
+  for (int32_t i = 0; i < count && i < kProfCounters; ++i) {
+    const double v = (double)pl.h_prof[i];
+    const bool is_time = i < kProfItems || i == kProfSync;
+    out[i] = is_time ? v / pl.ctx->wall_khz / slots : v;
+  }
+  return SBC_OK;
+}
+
 sbc_status sbc_plan_use_graph(sbc_plan p, int enable) {
   if (!p) return fail(SBC_E_INVALID_ARG, "plan is NULL");
   if (p->plan.ran) (void)hipEventSynchronize(p->plan.ev_end);
   p->plan.use_graph = enable != 0;
   return SBC_OK;
+}
+
+sbc_status sbc_copy_bandwidth(sbc_context ctx, size_t bytes, int reps, double* gbps) {
+  if (!ctx || !gbps || reps < 1 || bytes < 16) return fail(SBC_E_INVALID_ARG, "bad argument");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  bytes &= ~(size_t)15;
+  DevBuf a, b;
+  if ((e = a.alloc(bytes)) != hipSuccess || (e = b.alloc(bytes)) != hipSuccess) return hip_fail(e, "alloc");
+  hipStream_t s = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  sbc_status rc = SBC_OK;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  if ((e = hipEventCreate(&t0)) == hipSuccess && (e = hipEventCreate(&t1)) == hipSuccess) {
+    const int grid = ctx->cus * 8;
+    e = launch_fill_u64(a.as<uint64_t>(), 0x0123456789abcdefull, (int64_t)(bytes / 8), s);
+    if (e == hipSuccess) e = launch_copy(a.p, b.p, (int64_t)bytes, grid, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(t0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(a.p, b.p, (int64_t)bytes, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(t1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess) *gbps = ms > 0 ? 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
+  }
+  if (e != hipSuccess) rc = hip_fail(e, "copy bandwidth");
+  if (s) (void)hipStreamSynchronize(s);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (s) (void)hipStreamDestroy(s);
+  return rc;
 }
 
 sbc_status sbc_betweenness(sbc_context ctx, sbc_graph g, uint32_t mode, double* bc_host, sbc_run_stats* st) {
@@ -377,7 +437,7 @@ static sbc_status piece_problem(int32_t n, const int32_t* row_ptr, const int32_t
 sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* reach,
                         const int32_t* ident, int kernel, double* bc_host, sbc_run_stats* st) {
   if (!ctx || !bc_host) return fail(SBC_E_INVALID_ARG, "NULL argument");
-  if (kernel < 0 || kernel > 3) return fail(SBC_E_INVALID_ARG, "kernel must be 0..3");
+  if (kernel < 0 || kernel > 4) return fail(SBC_E_INVALID_ARG, "kernel must be 0..4");
   SBC_TRY({
     Prepared prob;
     sbc_status rc = piece_problem(n, row_ptr, col, reach, ident, &prob);

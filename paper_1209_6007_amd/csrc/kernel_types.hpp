@@ -19,6 +19,7 @@ constexpr int32_t kFlagBadItem = 8;         // work item index or source range o
 constexpr int32_t kFlagBadPiece = 16;       // piece offsets out of bounds or larger than the slot
 constexpr int32_t kFlagBadArc = 32;         // row bounds, neighbour id or queue entry out of range
 constexpr int32_t kFlagBadSource = 64;      // a source id outside its piece
+constexpr int32_t kFlagTeamTimeout = 128;   // a team barrier wait exceeded its bound (team aborted)
 constexpr int32_t kFlagRangeMask = kFlagBadItem | kFlagBadPiece | kFlagBadArc | kFlagBadSource;
 
 // Packed pieces in device memory.  Piece p owns global piece vertices
@@ -71,11 +72,55 @@ struct MsState {
   uint64_t* fa;    // [slots][stride]     frontier masks, double buffered
   uint64_t* fb;
   uint64_t* ba;    // [slots][stride]     backward level masks, by level parity
-  uint64_t* bb;
+  uint64_t* bb;    //                     (the team kernel rotates three: level mod 3)
+  uint64_t* bc;    //                     team kernel only
   int32_t* lvl;    // [slots][stride+3]   level starts in q
   double* part;    // [slots][part_cap*64] partial sums of split high-degree rows
+  uint64_t* prof;  // [slots][kProfCounters] phase timers, or null
   int64_t stride;
   int32_t part_cap;
+};
+
+// Per-slot phase timers of the batch kernel (wall-clock ticks, or counts).
+enum ProfCounter {
+  kProfFetch = 0,      // taking items and setting up a batch
+  kProfPhaseA = 1,     // forward: discovering the next level
+  kProfPhaseB = 2,     // forward: path counts of the new level
+  kProfPhaseBHeavy = 3,
+  kProfPhaseC = 4,     // forward: retiring the frontier
+  kProfBackward = 5,   // backward: dependencies and accumulation
+  kProfBackHeavy = 6,
+  kProfRestore = 7,    // clearing the slot for the next batch
+  kProfItems = 8,      // count
+  kProfLevels = 9,     // count
+  kProfEntries = 10,   // count of (vertex, level) entries
+  kProfSync = 11,      // team kernel: waiting at team barriers
+  kProfCounters = 12
+};
+
+// Team kernel: the workgroups of a launch form `nteams` teams (workgroup b is
+// in team b mod nteams, the XCD the dispatcher deals it to); each team works
+// on one 64-source item at a time in one MsState slot.  TeamCtl is the team's
+// control block in global memory (zero before launch).
+constexpr int kTeamHeavyMax = 1024;  // split rows per level per team
+
+struct TeamCtl {
+  int32_t arrive;    // barrier arrivals of the current phase
+  int32_t gen;       // barrier generation
+  int32_t abort;     // set once a barrier wait timed out
+  int32_t qtail;     // entries in the team's queue
+  int32_t item[2];   // items taken by the team's leader, by iteration parity
+  int32_t hcnt[3];   // heavy rows registered, by registering phase mod 3
+  int32_t scnt[3];   // slices registered, by registering phase mod 3
+  int32_t pad[20];   // 128 bytes
+};
+
+struct TeamArgs {
+  TeamCtl* ctl;         // [nteams]
+  int32_t* heavy;       // [nteams][2][kTeamHeavyMax]: queue index, first slice
+  int32_t nteams;
+  int32_t pad_;
+  int64_t spin_ticks;   // bound of one barrier wait, in wall-clock ticks
 };
 
 struct QueueArgs {

@@ -53,15 +53,68 @@ hipError_t launch_wg_b(const DevPieces& P, const QueueArgs& Q, bool r, bool i, i
   return launch_wg_t<BLOCK, false, false, LDS>(P, Q, grid, max_np, st, dbg, stream);
 }
 
-template <int WAVES>
+template <int WAVES, int EU>
 hipError_t launch_ms_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
                        hipStream_t stream) {
   (void)hipGetLastError();
-  if (r && i) hipLaunchKernelGGL((ms_kernel<WAVES, true, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
-  else if (r) hipLaunchKernelGGL((ms_kernel<WAVES, true, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
-  else if (i) hipLaunchKernelGGL((ms_kernel<WAVES, false, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
-  else hipLaunchKernelGGL((ms_kernel<WAVES, false, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  if (r && i)
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, true, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  else if (r)
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, true, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  else if (i)
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, false, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
+  else
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, false, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st);
   return hipGetLastError();
+}
+
+template <int WAVES>
+hipError_t launch_ms_e(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int eu, int grid, const MsState& st,
+                       hipStream_t stream) {
+  switch (eu) {
+    case 0: return launch_ms_w<WAVES, 0>(P, Q, r, i, grid, st, stream);
+    case 6: return launch_ms_w<WAVES, 6>(P, Q, r, i, grid, st, stream);
+    case 8: return launch_ms_w<WAVES, 8>(P, Q, r, i, grid, st, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The team kernel needs all of its workgroups resident at once: a cooperative
+// launch makes the runtime start the grid only when that holds (and reject a
+// grid that never could).
+template <int WAVES, int EU, bool R, bool I>
+hipError_t launch_team_t(const DevPieces& P, const QueueArgs& Q, int grid, const MsState& st, const TeamArgs& T,
+                         hipStream_t stream) {
+  DevPieces p = P;
+  QueueArgs q = Q;
+  MsState s = st;
+  TeamArgs t = T;
+  void* args[] = {&p, &q, &s, &t};
+  (void)hipGetLastError();
+  const hipError_t e = hipLaunchCooperativeKernel(ms_team_kernel<WAVES, EU, R, I>, dim3(grid), dim3(WAVES * 64),
+                                                  args, (unsigned)sizeof(TeamShared<WAVES * 64>), stream);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+template <int WAVES, int EU>
+hipError_t launch_team_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
+                         const TeamArgs& T, hipStream_t stream) {
+  if (r && i) return launch_team_t<WAVES, EU, true, true>(P, Q, grid, st, T, stream);
+  if (r) return launch_team_t<WAVES, EU, true, false>(P, Q, grid, st, T, stream);
+  if (i) return launch_team_t<WAVES, EU, false, true>(P, Q, grid, st, T, stream);
+  return launch_team_t<WAVES, EU, false, false>(P, Q, grid, st, T, stream);
+}
+
+template <int WAVES, int EU>
+int occ_team_w() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)ms_team_kernel<WAVES, EU, true, true>,
+                                                   WAVES * 64, sizeof(TeamShared<WAVES * 64>)) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
 }
 
 template <int BLOCK, bool LDS>
@@ -75,11 +128,11 @@ int occ_wg_b(size_t dyn) {
   return nb > 0 ? nb : 1;
 }
 
-template <int WAVES>
+template <int WAVES, int EU>
 int occ_ms_w() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)ms_kernel<WAVES, true, true>, WAVES * 64, 0) !=
-      hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)ms_kernel<WAVES, EU, true, true>, WAVES * 64,
+                                                   0) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
@@ -100,15 +153,21 @@ int occupancy_wg(int block, bool lds, size_t dyn) {
   }
 }
 
-int occupancy_ms(int waves) {
-  switch (waves) {
-    case 4: return occ_ms_w<4>();
-    case 8: return occ_ms_w<8>();
-    case 16: return occ_ms_w<16>();
+int occupancy_ms(int waves, int eu) {
+  const int key = waves * 100 + eu;
+  switch (key) {
+    case 400: return occ_ms_w<4, 0>();
+    case 406: return occ_ms_w<4, 6>();
+    case 408: return occ_ms_w<4, 8>();
+    case 800: return occ_ms_w<8, 0>();
+    case 806: return occ_ms_w<8, 6>();
+    case 808: return occ_ms_w<8, 8>();
+    case 1600: return occ_ms_w<16, 0>();
+    case 1606: return occ_ms_w<16, 6>();
+    case 1608: return occ_ms_w<16, 8>();
     default: return 1;
   }
 }
-
 hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, bool lds, int block, int grid,
                      int32_t max_np, const WgState& st, const DebugOut* dbg, hipStream_t stream) {
   DebugOut d{nullptr, nullptr, nullptr};
@@ -131,12 +190,36 @@ hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
   }
 }
 
-hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
+hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
                      const MsState& st, hipStream_t stream) {
   switch (waves) {
-    case 4: return launch_ms_w<4>(P, Q, reach, ident, grid, st, stream);
-    case 8: return launch_ms_w<8>(P, Q, reach, ident, grid, st, stream);
-    case 16: return launch_ms_w<16>(P, Q, reach, ident, grid, st, stream);
+    case 4: return launch_ms_e<4>(P, Q, reach, ident, eu, grid, st, stream);
+    case 8: return launch_ms_e<8>(P, Q, reach, ident, eu, grid, st, stream);
+    case 16: return launch_ms_e<16>(P, Q, reach, ident, eu, grid, st, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+int occupancy_team(int waves, int eu) {
+  switch (waves * 100 + eu) {
+    case 400: return occ_team_w<4, 0>();
+    case 408: return occ_team_w<4, 8>();
+    case 800: return occ_team_w<8, 0>();
+    case 808: return occ_team_w<8, 8>();
+    case 1600: return occ_team_w<16, 0>();
+    case 1608: return occ_team_w<16, 8>();
+    default: return 0;
+  }
+}
+
+hipError_t launch_team(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
+                       const MsState& st, const TeamArgs& T, hipStream_t stream) {
+  switch (waves * 100 + eu) {
+    case 400: return launch_team_w<4, 0>(P, Q, reach, ident, grid, st, T, stream);
+    case 408: return launch_team_w<4, 8>(P, Q, reach, ident, grid, st, T, stream);
+    case 800: return launch_team_w<8, 0>(P, Q, reach, ident, grid, st, T, stream);
+    case 808: return launch_team_w<8, 8>(P, Q, reach, ident, grid, st, T, stream);
+    case 1600: return launch_team_w<16, 0>(P, Q, reach, ident, grid, st, T, stream);
+    case 1608: return launch_team_w<16, 8>(P, Q, reach, ident, grid, st, T, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -148,6 +231,14 @@ hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t
   (void)hipGetLastError();
   hipLaunchKernelGGL(mapback_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, nverts, nmap, map_off, map_idx,
                      bcp, corr, bcx, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, int grid, hipStream_t stream) {
+  const int64_t n = bytes / 16;
+  if (n <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, (const uint4*)src, (uint4*)dst, n);
   return hipGetLastError();
 }
 

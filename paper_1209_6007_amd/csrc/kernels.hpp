@@ -14,18 +14,25 @@ namespace sbc {
 // or the global-memory state `st`.  `block` in {64, 256, 512, 1024}.
 hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, bool lds, int block,
                      int grid, int32_t max_np, const WgState& st, const DebugOut* dbg, hipStream_t stream);
-hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
+hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
                      const MsState& st, hipStream_t stream);
+// Team kernel (a cooperative launch of `grid` workgroups in T.nteams teams);
+// waves in {4, 8, 16}, eu in {0, 8}.
+hipError_t launch_team(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
+                       const MsState& st, const TeamArgs& T, hipStream_t stream);
 hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
                           const double* bcp, const double* corr, const double* bcx, double scale, double* out,
                           hipStream_t stream);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, int grid, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t stream);
 
 // Resident workgroups per compute unit (from the HIP occupancy calculator).
 int occupancy_wg(int block, bool lds, size_t dyn_lds_bytes);
-int occupancy_ms(int waves);
+int occupancy_ms(int waves, int eu);
+// 0 when the configuration is not built or cannot be resident.
+int occupancy_team(int waves, int eu);
 
 // LDS bytes the LDS-resident kernel needs for a piece of np vertices.
 size_t wg_lds_bytes(int32_t max_np);

@@ -29,6 +29,11 @@
 
 #include "kernel_types.hpp"
 
+#ifndef SBC_KERNEL_BOUNDS
+#define SBC_KERNEL_BOUNDS(block, eu) \
+  __attribute__((amdgpu_flat_work_group_size(1, block), amdgpu_waves_per_eu((eu) > 0 ? (eu) : 1)))
+#endif
+
 namespace sbc {
 namespace dev {
 
@@ -42,6 +47,50 @@ __device__ __forceinline__ void raise_flag(int32_t* flags, int32_t bit) {
 template <typename T>
 __device__ __forceinline__ T coherent_load(T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Load of a value that a wave of the same workgroup produced (with an atomic
+// or a plain store) before a workgroup barrier.  The waves of a workgroup share
+// one CU and its L1, so workgroup scope suffices; unlike an agent-scope load it
+// carries no cache-bypass bits and can hit in L2.
+#ifndef SBC_MASK_SCOPE
+#define SBC_MASK_SCOPE __HIP_MEMORY_SCOPE_WORKGROUP
+#endif
+template <typename T>
+__device__ __forceinline__ T group_load(T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, SBC_MASK_SCOPE);
+}
+
+// Neighbour rows loaded together by one wave in the pull loops.
+#ifndef SBC_PULL_UNROLL
+#define SBC_PULL_UNROLL 4
+#endif
+constexpr int kPullUnroll = SBC_PULL_UNROLL;
+static_assert(kPullUnroll >= 1 && (kPullUnroll & (kPullUnroll - 1)) == 0, "power of two");
+
+// Loads of sigma / coefficient rows and of adjacency: optionally streaming
+// (non-temporal), so that they do not push the per-vertex masks out of L2.
+#ifndef SBC_STREAM_ROWS
+#define SBC_STREAM_ROWS 0
+#endif
+#ifndef SBC_STREAM_COL
+#define SBC_STREAM_COL 0
+#endif
+template <typename T>
+__device__ __forceinline__ T row_load(const T* p) {
+#if SBC_STREAM_ROWS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ T col_load(const T* p) {
+#if SBC_STREAM_COL
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int k) {
@@ -312,7 +361,10 @@ constexpr int kSliceArcs = kMsSliceArcs;  // arcs per split slice
 constexpr int kHeavyMax = kMsHeavyMax;   // split rows per level
 
 // Sum over the neighbours c of a vertex (arcs [e0, e1)) of sg[c*64+lane] for
-// the lanes in need & mk[c] (scaled by ident[c] when `scale` is set).
+// the lanes in need & mk[c] (scaled by ident[c] when `scale` is set).  The
+// wave gathers 64 neighbour masks at a time, then visits the neighbours with
+// any wanted lane kPullUnroll at a time, so that that many row loads are in
+// flight together instead of one after another.
 __device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int32_t e0, int32_t e1, int32_t np,
                                            uint64_t* __restrict__ mk, const uint64_t need,
                                            const double* __restrict__ sg, const int32_t* __restrict__ idn,
@@ -323,9 +375,9 @@ __device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int3
     int32_t c = 0;
     uint64_t m = 0;
     if (e < e1) {
-      c = col[e];
+      c = col_load(&col[e]);
       if (c >= 0 && c < np) {
-        m = coherent_load(&mk[c]) & need;
+        m = group_load(&mk[c]) & need;
       } else {
         raise_flag(flags, kFlagBadArc);
         c = 0;
@@ -333,15 +385,26 @@ __device__ __forceinline__ double pull_row(const int32_t* __restrict__ col, int3
     }
     uint64_t act = __ballot(m != 0);
     while (act) {
-      const int k = __builtin_ctzll(act);
-      act &= act - 1;
-      const int32_t u = __builtin_amdgcn_readlane(c, k);
-      const uint64_t mu = readlane64(m, k);
-      if ((mu >> lane) & 1) {
-        double x = sg[(size_t)u * 64 + lane];
-        if (scale) x *= (double)idn[u];
-        acc += x;
+      // Up to kPullUnroll neighbours at a time: their row loads are issued
+      // together, then summed in a fixed pairwise order.
+      double x[kPullUnroll];
+#pragma unroll
+      for (int j = 0; j < kPullUnroll; ++j) {
+        x[j] = 0.0;
+        if (act) {  // wave-uniform
+          const int k = __builtin_ctzll(act);
+          act &= act - 1;
+          const int32_t u = __builtin_amdgcn_readlane(c, k);
+          const uint64_t mu = readlane64(m, k);
+          if ((mu >> lane) & 1) x[j] = row_load(&sg[(size_t)u * 64 + lane]);
+          if (scale) x[j] *= (double)idn[u];
+        }
       }
+#pragma unroll
+      for (int w = 1; w < kPullUnroll; w <<= 1)
+#pragma unroll
+        for (int j = 0; j + w < kPullUnroll; j += 2 * w) x[j] += x[j + w];
+      acc += x[0];
     }
   }
   return acc;
@@ -363,8 +426,11 @@ __device__ __forceinline__ bool wave_row(const int32_t* __restrict__ rowp, int32
   return true;
 }
 
-template <int WAVES, bool REACH, bool IDENT>
-__global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q, MsState st) {
+// EU > 0 asks the compiler for at least EU resident waves per SIMD (it then
+// keeps the kernel within 512/EU VGPRs); the kernel is latency-bound, so more
+// waves in flight can matter more than registers.
+template <int WAVES, int EU, bool REACH, bool IDENT>
+__global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueArgs Q, MsState st) {
   if (Q.magic != kArgMagic) return;
   constexpr int BLOCK = WAVES * 64;
   __shared__ int s_item;
@@ -391,6 +457,17 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
   double* part = st.part + slot * (size_t)st.part_cap * 64;
   const int64_t qcap = st.stride * 64;
   const int32_t narcs = P.narcs;
+  // Phase timers: thread 0 charges the wall-clock time since its last mark to
+  // one counter of this slot.
+  uint64_t* prof = st.prof ? st.prof + slot * kProfCounters : nullptr;
+  long long tmark = prof ? wall_clock64() : 0;
+  auto mark = [&](int idx) {
+    if (prof && tid == 0) {
+      const long long now = wall_clock64();
+      prof[idx] += (uint64_t)(now - tmark);
+      tmark = now;
+    }
+  };
 
   while (true) {
     if (tid == 0) s_item = atomicAdd(Q.head, 1);
@@ -444,6 +521,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
       s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
     }
     __syncthreads();
+    mark(kProfFetch);
 
     uint64_t* fcur = bufa;
     uint64_t* fnxt = bufb;
@@ -509,6 +587,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
         __syncthreads();
       }
       const int nt = (int)min((int64_t)(qe + s_cnt[L % 3]), qcap);
+      mark(kProfPhaseA);
       if (nt == qe) break;
       // Phase B: sigma of the new lanes, one wave per vertex, pulling from the
       // neighbours on level L (their frontier masks); long rows are deferred.
@@ -517,7 +596,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
         const int32_t w = q[i];
         int32_t e0, e1;
         if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-        const uint64_t need = coherent_load(&fnxt[w]);  // built with atomicOr
+        const uint64_t need = group_load(&fnxt[w]);  // built with atomicOr
         if (e1 - e0 > kHubArcs) {
           int reg = 0;
           if (lane == 0) {
@@ -542,6 +621,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
         }
       }
       __syncthreads();
+      mark(kProfPhaseB);
       const int nh = min(s_nheavy, kHeavyMax);
       if (nh > 0) {
         for (int h = 0; h < nh; ++h) {
@@ -550,7 +630,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           const int32_t w = q[i];
           int32_t e0, e1;
           if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-          const uint64_t need = coherent_load(&fnxt[w]);
+          const uint64_t need = group_load(&fnxt[w]);
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
           for (int sl = wave; sl < ns; sl += WAVES) {
             const int32_t a = e0 + sl * kSliceArcs;
@@ -566,7 +646,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           const int32_t w = q[i];
           int32_t e0, e1;
           if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-          const uint64_t need = coherent_load(&fnxt[w]);
+          const uint64_t need = group_load(&fnxt[w]);
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
@@ -577,6 +657,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           }
         }
         __syncthreads();
+        mark(kProfPhaseBHeavy);
       }
       // Phase C: retire level L's frontier masks; level L+1 becomes current.
       for (int i = qs + tid; i < qe; i += BLOCK) {
@@ -585,6 +666,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
       }
       if (tid == 0) lvl[L + 2] = nt;
       __syncthreads();
+      mark(kProfPhaseC);
       uint64_t* t = fcur;
       fcur = fnxt;
       fnxt = t;
@@ -597,6 +679,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
       if (u >= 0 && u < np) fcur[u] = 0;
     }
     __syncthreads();
+    mark(kProfPhaseC);
     const int total = qe;
     const int Lmax = L;
 
@@ -653,6 +736,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
         }
       }
       __syncthreads();
+      mark(kProfBackward);
       const int nh = min(s_nheavy, kHeavyMax);
       if (nh > 0) {
         for (int h = 0; h < nh; ++h) {
@@ -697,6 +781,7 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
           }
         }
         __syncthreads();
+        mark(kProfBackHeavy);
       }
     }
     // Restore the slot: clear the backward masks of the two lowest levels and
@@ -713,7 +798,489 @@ __global__ __launch_bounds__(WAVES * 64) void ms_kernel(DevPieces P, QueueArgs Q
       if (u >= 0 && u < np) vis[u] = 0;
     }
     __syncthreads();
+    mark(kProfRestore);
+    if (prof && tid == 0) {
+      prof[kProfItems] += 1;
+      prof[kProfLevels] += (uint64_t)Lmax;
+      prof[kProfEntries] += (uint64_t)total;
+    }
     if (tid == 0) atomicAdd(Q.done, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Team kernel: the same traversal as ms_kernel, for large pieces.  Instead of
+// one workgroup per 64-source item, the workgroups of a launch form teams
+// (workgroup b joins team b mod nteams, i.e. the XCD the dispatcher deals it
+// to), and all workgroups of a team work on the team's current item, with the
+// (vertex, level) entries of each level spread over every wave of the team.
+// One item's per-vertex lane masks (about 0.5 MB per mask for a piece of
+// 64K vertices) then stay in one L2, instead of one cold copy per workgroup.
+//
+// Phases are separated by team barriers: agent-scope release, an arrival
+// counter, a spin on the generation word bounded by T.spin_ticks, and an
+// agent-scope acquire.  A timed-out wait aborts the team and raises
+// kFlagTeamTimeout, so every wave still leaves the kernel.  The kernel needs
+// all of its workgroups resident at once; the host launches it cooperatively.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+struct TeamShared {
+  int wtot[BLOCK / 64];
+  int scan[BLOCK];
+  int e0[BLOCK];
+  uint64_t f[BLOCK];
+  int ok;
+};
+
+template <typename T>
+__device__ __forceinline__ T ctl_load(T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int WAVES, int EU, bool REACH, bool IDENT>
+__global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, QueueArgs Q, MsState st, TeamArgs T) {
+  if (Q.magic != kArgMagic) return;
+  constexpr int BLOCK = WAVES * 64;
+  SBC_DYNAMIC_LDS(lds_raw);
+  TeamShared<BLOCK>& S = *reinterpret_cast<TeamShared<BLOCK>*>(lds_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nteams = T.nteams;
+  if (nteams < 1 || (int)gridDim.x < nteams) return;  // every workgroup takes this exit together
+  const int team = (int)blockIdx.x % nteams, rank = (int)blockIdx.x / nteams;
+  const int tsize = ((int)gridDim.x - 1 - team) / nteams + 1;  // workgroups in this team
+  const int gwave = rank * WAVES + wave, twaves = tsize * WAVES;
+  const int gthr = rank * BLOCK + tid, tthr = tsize * BLOCK;
+  const bool leader = rank == 0 && tid == 0;
+  TeamCtl* ctl = T.ctl + team;
+  int32_t* hv_i = T.heavy + (size_t)team * 2 * kTeamHeavyMax;  // queue index of each split row
+  int32_t* hv_off = hv_i + kTeamHeavyMax;                      // its first slice in part[]
+  const size_t slot = team;
+  double* sg = st.sg + slot * (size_t)st.stride * 64;
+  int32_t* q = st.q + slot * (size_t)st.stride * 64;
+  uint64_t* qm = st.qm + slot * (size_t)st.stride * 64;
+  uint64_t* vis = st.vis + slot * (size_t)st.stride;
+  uint64_t* bufa = st.fa + slot * (size_t)st.stride;
+  uint64_t* bufb = st.fb + slot * (size_t)st.stride;
+  uint64_t* bm0 = st.ba + slot * (size_t)st.stride;  // backward masks of levels = 0 mod 3
+  uint64_t* bm1 = st.bb + slot * (size_t)st.stride;  // ... = 1 mod 3
+  uint64_t* bm2 = st.bc + slot * (size_t)st.stride;  // ... = 2 mod 3
+  auto bmask = [&](int l) { return (l % 3 == 0) ? bm0 : ((l % 3 == 1) ? bm1 : bm2); };
+  int32_t* lvl = st.lvl + slot * (size_t)(st.stride + 3);
+  double* part = st.part + slot * (size_t)st.part_cap * 64;
+  const int64_t qcap = st.stride * 64;
+  const int32_t narcs = P.narcs;
+  uint64_t* prof = st.prof ? st.prof + (size_t)blockIdx.x * kProfCounters : nullptr;
+  long long tmark = prof ? wall_clock64() : 0;
+  auto mark = [&](int idx) {
+    if (prof && tid == 0) {
+      const long long now = wall_clock64();
+      prof[idx] += (uint64_t)(now - tmark);
+      tmark = now;
+    }
+  };
+  int gen = 0;
+  // Team barrier; false once the team has been aborted.
+  auto team_sync = [&](int phase) -> bool {
+    mark(phase);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+      const int arrived = __hip_atomic_fetch_add(&ctl->arrive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == tsize - 1) {
+        __hip_atomic_store(&ctl->arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const long long t0 = wall_clock64();
+        while (ctl_load(&ctl->gen) == gen && !ctl_load(&ctl->abort)) {
+          if (wall_clock64() - t0 > T.spin_ticks) {
+            __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            raise_flag(Q.flags, kFlagTeamTimeout);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      S.ok = ctl_load(&ctl->abort) ? 0 : 1;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ++gen;
+    mark(kProfSync);
+    return S.ok != 0;
+  };
+
+  for (int iter = 0;; ++iter) {
+    if (leader) ctl->item[iter & 1] = atomicAdd(Q.head, 1);
+    if (!team_sync(kProfFetch)) break;
+    const int it = ctl_load(&ctl->item[iter & 1]);
+    if (it < 0 || it >= Q.nitems) break;  // the same verdict in the whole team
+    const WorkItem W = Q.items[it];
+    int32_t vb, np;
+    const bool item_good = item_ok(P, Q, W, st.stride, &vb, &np) && W.s1 - W.s0 >= 1 && W.s1 - W.s0 <= 64;
+    if (!item_good) {
+      if (leader) {
+        raise_flag(Q.flags, kFlagBadItem);
+        atomicAdd(Q.done, 1);
+      }
+      continue;
+    }
+    const int32_t* rowp = P.row + vb;
+    const int32_t* col = P.col;
+    const int32_t* rch = REACH ? P.reach + vb : nullptr;
+    const int32_t* idn = IDENT ? P.ident + vb : nullptr;
+    double* bcp = P.bcp + vb;
+    const int nsrc = W.s1 - W.s0;
+
+    // Lane j runs source src_order[vb + s0 + j].
+    int32_t s = -1;
+    if (lane < nsrc) s = P.src_order[vb + W.s0 + lane];
+    if (__ballot(lane < nsrc && (s < 0 || s >= np)) != 0) {  // the same verdict in every wave of the team
+      if (leader) {
+        raise_flag(Q.flags, kFlagBadSource);
+        atomicAdd(Q.done, 1);
+      }
+      continue;
+    }
+    double wsrc = 0.0;
+    if (lane < nsrc) {
+      wsrc = 1.0;
+      if (REACH) wsrc *= (double)rch[s];
+      if (IDENT) wsrc *= (double)idn[s];
+      if (rank == 0 && wave == 0) {
+        q[lane] = s;
+        qm[lane] = 1ull << lane;
+        bufa[s] = 1ull << lane;
+        vis[s] = 1ull << lane;
+        sg[(size_t)s * 64 + lane] = 1.0;
+      }
+    }
+    if (leader) {
+      lvl[0] = 0;
+      lvl[1] = nsrc;
+      ctl->qtail = nsrc;
+      ctl->hcnt[0] = 0;
+      ctl->scnt[0] = 0;
+    }
+    if (!team_sync(kProfFetch)) break;
+
+    uint64_t* fcur = bufa;
+    uint64_t* fnxt = bufb;
+    int qs = 0, qe = nsrc, L = 0, hstep = 0;
+    bool alive = true;
+    // ---------------- forward sweep ----------------
+    while (true) {
+      if (leader) {  // counters of the next registering phase (last used three phases ago)
+        ctl->hcnt[(hstep + 1) % 3] = 0;
+        ctl->scnt[(hstep + 1) % 3] = 0;
+      }
+      // Phase A: the team's workgroups take blocks of level-L entries in turn
+      // and spread each block's arcs evenly over their threads.
+      for (int cb = qs + rank * BLOCK; cb < qe; cb += tsize * BLOCK) {
+        const int i = cb + tid;
+        int e0 = 0, deg = 0;
+        uint64_t fu = 0;
+        if (i < qe) {
+          const int32_t u = q[i];
+          if (u >= 0 && u < np) {
+            e0 = rowp[u];
+            const int32_t e1 = rowp[u + 1];
+            if (e0 >= 0 && e1 >= e0 && e1 <= narcs) {
+              deg = e1 - e0;
+              fu = qm[i];
+            } else {
+              raise_flag(Q.flags, kFlagBadArc);
+              e0 = 0;
+            }
+          } else {
+            raise_flag(Q.flags, kFlagBadArc);
+          }
+        }
+        int total;
+        const int ex = block_excl_scan<BLOCK>(deg, S.wtot, &total);
+        S.scan[tid] = ex;
+        S.e0[tid] = e0;
+        S.f[tid] = fu;
+        __syncthreads();
+        const int nv = min(BLOCK, qe - cb);
+        for (int tb = wave * 64; tb < total; tb += BLOCK) {  // wave-uniform trip count
+          const int t = tb + lane;
+          int32_t w = -1;
+          uint64_t nw = 0;
+          if (t < total) {
+            int lo = 0, hi = nv - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (S.scan[mid] <= t) lo = mid;
+              else hi = mid - 1;
+            }
+            w = col_load(&col[S.e0[lo] + (t - S.scan[lo])]);
+            if (w < 0 || w >= np) {
+              raise_flag(Q.flags, kFlagBadArc);
+              w = -1;
+            } else {
+              nw = S.f[lo] & ~vis[w];
+            }
+          }
+          bool isnew = false;
+          if (nw) isnew = atomicOr((unsigned long long*)&fnxt[w], (unsigned long long)nw) == 0;
+          // One queue reservation per wave for the vertices it reached first.
+          const uint64_t bal = __ballot(isnew);
+          if (bal) {
+            const int first = __builtin_ctzll(bal);
+            int base = 0;
+            if (lane == first) base = atomicAdd(&ctl->qtail, (int)__builtin_popcountll(bal));
+            base = __builtin_amdgcn_readlane(base, first);
+            if (isnew) {
+              const int64_t pos = (int64_t)base + __builtin_popcountll(bal & ((1ull << lane) - 1));
+              if (pos < qcap) q[pos] = w;
+              else raise_flag(Q.flags, kFlagQueueOverflow);
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (!team_sync(kProfPhaseA)) {
+        alive = false;
+        break;
+      }
+      const int nt = (int)min((int64_t)ctl_load(&ctl->qtail), qcap);
+      if (nt == qe) break;  // the same verdict in the whole team
+      // Phase B: sigma of the new lanes, one wave per entry, spread over the
+      // team; long rows are registered for splitting.
+      const bool scale = IDENT && L > 0;
+      const int hs = hstep % 3;
+      for (int i = qe + gwave; i < nt; i += twaves) {
+        const int32_t w = q[i];
+        int32_t e0, e1;
+        if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+        const uint64_t need = fnxt[w];
+        if (e1 - e0 > kHubArcs) {
+          int reg = 0;
+          if (lane == 0) {
+            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+            const int h = atomicAdd(&ctl->hcnt[hs], 1);
+            const int o = atomicAdd(&ctl->scnt[hs], ns);
+            if (h < kTeamHeavyMax && o + ns <= st.part_cap) {
+              hv_i[h] = i;
+              hv_off[h] = o;
+              reg = 1;
+            } else if (h < kTeamHeavyMax) {
+              hv_i[h] = -1;
+            }
+          }
+          if (__builtin_amdgcn_readfirstlane(reg)) continue;
+        }
+        const double acc = pull_row(col, e0, e1, np, fcur, need, sg, idn, scale, lane, Q.flags);
+        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+        if (lane == 0) {
+          vis[w] |= need;
+          qm[i] = need;
+        }
+      }
+      if (!team_sync(kProfPhaseB)) {
+        alive = false;
+        break;
+      }
+      const int nh = min(ctl_load(&ctl->hcnt[hs]), kTeamHeavyMax);
+      if (nh > 0) {  // the same verdict in the whole team
+        // Slice u of all registered slices goes to team wave u mod twaves.
+        for (int h = 0; h < nh; ++h) {
+          const int i = hv_i[h];
+          if (i < 0) continue;
+          const int32_t w = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t need = fnxt[w];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const int o = hv_off[h];
+          for (int sl = ((gwave - o) % twaves + twaves) % twaves; sl < ns; sl += twaves) {
+            const int32_t a = e0 + sl * kSliceArcs;
+            const int32_t b = min(e1, a + kSliceArcs);
+            part[(size_t)(o + sl) * 64 + lane] = pull_row(col, a, b, np, fcur, need, sg, idn, scale, lane, Q.flags);
+          }
+        }
+        if (!team_sync(kProfPhaseBHeavy)) {
+          alive = false;
+          break;
+        }
+        for (int h = gwave; h < nh; h += twaves) {
+          const int i = hv_i[h];
+          if (i < 0) continue;
+          const int32_t w = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t need = fnxt[w];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          double acc = 0.0;
+          for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
+          if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+          if (lane == 0) {
+            vis[w] |= need;
+            qm[i] = need;
+          }
+        }
+      }
+      // Phase C: retire level L's frontier masks; level L+1 becomes current.
+      for (int i = qs + gthr; i < qe; i += tthr) {
+        const int32_t u = q[i];
+        if (u >= 0 && u < np) fcur[u] = 0;
+      }
+      if (leader) lvl[L + 2] = nt;
+      if (!team_sync(kProfPhaseC)) {
+        alive = false;
+        break;
+      }
+      uint64_t* t = fcur;
+      fcur = fnxt;
+      fnxt = t;
+      qs = qe;
+      qe = nt;
+      ++L;
+      ++hstep;
+    }
+    if (!alive) break;
+    for (int i = qs + gthr; i < qe; i += tthr) {
+      const int32_t u = q[i];
+      if (u >= 0 && u < np) fcur[u] = 0;
+    }
+    const int total = qe;
+    const int Lmax = L;
+
+    // ---------------- backward sweep ----------------
+    // Level l writes the masks of array l mod 3 and reads those of level l+1;
+    // meanwhile the idle array (l+2) mod 3 is cleared for level l-1.
+    for (int l = Lmax; l >= 1 && alive; --l) {
+      uint64_t* bw = bmask(l);
+      uint64_t* br = bmask(l + 1);
+      uint64_t* bz = bmask(l + 2);
+      if (leader) {
+        ctl->hcnt[(hstep + 1) % 3] = 0;
+        ctl->scnt[(hstep + 1) % 3] = 0;
+      }
+      const int hs = hstep % 3;
+      if (l + 2 <= Lmax)
+        for (int i = lvl[l + 2] + gthr; i < lvl[l + 3]; i += tthr) {
+          const int32_t u = q[i];
+          if (u >= 0 && u < np) bz[u] = 0;
+        }
+      const int b = lvl[l], e = lvl[l + 1];
+      for (int i = b + gwave; i < e; i += twaves) {
+        const int32_t v = q[i];
+        int32_t e0, e1;
+        if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+        const uint64_t amask = qm[i];
+        if (e1 - e0 > kHubArcs) {
+          int reg = 0;
+          if (lane == 0) {
+            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+            const int h = atomicAdd(&ctl->hcnt[hs], 1);
+            const int o = atomicAdd(&ctl->scnt[hs], ns);
+            if (h < kTeamHeavyMax && o + ns <= st.part_cap) {
+              hv_i[h] = i;
+              hv_off[h] = o;
+              reg = 1;
+            } else if (h < kTeamHeavyMax) {
+              hv_i[h] = -1;
+            }
+          }
+          if (__builtin_amdgcn_readfirstlane(reg)) continue;
+        }
+        const double acc = pull_row(col, e0, e1, np, br, amask, sg, idn, false, lane, Q.flags);
+        double contrib = 0.0;
+        if ((amask >> lane) & 1) {
+          const size_t at = (size_t)v * 64 + lane;
+          const double sv = sg[at];
+          const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+          sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+          contrib = wsrc * dv;
+          if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+        }
+        contrib = wave_sum(contrib);
+        if (lane == 0) {
+          atomicAdd(&bcp[v], contrib);
+          bw[v] = amask;
+        }
+      }
+      if (!team_sync(kProfBackward)) {
+        alive = false;
+        break;
+      }
+      const int nh = min(ctl_load(&ctl->hcnt[hs]), kTeamHeavyMax);
+      if (nh > 0) {
+        for (int h = 0; h < nh; ++h) {
+          const int i = hv_i[h];
+          if (i < 0) continue;
+          const int32_t v = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t amask = qm[i];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const int o = hv_off[h];
+          for (int sl = ((gwave - o) % twaves + twaves) % twaves; sl < ns; sl += twaves) {
+            const int32_t a = e0 + sl * kSliceArcs;
+            const int32_t bnd = min(e1, a + kSliceArcs);
+            part[(size_t)(o + sl) * 64 + lane] = pull_row(col, a, bnd, np, br, amask, sg, idn, false, lane, Q.flags);
+          }
+        }
+        if (!team_sync(kProfBackHeavy)) {
+          alive = false;
+          break;
+        }
+        for (int h = gwave; h < nh; h += twaves) {
+          const int i = hv_i[h];
+          if (i < 0) continue;
+          const int32_t v = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t amask = qm[i];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          double acc = 0.0;
+          for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
+          double contrib = 0.0;
+          if ((amask >> lane) & 1) {
+            const size_t at = (size_t)v * 64 + lane;
+            const double sv = sg[at];
+            const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+            sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+            contrib = wsrc * dv;
+            if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+          }
+          contrib = wave_sum(contrib);
+          if (lane == 0) {
+            atomicAdd(&bcp[v], contrib);
+            bw[v] = amask;
+          }
+        }
+        if (!team_sync(kProfBackHeavy)) {
+          alive = false;
+          break;
+        }
+      }
+      ++hstep;
+    }
+    if (!alive) break;
+    // Restore the slot: the backward masks of levels 1 and 2 and the visit
+    // masks of every entry.  The next item starts after a team barrier.
+    for (int l = 1; l <= 2 && l <= Lmax; ++l) {
+      uint64_t* bw = bmask(l);
+      for (int i = lvl[l] + gthr; i < lvl[l + 1]; i += tthr) {
+        const int32_t u = q[i];
+        if (u >= 0 && u < np) bw[u] = 0;
+      }
+    }
+    for (int i = gthr; i < total; i += tthr) {
+      const int32_t u = q[i];
+      if (u >= 0 && u < np) vis[u] = 0;
+    }
+    mark(kProfRestore);
+    if (leader) {
+      if (prof) {
+        prof[kProfItems] += 1;
+        prof[kProfLevels] += (uint64_t)Lmax;
+        prof[kProfEntries] += (uint64_t)total;
+      }
+      atomicAdd(Q.done, 1);
+    }
   }
 }
 
@@ -731,6 +1298,13 @@ __global__ void mapback_kernel(int32_t n, int32_t nverts, int32_t nmap, const in
     acc += bcp[x] + (corr ? corr[x] : 0.0);
   }
   out[v] = acc * scale;
+}
+
+// Streaming copy of 16-byte words: a kernel of known traffic (read n*16
+// bytes, write n*16 bytes) for bandwidth calibration.
+__global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 template <typename T>

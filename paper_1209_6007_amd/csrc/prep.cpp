@@ -355,13 +355,14 @@ struct Builder {
 }  // namespace
 
 int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStats* st, std::string* why) {
-  bool opd = false, opa = false, opi = false;
+  bool opd = false, opa = false, opi = false, opo = false;
   for (char c : ops) {
-    if (c == 'd') opd = true;
+    if (c == 'o') opo = true;
+    else if (c == 'd') opd = true;
     else if (c == 'a' || c == 'b') opa = true;
     else if (c == 'i') opi = true;
     else {
-      *why = std::string("unknown preprocessing letter '") + c + "' (known: d, a, b, i)";
+      *why = std::string("unknown preprocessing letter '") + c + "' (known: o, d, a, b, i)";
       return SBC_E_INVALID_ARG;
     }
   }
@@ -622,9 +623,68 @@ int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStat
   Q.src_order.resize(V);
   for (int32_t p = 0; p < Q.pieces(); ++p)
     for (int32_t i = Q.vtx_off[p]; i < Q.vtx_off[p + 1]; ++i) Q.src_order[i] = i - Q.vtx_off[p];
+  if (opo) order_pieces(&Q);
   st->ms_pack = now_ms() - t2;
   *P = std::move(Q);
   return SBC_OK;
+}
+
+void order_pieces(Prepared* P) {
+  const int32_t np_total = P->pieces();
+  const int64_t V = P->V();
+  std::vector<int32_t> newid(V);  // global old piece vertex -> global new piece vertex
+  std::vector<int32_t> order, seen;
+  std::vector<int32_t> row2(V + 1), col2(P->col.size()), reach2(V), ident2(V), src2(V);
+  std::vector<double> corr2(V);
+  row2[0] = 0;
+  for (int32_t p = 0; p < np_total; ++p) {
+    const int32_t vb = P->vtx_off[p], np = P->vtx_off[p + 1] - vb;
+    order.clear();
+    seen.assign(np, 0);
+    int32_t start = 0;
+    for (int32_t v = 1; v < np; ++v)
+      if (P->row[vb + v + 1] - P->row[vb + v] > P->row[vb + start + 1] - P->row[vb + start]) start = v;
+    for (int32_t root = start, scan = 0; (int32_t)order.size() < np;) {
+      if (seen[root]) {
+        while (scan < np && seen[scan]) ++scan;
+        root = scan;
+        continue;
+      }
+      seen[root] = 1;
+      size_t h = order.size();
+      order.push_back(root);
+      for (; h < order.size(); ++h) {
+        const int32_t v = order[h];
+        for (int32_t e = P->row[vb + v]; e < P->row[vb + v + 1]; ++e) {
+          const int32_t w = P->col[e];
+          if (!seen[w]) {
+            seen[w] = 1;
+            order.push_back(w);
+          }
+        }
+      }
+    }
+    for (int32_t i = 0; i < np; ++i) newid[vb + order[i]] = vb + i;
+    for (int32_t i = 0; i < np; ++i) {
+      const int32_t old = vb + order[i];
+      const int32_t deg = P->row[old + 1] - P->row[old];
+      const int32_t out = row2[vb + i];
+      for (int32_t k = 0; k < deg; ++k) col2[out + k] = newid[vb + P->col[P->row[old] + k]] - vb;
+      std::sort(col2.begin() + out, col2.begin() + out + deg);
+      row2[vb + i + 1] = out + deg;
+      reach2[vb + i] = P->reach[old];
+      ident2[vb + i] = P->ident[old];
+      corr2[vb + i] = P->corr[old];
+      src2[vb + i] = i;
+    }
+  }
+  for (auto& x : P->map_idx) x = newid[x];
+  P->row.swap(row2);
+  P->col.swap(col2);
+  P->reach.swap(reach2);
+  P->ident.swap(ident2);
+  P->corr.swap(corr2);
+  P->src_order.swap(src2);
 }
 
 void cluster_sources(Prepared* P, int group) {

@@ -74,4 +74,11 @@ void plain_problem(const HostGraph& g, Prepared* out);
 // vertices, so that the sources of one multi-source batch lie close together.
 void cluster_sources(Prepared* p, int group);
 
+// Vertex ordering of Section 4.1 ("o"), per piece: local ids are renumbered
+// in breadth-first order from the piece's highest-degree vertex, so that a
+// traversal touches nearby rows and the most-used (hub) rows sit together.
+// Rows, attributes, per-member terms and the map back to the original graph
+// are permuted consistently.
+void order_pieces(Prepared* p);
+
 }  // namespace sbc

@@ -13,6 +13,9 @@ namespace sbc {
 namespace {
 thread_local std::string g_last_error;
 
+// Control block: work-queue heads, items done per class, error flags.
+constexpr int kCtlHeads = 0, kCtlDone = 8, kCtlFlags = 16, kCtlInts = 32;
+
 double wall_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -93,7 +96,9 @@ size_t Plan::device_bytes() const {
   size_t t = 0;
   for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
                           &d_map_off, &d_map_idx, &d_out, &d_ctl, &ms_sg, &ms_q, &ms_qm, &ms_vis, &ms_fa, &ms_fb,
-                          &ms_ba, &ms_bb, &ms_lvl, &ms_part, &wg_d, &wg_sig, &wg_q, &wg_lvl})
+                          &ms_ba, &ms_bb, &ms_lvl, &ms_part, &ms_prof, &wg_d, &wg_sig, &wg_q, &wg_lvl, &tm_sg, &tm_q,
+                          &tm_qm, &tm_vis, &tm_fa, &tm_fb, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof,
+                          &tm_ctl, &tm_heavy})
     t += b->bytes;
   for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes;
   return t;
@@ -110,11 +115,15 @@ size_t ms_slot_bytes(int64_t stride, int64_t part_cap) {
 size_t wg_slot_bytes(int64_t stride) { return (size_t)stride * 16 + (size_t)(stride + 2) * 4; }
 
 int classify(const Params& pr, int32_t np, bool plain, int force) {
-  if (!kPerSourceKernelsEnabled) return KC_BATCH;
+  if (force == 4) return KC_TEAM;
+  if (force == 3) return KC_BATCH;
+  const bool team = pr.team_min_vertices > 0 && np >= pr.team_min_vertices;
+  if (!kPerSourceKernelsEnabled) return team ? KC_TEAM : KC_BATCH;
   if (force == 1) return KC_GLOBAL;
   if (force == 2) return np <= pr.wave_max_vertices ? KC_WAVE : KC_LDS;
   if (force == 3) return KC_BATCH;
   if (plain && pr.plain_kernel == 1) return KC_GLOBAL;
+  if (team) return KC_TEAM;
   if (np >= pr.batch_min_vertices) return KC_BATCH;
   if (np <= pr.wave_max_vertices) return KC_WAVE;
   if (np <= pr.lds_max_vertices) return KC_LDS;
@@ -126,17 +135,25 @@ int classify(const Params& pr, int32_t np, bool plain, int force) {
 size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
   size_t t = (size_t)prob.V() * (4 * 4 + 8 * 2) + prob.A() * 4 + (size_t)prob.n * (8 * 2 + 4) +
              prob.map_idx.size() * 4 + (size_t)prob.pieces() * 4;
-  int64_t max_batch = 0, max_batch_arcs = 0, max_glob = 0;
+  int64_t max_batch = 0, max_batch_arcs = 0, max_glob = 0, max_team = 0, max_team_arcs = 0;
   for (int32_t p = 0; p < prob.pieces(); ++p) {
     int32_t np = prob.vtx_off[p + 1] - prob.vtx_off[p];
+    const int64_t arcs = prob.row[prob.vtx_off[p + 1]] - prob.row[prob.vtx_off[p]];
     int k = classify(c->params, np, false, 0);
     if (k == KC_BATCH) {
       max_batch = std::max<int64_t>(max_batch, np);
-      max_batch_arcs = std::max<int64_t>(max_batch_arcs, prob.row[prob.vtx_off[p + 1]] - prob.row[prob.vtx_off[p]]);
+      max_batch_arcs = std::max<int64_t>(max_batch_arcs, arcs);
+    }
+    if (k == KC_TEAM) {
+      max_team = std::max<int64_t>(max_team, np);
+      max_team_arcs = std::max<int64_t>(max_team_arcs, arcs);
     }
     if (k == KC_GLOBAL) max_glob = std::max<int64_t>(max_glob, np);
   }
   if (max_batch) t += ms_slot_bytes(max_batch, max_batch_arcs / kMsSliceArcs + 2 * kMsHeavyMax) * 4;
+  if (max_team)
+    t += (ms_slot_bytes(max_team, max_team_arcs / kMsSliceArcs + 2 * kTeamHeavyMax) + (size_t)max_team * 8) *
+         std::max<int64_t>(1, c->params.team_count);
   if (max_glob) t += wg_slot_bytes(max_glob) * 16;
   return t;
 }
@@ -221,7 +238,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     int32_t chunk = 1;
     if (k == KC_WAVE) chunk = (int32_t)pr.wave_sources_per_item;
     if (k == KC_LDS) chunk = (int32_t)pr.lds_sources_per_item;
-    if (k == KC_BATCH) chunk = 64;
+    if (k == KC_BATCH || k == KC_TEAM) chunk = 64;
     for (int32_t s0 = 0; s0 < nsrc; s0 += chunk) items[k].push_back({p, s0, std::min(nsrc, s0 + chunk), k});
     max_np[k] = std::max(max_np[k], np);
     sources_in[k] += nsrc;
@@ -254,10 +271,10 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   if ((e = d_out.alloc(std::max<int32_t>(n, 1) * sizeof(double))) != hipSuccess) return hip_fail(e, "alloc out");
   for (int k = 0; k < KC_COUNT; ++k)
     if ((e = upload(d_items[k], items[k])) != hipSuccess) return hip_fail(e, "upload items");
-  if ((e = d_ctl.alloc(sizeof(int32_t) * 16)) != hipSuccess) return hip_fail(e, "alloc ctl");
-  if ((e = hipHostMalloc((void**)&h_ctl, sizeof(int32_t) * 16, hipHostMallocDefault)) != hipSuccess)
+  if ((e = d_ctl.alloc(sizeof(int32_t) * kCtlInts)) != hipSuccess) return hip_fail(e, "alloc ctl");
+  if ((e = hipHostMalloc((void**)&h_ctl, sizeof(int32_t) * kCtlInts, hipHostMallocDefault)) != hipSuccess)
     return hip_fail(e, "hipHostMalloc");
-  std::memset(h_ctl, 0, sizeof(int32_t) * 16);
+  std::memset(h_ctl, 0, sizeof(int32_t) * kCtlInts);
 
   // Traversal state, sized by occupancy and the memory budget.
   size_t freeb = 0, totalb = 0;
@@ -304,7 +321,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
         max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
     }
     const int64_t part_cap = max_arcs / kMsSliceArcs + 2 * kMsHeavyMax;
-    const int occ = occupancy_ms((int)pr.batch_wg_waves);
+    const int occ = occupancy_ms((int)pr.batch_wg_waves, (int)pr.batch_waves_per_eu);
     int g = cus * occ;
     if (pr.slots > 0) g = (int)pr.slots;
     const size_t per = ms_slot_bytes(stride, part_cap);
@@ -334,8 +351,75 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     ms.bb = ms_bb.as<uint64_t>();
     ms.lvl = ms_lvl.as<int32_t>();
     ms.part = ms_part.as<double>();
+    ms.prof = nullptr;
+    if (pr.profile_phases) {
+      if ((e = ms_prof.alloc(G * kProfCounters * 8)) != hipSuccess) return hip_fail(e, "alloc ms prof");
+      ms.prof = ms_prof.as<uint64_t>();
+    }
     for (uint64_t* p : {ms.vis, ms.fa, ms.fb, ms.ba, ms.bb})
       if ((e = launch_fill_u64(p, 0, (int64_t)G * stride, own)) != hipSuccess) return hip_fail(e, "fill ms");
+  }
+  if (nitems[KC_TEAM]) {
+    // One slot per team; the grid is every workgroup that can be resident,
+    // dealt round-robin to the teams.
+    int64_t stride = 0, max_arcs = 0;
+    for (int32_t p = 0; p < P; ++p) {
+      const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
+      if (piece_class[p] != KC_TEAM) continue;
+      stride = std::max<int64_t>(stride, np);
+      max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
+    }
+    team_waves = (int)pr.batch_wg_waves;
+    team_eu = pr.team_waves_per_eu > 0 ? 8 : 0;
+    block[KC_TEAM] = team_waves * 64;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess) {
+      (void)hipGetLastError();
+      coop = 0;
+    }
+    if (!coop) return fail(SBC_E_DEVICE, "the device does not support cooperative launches (team kernel)");
+    const int occ = occupancy_team(team_waves, team_eu);
+    if (occ <= 0) return fail(SBC_E_INVALID_ARG, "team kernel configuration cannot be resident");
+    const int nteams = (int)std::max<int64_t>(1, std::min<int64_t>(pr.team_count, (int64_t)cus * occ));
+    int g = cus * occ;
+    if (pr.slots > 0) g = (int)std::min<int64_t>(pr.slots, g);
+    g = std::max(nteams, g - g % nteams);
+    grid[KC_TEAM] = g;
+    const int64_t part_cap = max_arcs / kMsSliceArcs + 2 * kTeamHeavyMax;
+    tm.stride = stride;
+    tm.part_cap = (int32_t)part_cap;
+    const size_t T = nteams;
+    if ((e = tm_sg.alloc(T * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc team sg");
+    if ((e = tm_q.alloc(T * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc team q");
+    if ((e = tm_qm.alloc(T * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc team qm");
+    for (DevBuf* b : {&tm_vis, &tm_fa, &tm_fb, &tm_ba, &tm_bb, &tm_bc})
+      if ((e = b->alloc(T * stride * 8)) != hipSuccess) return hip_fail(e, "alloc team masks");
+    if ((e = tm_lvl.alloc(T * (stride + 3) * 4)) != hipSuccess) return hip_fail(e, "alloc team lvl");
+    if ((e = tm_part.alloc(T * part_cap * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc team part");
+    if ((e = tm_ctl.alloc(T * sizeof(TeamCtl))) != hipSuccess) return hip_fail(e, "alloc team ctl");
+    if ((e = tm_heavy.alloc(T * 2 * kTeamHeavyMax * 4)) != hipSuccess) return hip_fail(e, "alloc team heavy");
+    tm.sg = tm_sg.as<double>();
+    tm.q = tm_q.as<int32_t>();
+    tm.qm = tm_qm.as<uint64_t>();
+    tm.vis = tm_vis.as<uint64_t>();
+    tm.fa = tm_fa.as<uint64_t>();
+    tm.fb = tm_fb.as<uint64_t>();
+    tm.ba = tm_ba.as<uint64_t>();
+    tm.bb = tm_bb.as<uint64_t>();
+    tm.bc = tm_bc.as<uint64_t>();
+    tm.lvl = tm_lvl.as<int32_t>();
+    tm.part = tm_part.as<double>();
+    tm.prof = nullptr;
+    if (pr.profile_phases) {
+      if ((e = tm_prof.alloc((size_t)g * kProfCounters * 8)) != hipSuccess) return hip_fail(e, "alloc team prof");
+      tm.prof = tm_prof.as<uint64_t>();
+    }
+    for (uint64_t* p : {tm.vis, tm.fa, tm.fb, tm.ba, tm.bb, tm.bc})
+      if ((e = launch_fill_u64(p, 0, (int64_t)T * stride, own)) != hipSuccess) return hip_fail(e, "fill team");
+    targs.ctl = tm_ctl.as<TeamCtl>();
+    targs.heavy = tm_heavy.as<int32_t>();
+    targs.nteams = nteams;
+    targs.spin_ticks = (int64_t)((double)pr.team_spin_ms * c->wall_khz);
   }
   if (opt.debug_single) {
     const int64_t np = V;
@@ -352,24 +436,37 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
 sbc_status Plan::enqueue(double* out, hipStream_t s) {
   hipError_t e;
   int32_t* ctl = d_ctl.as<int32_t>();
-  int32_t* heads = ctl;            // [0..3]
-  int32_t* done = ctl + 4;         // [4..7]
-  int32_t* flags = ctl + 8;        // [8]
+  int32_t* heads = ctl + kCtlHeads;
+  int32_t* done = ctl + kCtlDone;
+  int32_t* flags = ctl + kCtlFlags;
   if ((e = launch_fill_f64(d_bcp.as<double>(), 0.0, V, s)) != hipSuccess) return hip_fail(e, "fill bcp");
-  if ((e = launch_fill_i32(ctl, 0, 16, s)) != hipSuccess) return hip_fail(e, "fill ctl");
+  if ((e = launch_fill_i32(ctl, 0, kCtlInts, s)) != hipSuccess) return hip_fail(e, "fill ctl");
+  if (ms.prof && (e = launch_fill_u64(ms.prof, 0, (int64_t)grid[KC_BATCH] * kProfCounters, s)) != hipSuccess)
+    return hip_fail(e, "fill prof");
+  if (nitems[KC_TEAM]) {
+    if ((e = launch_fill_i32((int32_t*)targs.ctl, 0, (int64_t)targs.nteams * (int64_t)(sizeof(TeamCtl) / 4), s)) !=
+        hipSuccess)
+      return hip_fail(e, "fill team ctl");
+    if (tm.prof && (e = launch_fill_u64(tm.prof, 0, (int64_t)grid[KC_TEAM] * kProfCounters, s)) != hipSuccess)
+      return hip_fail(e, "fill prof");
+  }
   DevPieces dp{d_vtx_off.as<int32_t>(), d_row.as<int32_t>(), d_col.as<int32_t>(), d_reach.as<int32_t>(),
                d_ident.as<int32_t>(), d_src.as<int32_t>(), d_bcp.as<double>(), P, (int32_t)V, (int32_t)A, 0};
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
-  // Largest classes first so the long multi-source items start early.
-  const int order[KC_COUNT] = {KC_BATCH, KC_GLOBAL, KC_LDS, KC_WAVE};
+  // Largest classes first so the long multi-source items start early.  The
+  // team kernel occupies the whole device, so the other classes follow it.
+  const int order[KC_COUNT] = {KC_TEAM, KC_BATCH, KC_GLOBAL, KC_LDS, KC_WAVE};
   for (int k : order) {
     if (!nitems[k]) continue;
     hipStream_t ks = side[k];
-    if ((e = hipStreamWaitEvent(ks, ev_fork, 0)) != hipSuccess) return hip_fail(e, "wait");
+    hipEvent_t after = (k != KC_TEAM && nitems[KC_TEAM]) ? ev_kc_end[KC_TEAM] : ev_fork;
+    if ((e = hipStreamWaitEvent(ks, after, 0)) != hipSuccess) return hip_fail(e, "wait");
     if (!use_graph && (e = hipEventRecord(ev_kc_start[k], ks)) != hipSuccess) return hip_fail(e, "event");
     QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], kArgMagic, heads + k, flags, done + k};
-    if (k == KC_BATCH) {
-      e = launch_ms(dp, qa, reach, ident, block[k] / 64, grid[k], ms, ks);
+    if (k == KC_TEAM) {
+      e = launch_team(dp, qa, reach, ident, team_waves, team_eu, grid[k], tm, targs, ks);
+    } else if (k == KC_BATCH) {
+      e = launch_ms(dp, qa, reach, ident, block[k] / 64, (int)ctx->params.batch_waves_per_eu, grid[k], ms, ks);
     } else {
       const bool lds = (k == KC_WAVE || k == KC_LDS);
       e = launch_wg(dp, qa, reach, ident, lds, block[k], grid[k], max_np[k], wg, dbg.dist ? &dbg : nullptr, ks);
@@ -388,7 +485,7 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
                        nullptr, scale, dst, s);
   }
   if (e != hipSuccess) return hip_fail(e, "launch mapback");
-  if ((e = hipMemcpyAsync(h_ctl, ctl, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s)) != hipSuccess)
+  if ((e = hipMemcpyAsync(h_ctl, ctl, sizeof(int32_t) * kCtlInts, hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e, "copy ctl");
   return SBC_OK;
 }
@@ -443,7 +540,7 @@ sbc_status Plan::sync(sbc_run_stats* st) {
   const double t0 = wall_ms();
   if ((e = hipEventSynchronize(ev_end)) != hipSuccess) return hip_fail(e, "sync");
   float ms_all = 0, ms_tr = 0, ms_mb = 0;
-  double class_ms[KC_COUNT] = {0, 0, 0, 0};
+  double class_ms[KC_COUNT] = {0, 0, 0, 0, 0};
   (void)hipEventElapsedTime(&ms_all, ev_start, ev_end);
   if (!use_graph) {
     float a = 0, b = 0;
@@ -462,7 +559,20 @@ sbc_status Plan::sync(sbc_run_stats* st) {
   } else {
     ms_tr = ms_all;
   }
-  const int32_t flags = h_ctl[8];
+  const int32_t flags = h_ctl[kCtlFlags];
+  if (ms.prof || tm.prof) {
+    h_prof.assign(kProfCounters, 0);
+    prof_slots = 0;
+    for (int k : {KC_BATCH, KC_TEAM}) {
+      uint64_t* src = (k == KC_BATCH) ? ms.prof : tm.prof;
+      if (!src || !nitems[k]) continue;
+      std::vector<uint64_t> raw((size_t)grid[k] * kProfCounters);
+      if ((e = hipMemcpy(raw.data(), src, raw.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "copy phase timers");
+      for (size_t i = 0; i < raw.size(); ++i) h_prof[i % kProfCounters] += raw[i];
+      prof_slots += grid[k];
+    }
+  }
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->ms_device = ms_all;
@@ -472,7 +582,7 @@ sbc_status Plan::sync(sbc_run_stats* st) {
     st->teps = teps;
     st->algo_bytes = algo_bytes;
     st->items = total_items;
-    st->batched_sources = sources_in[KC_BATCH];
+    st->batched_sources = sources_in[KC_BATCH] + sources_in[KC_TEAM];
     st->lds_sources = sources_in[KC_LDS] + sources_in[KC_WAVE];
     st->global_sources = sources_in[KC_GLOBAL];
     st->overflow = flags;
@@ -484,11 +594,14 @@ sbc_status Plan::sync(sbc_run_stats* st) {
       st->items_class[k] = nitems[k];
     }
   }
+  if (flags & kFlagTeamTimeout) return fail(SBC_E_DEVICE, "a team barrier wait timed out (team kernel aborted)");
   if (flags & kFlagRangeMask)
     return fail(SBC_E_DEVICE, "device-side range check failed (flags " + std::to_string(flags) + ")");
   if (flags & kFlagQueueOverflow) return fail(SBC_E_TOO_LARGE, "traversal queue overflow");
-  if (flags & kFlagSigmaOverflow) return fail(SBC_E_SIGMA_OVERFLOW, "a shortest-path count exceeded the binary64 range");  int32_t done_total = 0;
-  for (int k = 0; k < KC_COUNT; ++k) done_total += h_ctl[4 + k];
+  if (flags & kFlagSigmaOverflow)
+    return fail(SBC_E_SIGMA_OVERFLOW, "a shortest-path count exceeded the binary64 range");
+  int32_t done_total = 0;
+  for (int k = 0; k < KC_COUNT; ++k) done_total += h_ctl[kCtlDone + k];
   if (done_total != total_items)
     return fail(SBC_E_DEVICE, "work queue drained " + std::to_string(done_total) + " of " +
                                   std::to_string(total_items) + " items");

@@ -38,7 +38,8 @@ struct Params {
   int64_t wave_max_vertices = 128;    // pieces up to this size: one source per wavefront, LDS state
   int64_t lds_max_vertices = 4096;    // pieces up to this size: one source per workgroup, LDS state
   int64_t batch_min_vertices = 4097;  // pieces from this size: 64-source batches
-  int64_t batch_wg_waves = 16;        // wavefronts per multi-source workgroup
+  int64_t batch_wg_waves = 8;         // wavefronts per multi-source workgroup
+  int64_t batch_waves_per_eu = 8;     // occupancy target of the batch kernel (0, 6 or 8 waves per SIMD)
   int64_t lds_block = 256;            // threads per LDS workgroup
   int64_t lds_sources_per_item = 32;  // sources per LDS work item
   int64_t wave_sources_per_item = 64; // sources per wavefront work item
@@ -46,6 +47,12 @@ struct Params {
   int64_t cluster_sources = 1;        // breadth-first-ball source order for batches
   int64_t plain_kernel = 0;           // plain mode: 0 automatic, 1 one source per workgroup (global)
   int64_t mem_budget_mb = 0;          // traversal state budget (0: 60% of free memory)
+  int64_t profile_phases = 0;         // 1: per-phase timers in the batch kernel
+  int64_t order_plain = 0;            // 1: plain problems renumbered breadth-first
+  int64_t team_min_vertices = 16384;  // pieces from this size: team kernel (0: never)
+  int64_t team_count = 8;             // teams of the team kernel (one per XCD)
+  int64_t team_waves_per_eu = 8;      // occupancy target of the team kernel (0 or 8)
+  int64_t team_spin_ms = 20000;       // bound of one team barrier wait
 };
 
 }  // namespace sbc
@@ -55,6 +62,7 @@ struct sbc_context_s {
   hipDeviceProp_t prop{};
   int cus = 0;
   size_t lds_limit = 64 * 1024;  // dynamic LDS one workgroup may use
+  double wall_khz = 100000.0;    // device wall-clock rate
   sbc::Params params;
   std::mutex mu;
 };
@@ -69,7 +77,7 @@ struct sbc_graph_s {
 
 namespace sbc {
 
-enum KernelClass { KC_WAVE = 0, KC_LDS = 1, KC_BATCH = 2, KC_GLOBAL = 3, KC_COUNT = 4 };
+enum KernelClass { KC_WAVE = 0, KC_LDS = 1, KC_BATCH = 2, KC_GLOBAL = 3, KC_TEAM = 4, KC_COUNT = 5 };
 
 // The one-source-per-workgroup kernels (LDS and global-memory state) are
 // switched off: their first runs on the GPU ended in a memory fault whose
@@ -84,7 +92,7 @@ constexpr bool kPerSourceKernelsEnabled = false;
 #endif
 
 struct PlanOptions {
-  int force_kernel = 0;                 // 0 automatic, 1 global, 2 LDS, 3 batch
+  int force_kernel = 0;                 // 0 automatic, 1 global, 2 LDS, 3 batch, 4 team
   const int32_t* sources = nullptr;     // plain-mode source subset (host), or null
   int64_t nsrc = 0;
   bool debug_single = false;            // one source, keep per-vertex outputs
@@ -103,23 +111,30 @@ struct Plan {
   // device problem
   DevBuf d_vtx_off, d_row, d_col, d_reach, d_ident, d_src, d_bcp, d_corr, d_bcx, d_map_off, d_map_idx, d_out;
   DevBuf d_items[KC_COUNT];
-  DevBuf d_ctl;             // int32: heads[KC_COUNT], done[KC_COUNT], flags
+  DevBuf d_ctl;             // int32: heads[KC_COUNT] at 0, done[KC_COUNT] at 8, flags at 16
   int32_t* h_ctl = nullptr; // pinned copy of the control block
-  int32_t nitems[KC_COUNT] = {0, 0, 0, 0};
-  int32_t max_np[KC_COUNT] = {0, 0, 0, 0};
-  int grid[KC_COUNT] = {0, 0, 0, 0};
-  int block[KC_COUNT] = {64, 256, 1024, 256};
-  int64_t sources_in[KC_COUNT] = {0, 0, 0, 0};
+  int32_t nitems[KC_COUNT] = {0, 0, 0, 0, 0};
+  int32_t max_np[KC_COUNT] = {0, 0, 0, 0, 0};
+  int grid[KC_COUNT] = {0, 0, 0, 0, 0};
+  int block[KC_COUNT] = {64, 256, 1024, 256, 512};
+  int64_t sources_in[KC_COUNT] = {0, 0, 0, 0, 0};
   // slot state
-  DevBuf ms_sg, ms_q, ms_qm, ms_vis, ms_fa, ms_fb, ms_ba, ms_bb, ms_lvl, ms_part;
+  DevBuf ms_sg, ms_q, ms_qm, ms_vis, ms_fa, ms_fb, ms_ba, ms_bb, ms_lvl, ms_part, ms_prof;
+  std::vector<uint64_t> h_prof;  // last execution's phase timers, summed over slots
+  int64_t prof_slots = 0;        // workgroups whose timers h_prof sums
   MsState ms{};
+  // team kernel state: one slot per team, plus control blocks and split-row lists
+  DevBuf tm_sg, tm_q, tm_qm, tm_vis, tm_fa, tm_fb, tm_ba, tm_bb, tm_bc, tm_lvl, tm_part, tm_prof, tm_ctl, tm_heavy;
+  MsState tm{};
+  TeamArgs targs{};
+  int team_waves = 8, team_eu = 8;
   DevBuf wg_d, wg_sig, wg_q, wg_lvl;
   WgState wg{};
   DebugOut dbg{nullptr, nullptr, nullptr};
   DevBuf dbg_dist, dbg_sigma, dbg_delta;
   // streams and timing
   hipStream_t own = nullptr;
-  hipStream_t side[KC_COUNT] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t side[KC_COUNT] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_start = nullptr, ev_trav = nullptr, ev_end = nullptr;
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_kc_start[KC_COUNT] = {}, ev_kc_end[KC_COUNT] = {};
@@ -131,7 +146,7 @@ struct Plan {
   double* graph_out = nullptr;
   bool ran = false;
   double teps = 0, algo_bytes = 0;
-  double teps_k[KC_COUNT] = {0, 0, 0, 0}, bytes_k[KC_COUNT] = {0, 0, 0, 0};
+  double teps_k[KC_COUNT] = {0, 0, 0, 0, 0}, bytes_k[KC_COUNT] = {0, 0, 0, 0, 0};
   int64_t total_items = 0;
   double last_host_ms = 0;
 

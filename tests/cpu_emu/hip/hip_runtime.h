@@ -5,7 +5,9 @@
 // up under AddressSanitizer instead of on a GPU.  Semantics:
 //   * every "asynchronous" call executes at once, in host program order;
 //   * a kernel launch runs its blocks one after another; each block runs
-//     blockDim.x OS threads, grouped in 64-lane waves;
+//     blockDim.x OS threads, grouped in 64-lane waves; a cooperative launch
+//     runs all blocks at once (their threads together), so blocks can wait
+//     for each other;
 //   * __syncthreads is a barrier over the block, wave intrinsics (ballot,
 //     shuffles, readlane) exchange values through a per-wave buffer with a
 //     wave barrier on each side (all lanes of a wave must reach them, which the
@@ -15,6 +17,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstdint>
@@ -24,14 +27,21 @@
 #include <mutex>
 #include <thread>
 #include <vector>
+#include <utility>
+#include <memory>
 
 #define __global__
 #define __device__
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define SBC_KERNEL_BOUNDS(block, eu)
 #define __shared__ static
 #define __align__(x) alignas(x)
+
+struct uint4 {
+  unsigned x, y, z, w;
+};
 
 struct dim3 {
   unsigned x = 1, y = 1, z = 1;
@@ -138,11 +148,57 @@ void launch(dim3 grid, dim3 block, size_t dyn_bytes, K&& body) {
   }
 }
 
+// All blocks at once (cooperative launch).  Kernels launched this way keep
+// their shared state in dynamic LDS (static __shared__ would be shared by all
+// blocks here).
+template <typename K>
+void launch_all(dim3 grid, dim3 block, size_t dyn_bytes, K&& body) {
+  std::lock_guard<std::mutex> lk(launch_mu);
+  std::vector<std::unique_ptr<Block>> blks;
+  std::vector<unsigned char*> dyns;
+  for (unsigned b = 0; b < grid.x; ++b) {
+    blks.emplace_back(new Block((int)block.x));
+    unsigned char* dynp = nullptr;
+    if (dyn_bytes) {
+      dynp = (unsigned char*)std::malloc(dyn_bytes);
+      std::memset(dynp, 0xC3, dyn_bytes);
+    }
+    blks.back()->dyn = dynp;
+    dyns.push_back(dynp);
+  }
+  std::vector<std::thread> ts;
+  ts.reserve((size_t)grid.x * block.x);
+  for (unsigned b = 0; b < grid.x; ++b)
+    for (unsigned t = 0; t < block.x; ++t)
+      ts.emplace_back([&, t, b] {
+        threadIdx = dim3(t);
+        blockIdx = dim3(b);
+        blockDim = block;
+        gridDim = grid;
+        tl_block = blks[b].get();
+        body();
+      });
+  for (auto& th : ts) th.join();
+  for (auto* d : dyns) std::free(d);
+}
+
+template <typename... A, size_t... I>
+void call_with(void (*k)(A...), void** args, std::index_sequence<I...>) {
+  k(*static_cast<A*>(args[I])...);
+}
+
 }  // namespace sbc_emu
 
 #define SBC_DYNAMIC_LDS(name) unsigned char* name = sbc_emu::tl_block->dyn
 
 inline void __syncthreads() { sbc_emu::tl_block->bar.wait(); }
+
+#include <chrono>
+inline long long wall_clock64() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+             .count() /
+         10;  // 100 MHz, like the device counter
+}
 
 inline unsigned long long __ballot(int pred) {
   return sbc_emu::exchange<uint64_t>(pred ? (1ull << sbc_emu::lane()) : 0ull, [](const uint64_t* s, int n) {
@@ -189,12 +245,16 @@ namespace sbc_emu {
 template <typename T>
 inline T atomic_load(T* p) {
   T v;
-  __atomic_load(p, &v, __ATOMIC_RELAXED);
+  __atomic_load(p, &v, __ATOMIC_SEQ_CST);
   return v;
 }
 }  // namespace sbc_emu
 #define __hip_atomic_load(p, order, scope) sbc_emu::atomic_load(p)
-#define __hip_atomic_fetch_or(p, v, order, scope) __atomic_fetch_or((p), (v), __ATOMIC_RELAXED)
+#define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+#define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_SEQ_CST)
+#define __hip_atomic_fetch_or(p, v, order, scope) __atomic_fetch_or((p), (v), __ATOMIC_SEQ_CST)
+#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
 
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
 inline int atomicCAS(int* p, int cmp, int v) {
@@ -231,7 +291,11 @@ typedef struct emu_graph* hipGraph_t;
 typedef struct emu_graph_exec* hipGraphExec_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
 enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipHostMallocDefault = 0 };
-enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock = 1 };
+enum hipDeviceAttribute_t {
+  hipDeviceAttributeMaxSharedMemoryPerBlock = 1,
+  hipDeviceAttributeWallClockRate = 2,
+  hipDeviceAttributeCooperativeLaunch = 3
+};
 enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 1 };
 enum hipStreamCaptureMode { hipStreamCaptureModeThreadLocal = 1 };
 
@@ -242,7 +306,9 @@ struct hipDeviceProp_t {
 };
 
 struct emu_stream {};
-struct emu_event {};
+struct emu_event {
+  double t_ms = 0;
+};
 
 inline const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "success" : "emulated HIP error"; }
 // As in HIP: a failing call leaves its error behind until hipGetLastError()
@@ -269,7 +335,15 @@ inline hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
 // Fails like a runtime that does not know the attribute, leaving a sticky
 // error: the library must neither depend on the answer nor mistake the stale
 // error for a failure of a later kernel launch.
-inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) {
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+  if (a == hipDeviceAttributeWallClockRate) {
+    *v = 100000;  // kHz
+    return hipSuccess;
+  }
+  if (a == hipDeviceAttributeCooperativeLaunch) {
+    *v = 1;
+    return hipSuccess;
+  }
   *v = 0;
   return emu_fail(hipErrorInvalidValue);
 }
@@ -318,10 +392,13 @@ inline hipError_t hipEventDestroy(hipEvent_t e) {
   delete e;
   return hipSuccess;
 }
-inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
+  e->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  return hipSuccess;
+}
 inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
-inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
-  *ms = 0.f;
+inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+  *ms = (float)(b->t_ms - a->t_ms);
   return hipSuccess;
 }
 inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipErrorNotSupported; }
@@ -339,3 +416,10 @@ inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* nb, const vo
 }
 
 #define hipLaunchKernelGGL(K, G, B, S, ST, ...) sbc_emu::launch((G), (B), (S), [&] { K(__VA_ARGS__); })
+
+template <typename... A>
+inline hipError_t hipLaunchCooperativeKernel(void (*k)(A...), dim3 grid, dim3 block, void** args, unsigned dyn,
+                                             hipStream_t) {
+  sbc_emu::launch_all(grid, block, dyn, [&] { sbc_emu::call_with(k, args, std::index_sequence_for<A...>{}); });
+  return hipSuccess;
+}

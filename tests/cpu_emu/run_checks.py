@@ -74,6 +74,12 @@ def main(which):
                            ("rmat8", gg.rmat_decorated(scale=8, seed=3))]
             for name, g in graphs:
                 want = oracle.bc(g)
+                sbc.sbc_context_set_param(ctx.h, "order_plain", 1)
+                assert_bc_close(sbc.betweenness(g.n, g.row_ptr, g.col, mode="plain", ctx=ctx), want, 1e-9,
+                                f"{name}/plain ordered")
+                assert_bc_close(sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ops="odai", ctx=ctx), want,
+                                1e-9, f"{name}/odai")
+                sbc.sbc_context_set_param(ctx.h, "order_plain", 0)
                 for batch_min in (4097, 2):  # default routing, then every piece on the batch kernel
                     sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", batch_min)
                     for mode in ("plain", "compressed"):
@@ -82,6 +88,26 @@ def main(which):
                 sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", 4097)
                 print(f"   {name} n={g.n} ok", flush=True)
         check("whole graphs", whole)
+
+        def copybw():
+            gb = sbc.sbc_copy_bandwidth(ctx.h, 1 << 16, 2)
+            assert gb > 0
+        check("copy calibration", copybw)
+
+        def phases():
+            g = gg.rmat_decorated(scale=7, seed=3)
+            pctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4, "profile_phases": 1, "batch_min_vertices": 2})
+            G = sbc.Graph(g.n, g.row_ptr, g.col)
+            G.preprocess("dai")
+            plan = sbc.sbc_plan_create(pctx.h, G.h, sbc.SBC_COMPRESSED)
+            sbc.sbc_plan_execute(plan)
+            sbc.sbc_plan_sync(plan)
+            ph = sbc.sbc_plan_phase_profile(plan)
+            assert_bc_close(sbc.sbc_plan_result(plan, g.n), oracle.bc(g), 1e-9, "profiled run")
+            sbc.sbc_plan_destroy(plan)
+            assert ph["items"] >= 1 and ph["levels"] >= 1 and ph["entries"] >= ph["items"], ph
+            print("   phases", {k: round(v, 3) for k, v in ph.items()}, flush=True)
+        check("phase timers", phases)
     if "hubs" in which:
         def hubs():
             # a vertex with more arcs than the batch kernel's split threshold
@@ -98,6 +124,80 @@ def main(which):
             sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", 4097)
             assert_bc_close(got, want, 1e-9, "hub rows")
         check("split rows", hubs)
+    if "team" in which:
+        def team():
+            # every piece on the team kernel; 2 teams of 2 workgroups, then one
+            # team of 3 (uneven ranks), then 3 teams of one workgroup
+            for tc, slots in ((2, 0), (1, 3), (3, 0)):
+                tctx = sbc.Context(0, {"slots": slots, "batch_wg_waves": 4, "team_count": tc,
+                                       "team_min_vertices": 3})
+                sizes = (5, 65, 130) if tc == 2 or full else (65,)
+                for n in sizes:
+                    r = gg.rng(n * 11 + tc)
+                    g = gg.erdos_renyi(n, min(0.9, 6.0 / max(n - 1, 1)), int(r.integers(1 << 30)))
+                    reach, ident = gg.random_attributes(n, int(r.integers(1 << 30)), rmax=5, kmax=3)
+                    for rr, kk in ((None, None), (reach, ident)):
+                        want = oracle.bc_weighted(g.n, g.row_ptr, g.col, rr, kk)
+                        got = sbc.sbc_piece_bc(tctx.h, g.n, g.row_ptr, g.col, rr, kk, kernel=4)
+                        assert_bc_close(got, want, 1e-9, f"team piece n={n} teams={tc}")
+                if tc == 2 or full:
+                    for name, g in (("rmat6", gg.rmat_decorated(scale=6, seed=3)),
+                                    ("decorated", gg.decorated_random(30, 0.1, 8, 5, 3, 11))):
+                        want = oracle.bc(g)
+                        for mode in ("plain", "compressed"):
+                            got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=tctx)
+                            assert_bc_close(got, want, 1e-9, f"team {name}/{mode} teams={tc}")
+                print(f"   teams={tc} slots={slots} ok", flush=True)
+                tctx.close()
+        check("team kernel", team)
+
+        def team_hubs():
+            n = 1300
+            r = gg.rng(5)
+            u = np.concatenate([np.zeros(1200, np.int64), r.integers(1, n, 600)])
+            v = np.concatenate([np.arange(1, 1201), r.integers(1, n, 600)])
+            g2 = gg.csr_from_edges(n, u, v)
+            src = np.arange(0, 70, dtype=np.int32)
+            want = oracle.bc_plain(g2.n, g2.row_ptr, g2.col, sources=src)
+            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 64})
+            G = sbc.Graph(g2.n, g2.row_ptr, g2.col)
+            got = sbc.sbc_betweenness_sources(tctx.h, G.h, src)
+            assert_bc_close(got, want, 1e-9, "team hub rows")
+            tctx.close()
+        check("team split rows", team_hubs)
+
+        def team_phases():
+            g = gg.rmat_decorated(scale=7, seed=3)
+            pctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
+                                   "profile_phases": 1})
+            G = sbc.Graph(g.n, g.row_ptr, g.col)
+            G.preprocess("dai")
+            plan = sbc.sbc_plan_create(pctx.h, G.h, sbc.SBC_COMPRESSED)
+            sbc.sbc_plan_execute(plan)
+            st = sbc.sbc_plan_sync(plan)
+            ph = sbc.sbc_plan_phase_profile(plan)
+            assert_bc_close(sbc.sbc_plan_result(plan, g.n), oracle.bc(g), 1e-9, "profiled team run")
+            sbc.sbc_plan_destroy(plan)
+            assert st["items_class"][4] >= 1 and st["grid_class"][4] == 4, st
+            assert ph["items"] >= 1 and ph["entries"] >= ph["items"] and ph["team_sync_ms"] >= 0, ph
+            print("   phases", {k: round(v, 3) for k, v in ph.items()}, flush=True)
+            pctx.close()
+        check("team phase timers", team_phases)
+
+        def team_abort():
+            # no barrier waiting allowed: the team aborts, every wave leaves the
+            # kernel, and the run reports a device error instead of hanging
+            g = gg.rmat_decorated(scale=6, seed=3)
+            actx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 1, "team_min_vertices": 3,
+                                   "team_spin_ms": 0})
+            try:
+                sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ctx=actx)
+            except sbc.SbcError as e:
+                assert e.status == -8 and "team barrier" in str(e), e
+            else:
+                raise AssertionError("aborted team run reported success")
+            actx.close()
+        check("team abort path", team_abort)
     if "server" in which:
         def server():
             gs = [gg.rmat_decorated(scale=7, seed=s) for s in range(3)] + [gg.grid_deleted(side=10, seed=4)]
@@ -114,4 +214,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "server"])
+    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "server"])

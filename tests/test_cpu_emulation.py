@@ -32,7 +32,7 @@ def emu_lib():
     return build_emu.build(asan=True)
 
 
-@pytest.mark.parametrize("which", ["single", "pieces", "whole", "hubs", "server"])
+@pytest.mark.parametrize("which", ["single", "pieces", "whole", "hubs", "team", "server"])
 def test_emulated_library(emu_lib, which):
     env = dict(os.environ)
     env["LD_PRELOAD"] = _asan()

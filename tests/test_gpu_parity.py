@@ -71,7 +71,7 @@ PIECE_SIZES = [3, 5, 63, 64, 65, 130, 257, 700, 2100]
 
 
 @pytest.mark.parametrize("kernel", [pytest.param(1, marks=pytest.mark.skip(reason=PER_SOURCE_OFF)),
-                                    pytest.param(2, marks=pytest.mark.skip(reason=PER_SOURCE_OFF)), 3])
+                                    pytest.param(2, marks=pytest.mark.skip(reason=PER_SOURCE_OFF)), 3, 4])
 @pytest.mark.parametrize("n", PIECE_SIZES)
 def test_piece_kernels_weighted(ctx, kernel, n):
     """Each traversal kernel on an attributed piece vs Algorithm 2 + ident."""
@@ -202,3 +202,103 @@ def test_sigma_overflow_is_reported(ctx):
     with pytest.raises(sbc.SbcError) as ei:
         run(ctx, g, "plain")
     assert ei.value.status == -9
+
+
+# ---------------------------------------------------------------- team kernel
+# All workgroups of one XCD share one 64-source batch; pieces from
+# team_min_vertices on use it (every piece, with the threshold at 3).
+
+
+@pytest.fixture(scope="module")
+def team_ctx():
+    c = sbc.Context(0, {"team_min_vertices": 3})
+    yield c
+    c.close()
+
+
+TEAM_GRAPHS = ["path50", "cycle33", "K12", "K3,7", "disconnected", "grid30", "blocks", "rmat11", "ba2100"]
+
+
+@pytest.mark.parametrize("name", TEAM_GRAPHS)
+@pytest.mark.parametrize("mode", ["plain", "compressed"])
+def test_team_whole_graph(team_ctx, name, mode):
+    g = SMALL[name]()
+    print(f"team graph {name} n={g.n} m={g.m} mode={mode}", flush=True)
+    got = run(team_ctx, g, mode)
+    assert_bc_close(got, oracle.bc(g), RTOL, f"team {name}/{mode}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_team_decorated_random(team_ctx, seed):
+    r = gg.rng(100 + seed)
+    g = gg.decorated_random(int(r.integers(60, 400)), float(r.uniform(0.01, 0.1)), int(r.integers(0, 60)),
+                            int(r.integers(0, 40)), int(r.integers(0, 20)), 7100 + seed)
+    want = oracle.bc(g)
+    for mode in ("plain", "compressed"):
+        assert_bc_close(run(team_ctx, g, mode), want, RTOL, f"team seed={seed}/{mode}")
+
+
+def test_team_split_rows():
+    """A hub with more arcs than the split threshold: its rows are pulled in
+    slices by many waves of the team and summed afterwards."""
+    n = 3000
+    r = gg.rng(5)
+    u = np.concatenate([np.zeros(2500, np.int64), np.ones(1500, np.int64), r.integers(2, n, 4000)])
+    v = np.concatenate([np.arange(1, 2501), np.arange(1000, 2500), r.integers(2, n, 4000)])
+    g = gg.csr_from_edges(n, u, v)
+    src = gg.rng(6).choice(g.n, size=200, replace=False).astype(np.int32)
+    want = oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src)
+    c = sbc.Context(0, {"team_min_vertices": 64})
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    got = sbc.sbc_betweenness_sources(c.h, G.h, src)
+    assert_bc_close(got, want, RTOL, "team hub rows")
+    assert_bc_close(run(c, g, "compressed"), oracle.bc(g), RTOL, "team hub graph compressed")
+    c.close()
+
+
+def test_team_default_threshold_sampled_sources(ctx):
+    """A 2^15-label R-MAT graph is one piece above the default team threshold:
+    300 sampled sources through the team kernel vs Algorithm 1 on the same
+    sources."""
+    g = gg.rmat_decorated(scale=15, seed=29)
+    src = gg.rng(7).choice(g.n, size=300, replace=False).astype(np.int32)
+    want = oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    got = sbc.sbc_betweenness_sources(ctx.h, G.h, src)
+    assert_bc_close(got, want, RTOL, "team sampled sources")
+
+
+def test_team_plan_graph_replay(team_ctx):
+    g = gg.rmat_decorated(scale=11, seed=23)
+    want = oracle.bc(g)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("dai")
+    plan = sbc.sbc_plan_create(team_ctx.h, G.h, sbc.SBC_COMPRESSED)
+    try:
+        sbc.sbc_plan_execute(plan)
+        st = sbc.sbc_plan_sync(plan)
+        assert st["items_class"][4] > 0 and st["grid_class"][4] >= 8, st
+        assert_bc_close(sbc.sbc_plan_result(plan, g.n), want, RTOL, "team eager")
+        sbc.sbc_plan_use_graph(plan, True)
+        for rep in range(3):
+            sbc.sbc_plan_execute(plan)
+            sbc.sbc_plan_sync(plan)
+            assert_bc_close(sbc.sbc_plan_result(plan, g.n), want, RTOL, f"team graph replay {rep}")
+            run(team_ctx, gg.path(20), "plain")
+    finally:
+        sbc.sbc_plan_destroy(plan)
+
+
+def test_team_abort_path_reports_error():
+    """With no barrier waiting allowed, a team of several workgroups aborts at
+    its first barrier: every wave leaves the kernel and the run reports a
+    device error (forced from the host through the wait bound)."""
+    g = gg.rmat_decorated(scale=9, seed=3)
+    c = sbc.Context(0, {"team_min_vertices": 3, "team_spin_ms": 0})
+    with pytest.raises(sbc.SbcError) as ei:
+        run(c, g, "compressed")
+    assert ei.value.status == -8 and "team barrier" in str(ei.value)
+    c.close()
+    # the device is fine afterwards
+    assert_bc_close(run(sbc.Context(0), gg.grid_deleted(side=12, seed=2), "compressed"),
+                    oracle.bc(gg.grid_deleted(side=12, seed=2)), RTOL, "after abort")

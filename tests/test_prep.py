@@ -18,7 +18,7 @@ import paper_1209_6007_amd as sbc
 from tests.helpers import assert_bc_close
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-OPS = ["", "d", "a", "i", "da", "di", "ai", "dai"]
+OPS = ["", "d", "a", "i", "da", "di", "ai", "dai", "o", "odai"]
 
 
 def setup_module(_m):
@@ -187,7 +187,7 @@ def test_workload_shapes_small(name):
     else:
         g = gg.random_tree(300, 8)
     want = oracle.bc(g)
-    for ops in ("d", "da", "dai", "ai"):
+    for ops in ("d", "da", "dai", "ai", "odai"):
         got, st = compressed_via_oracle(g, ops)
         assert_bc_close(got, want, 1e-9, f"{name} ops={ops}")
 
