@@ -14,7 +14,6 @@ Prints one JSON line (see the fields below).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -45,14 +44,6 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    p = os.path.join(ROOT, "paper_1209_6007_amd", "csrc", "kernels.hip")
-    with open(p, "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload: str, kclass: int):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source."""
@@ -63,6 +54,8 @@ def load_traffic(workload: str, kclass: int):
         with open(path) as f:
             d = json.load(f)
         e = d.get(workload, {}).get(CLASS_NAMES[kclass])
+        from paper_1209_6007_amd import kernel_source_hash
+
         if not e or e.get("kernel_sha") != kernel_source_hash():
             return None
         return float(e["bytes_per_launch"])
@@ -117,7 +110,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat17", choices=sorted(WORKLOADS))
-    ap.add_argument("--ops", default="dai")
+    ap.add_argument("--ops", default="odai", help="preprocessing letters (o: per-piece BFS order, Section 4.1)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

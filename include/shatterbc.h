@@ -130,8 +130,14 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        from its highest-degree vertex (Section 4.1)
  *   "team_min_vertices"  smallest piece run by the team kernel (0: never): all
  *                        workgroups of one XCD share one 64-source batch
- *   "team_count"         teams of the team kernel (default 8, one per XCD)
+ *   "team_count"         teams of the team kernel (default 64; a multiple of 8
+ *                        puts team_count/8 teams on each of the 8 XCDs)
  *   "team_waves_per_eu"  occupancy target of the team kernel: 0 or 8
+ *   "team_local_fences"  1 (default): a team whose workgroups all run on one XCD
+ *                        synchronises through that XCD's L2 (L1 invalidation
+ *                        only); 0: agent-scope fences always
+ *   "team_split_arcs"    team kernel: rows with more arcs are pulled in slices
+ *                        of 256 arcs spread over the team (default 1024)
  *   "team_spin_ms"       bound of one team barrier wait; a longer wait aborts
  *                        the launch with SBC_E_DEVICE instead of hanging
  *                        (0: no waiting at all, which aborts any team of more
@@ -215,6 +221,12 @@ sbc_status sbc_plan_result(sbc_plan p, double* bc_host);
  * count is the length of out (at most 12 values are written).
  * Errors: SBC_E_INVALID_ARG if profiling was off for this plan. */
 sbc_status sbc_plan_phase_profile(sbc_plan p, double* out, int32_t count);
+/* Team layout of the last execution's team kernel (pieces from
+ * "team_min_vertices" on): for team t < min(cap, *nteams), sizes[t] workgroups
+ * and xcc_masks[t] the set of XCDs (bit x for hardware XCC id x) they ran on.
+ * *nteams is 0 when the plan has no team pieces.  Waits for the execution.
+ * Errors: SBC_E_INVALID_ARG (NULL outputs, or not executed yet). */
+sbc_status sbc_plan_team_layout(sbc_plan p, int32_t* sizes, int32_t* xcc_masks, int32_t cap, int32_t* nteams);
 /* Capture one execution into a HIP graph and replay it on later executes
  * (enable = 1) or go back to direct launches (enable = 0). */
 sbc_status sbc_plan_use_graph(sbc_plan p, int enable);

@@ -18,6 +18,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libshatterbc.so")
 
+
+def kernel_source_hash() -> str:
+    """Hash of the device-code sources; counter results are tied to it."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernel_types.hpp", "kernels_dev.hpp", "kernels.hip"):
+        with open(os.path.join(_HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 SBC_OK = 0
 SBC_SANITIZE = 1
 SBC_PLAIN = 0
@@ -102,6 +113,7 @@ _SIGS = {
     "sbc_plan_result": ([_vp, _f64p], ctypes.c_int32),
     "sbc_plan_use_graph": ([_vp, ctypes.c_int], ctypes.c_int32),
     "sbc_plan_phase_profile": ([_vp, _f64p, ctypes.c_int32], ctypes.c_int32),
+    "sbc_plan_team_layout": ([_vp, _i32p, _i32p, ctypes.c_int32, _i32p], ctypes.c_int32),
     "sbc_betweenness": ([_vp, _vp, ctypes.c_uint32, _f64p, ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_betweenness_device": ([_vp, _vp, ctypes.c_uint32, _vp, _vp, ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_betweenness_sources": ([_vp, _vp, ctypes.c_int64, _i32p, _f64p, ctypes.POINTER(RunStats)], ctypes.c_int32),
@@ -271,6 +283,17 @@ def sbc_plan_phase_profile(plan) -> dict:
     out = np.zeros(len(PHASE_NAMES), np.float64)
     _check(lib().sbc_plan_phase_profile(plan, out.ctypes.data_as(_f64p), len(PHASE_NAMES)))
     return dict(zip(PHASE_NAMES, out.tolist()))
+
+
+def sbc_plan_team_layout(plan, cap: int = 64):
+    """(sizes, xcc_masks) of the team kernel's teams in the last execution."""
+    sizes = np.zeros(cap, np.int32)
+    masks = np.zeros(cap, np.int32)
+    nt = np.zeros(1, np.int32)
+    _check(lib().sbc_plan_team_layout(plan, sizes.ctypes.data_as(_i32p), masks.ctypes.data_as(_i32p), cap,
+                                      nt.ctypes.data_as(_i32p)))
+    k = min(int(nt[0]), cap)
+    return sizes[:k].copy(), masks[:k].copy()
 
 
 def sbc_plan_use_graph(plan, enable: bool = True):

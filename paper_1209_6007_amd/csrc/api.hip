@@ -107,6 +107,8 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "team_count") return &p.team_count;
   if (k == "team_waves_per_eu") return &p.team_waves_per_eu;
   if (k == "team_spin_ms") return &p.team_spin_ms;
+  if (k == "team_local_fences") return &p.team_local_fences;
+  if (k == "team_split_arcs") return &p.team_split_arcs;
   return nullptr;
 }
 
@@ -120,8 +122,10 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "batch_wg_waves") ok = value == 4 || value == 8 || value == 16;
   if (k == "batch_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
   if (k == "team_waves_per_eu") ok = value == 0 || value == 8;
-  if (k == "team_count") ok = value >= 1 && value <= 64;
+  if (k == "team_count") ok = value >= 1 && value <= 1024;
   if (k == "team_spin_ms") ok = value <= 600000;
+  if (k == "team_local_fences") ok = value == 0 || value == 1;
+  if (k == "team_split_arcs") ok = value >= 64 && value <= (1 << 30);
   if (k == "lds_block") ok = value == 64 || value == 256 || value == 512 || value == 1024;
   if (k == "lds_max_vertices") ok = value >= 1 && wg_lds_bytes((int32_t)value) <= ctx->lds_limit;
   if (k == "wave_max_vertices") ok = value >= 1 && value <= 1024;
@@ -318,6 +322,26 @@ sbc_status sbc_plan_phase_profile(sbc_plan p, double* out, int32_t count) {
     const double v = (double)pl.h_prof[i];
     const bool is_time = i < kProfItems || i == kProfSync;
     out[i] = is_time ? v / pl.ctx->wall_khz / slots : v;
+  }
+  return SBC_OK;
+}
+
+sbc_status sbc_plan_team_layout(sbc_plan p, int32_t* sizes, int32_t* xcc_masks, int32_t cap, int32_t* nteams) {
+  if (!p || !nteams || cap < 0 || (cap > 0 && (!sizes || !xcc_masks))) return fail(SBC_E_INVALID_ARG, "bad argument");
+  Plan& pl = p->plan;
+  *nteams = 0;
+  if (!pl.nitems[KC_TEAM]) return SBC_OK;
+  if (!pl.ran) return fail(SBC_E_INVALID_ARG, "plan has not been executed");
+  hipError_t e = hipSetDevice(pl.ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipEventSynchronize(pl.ev_end)) != hipSuccess) return hip_fail(e, "sync");
+  std::vector<TeamCtl> c((size_t)pl.targs.nteams);
+  if ((e = hipMemcpy(c.data(), pl.targs.ctl, c.size() * sizeof(TeamCtl), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "copy team control");
+  *nteams = pl.targs.nteams;
+  for (int32_t t = 0; t < pl.targs.nteams && t < cap; ++t) {
+    sizes[t] = c[t].join;
+    xcc_masks[t] = c[t].xccmask;
   }
   return SBC_OK;
 }

@@ -7,6 +7,7 @@ namespace sbc {
 
 constexpr int kMsSliceArcs = 256;  // arcs per split slice of a long row (multi-source kernel)
 constexpr int kMsHeavyMax = 128;   // split rows per level (multi-source kernel)
+constexpr int kMsHubArcs = 1024;   // rows longer than this are split (multi-source kernels)
 
 // Kernel arguments carry this word; a kernel that sees anything else returns
 // at once instead of dereferencing pointers it cannot trust.
@@ -20,6 +21,7 @@ constexpr int32_t kFlagBadPiece = 16;       // piece offsets out of bounds or la
 constexpr int32_t kFlagBadArc = 32;         // row bounds, neighbour id or queue entry out of range
 constexpr int32_t kFlagBadSource = 64;      // a source id outside its piece
 constexpr int32_t kFlagTeamTimeout = 128;   // a team barrier wait exceeded its bound (team aborted)
+constexpr int32_t kFlagHeavyOverflow = 256; // more long rows in a level than the team's split lists hold
 constexpr int32_t kFlagRangeMask = kFlagBadItem | kFlagBadPiece | kFlagBadArc | kFlagBadSource;
 
 // Packed pieces in device memory.  Piece p owns global piece vertices
@@ -70,7 +72,8 @@ struct MsState {
   uint64_t* qm;    // [slots][stride*64]  lanes of the entry at its level
   uint64_t* vis;   // [slots][stride]     lanes that reached the vertex
   uint64_t* fa;    // [slots][stride]     frontier masks, double buffered
-  uint64_t* fb;
+  uint64_t* fb;    //                     (the team kernel rotates three)
+  uint64_t* fc;    //                     team kernel only
   uint64_t* ba;    // [slots][stride]     backward level masks, by level parity
   uint64_t* bb;    //                     (the team kernel rotates three: level mod 3)
   uint64_t* bc;    //                     team kernel only
@@ -98,29 +101,33 @@ enum ProfCounter {
   kProfCounters = 12
 };
 
-// Team kernel: the workgroups of a launch form `nteams` teams (workgroup b is
-// in team b mod nteams, the XCD the dispatcher deals it to); each team works
-// on one 64-source item at a time in one MsState slot.  TeamCtl is the team's
-// control block in global memory (zero before launch).
-constexpr int kTeamHeavyMax = 1024;  // split rows per level per team
-
+// Team kernel: the workgroups of a launch form `nteams` teams by the XCD they
+// run on (the hardware XCC id), so that the workgroups of a team share one L2;
+// each team works on one 64-source item at a time in one MsState slot.
+// TeamCtl is a team's control block in global memory (zero before launch).
 struct TeamCtl {
   int32_t arrive;    // barrier arrivals of the current phase
   int32_t gen;       // barrier generation
   int32_t abort;     // set once a barrier wait timed out
   int32_t qtail;     // entries in the team's queue
   int32_t item[2];   // items taken by the team's leader, by iteration parity
-  int32_t hcnt[3];   // heavy rows registered, by registering phase mod 3
+  int32_t hcnt[3];   // long rows registered, by registering phase mod 3
   int32_t scnt[3];   // slices registered, by registering phase mod 3
-  int32_t pad[20];   // 128 bytes
+  int32_t join;      // workgroups in the team
+  int32_t xccmask;   // XCDs the team's workgroups run on
+  int32_t xjoin;     // (block of XCD x) workgroups that arrived on XCD x
+  int32_t gjoin;     // (block 0) workgroups of the whole launch that arrived
+  int32_t pad[16];   // 128 bytes
 };
 
 struct TeamArgs {
   TeamCtl* ctl;         // [nteams]
-  int32_t* heavy;       // [nteams][2][kTeamHeavyMax]: queue index, first slice
+  int32_t* heavy;       // [nteams][2][heavy_max]: queue index, first slice
   int32_t nteams;
-  int32_t pad_;
+  int32_t heavy_max;    // long rows per level a team can register (host-sized: never exceeded)
   int64_t spin_ticks;   // bound of one barrier wait, in wall-clock ticks
+  int32_t allow_local;  // 1: teams on one XCD release without writing back L2
+  int32_t split_arcs;   // rows with more arcs are pulled in slices over the team
 };
 
 struct QueueArgs {

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void wg_kernel(DevPieces P, QueueArgs Q, WgS
 // at, so the backward sweep visits exactly the (vertex, level) pairs that
 // exist.
 // ---------------------------------------------------------------------------
-constexpr int kHubArcs = 1024;   // rows longer than this are split over all waves
+constexpr int kHubArcs = kMsHubArcs;  // rows longer than this are split over all waves
 constexpr int kSliceArcs = kMsSliceArcs;  // arcs per split slice
 constexpr int kHeavyMax = kMsHeavyMax;   // split rows per level
 
@@ -810,31 +810,54 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
 
 // ---------------------------------------------------------------------------
 // Team kernel: the same traversal as ms_kernel, for large pieces.  Instead of
-// one workgroup per 64-source item, the workgroups of a launch form teams
-// (workgroup b joins team b mod nteams, i.e. the XCD the dispatcher deals it
-// to), and all workgroups of a team work on the team's current item, with the
+// one workgroup per 64-source item, the workgroups of a launch form teams by
+// the XCD they run on (read from the hardware XCC id when the launch starts),
+// and all workgroups of a team work on the team's current item, with the
 // (vertex, level) entries of each level spread over every wave of the team.
 // One item's per-vertex lane masks (about 0.5 MB per mask for a piece of
-// 64K vertices) then stay in one L2, instead of one cold copy per workgroup.
+// 64K vertices) then stay in that XCD's L2, instead of one cold copy per
+// workgroup.
 //
-// Phases are separated by team barriers: agent-scope release, an arrival
-// counter, a spin on the generation word bounded by T.spin_ticks, and an
-// agent-scope acquire.  A timed-out wait aborts the team and raises
+// Phases are separated by team barriers: release, an arrival counter, a spin
+// on the generation word bounded by T.spin_ticks, acquire.  Acquire is an
+// agent-scope fence (it invalidates the CU's L1).  When all of a team's
+// workgroups run on one XCD (so share its L2), release only waits for the
+// wave's own stores, which the per-CU L1 writes through to that L2; a team
+// spread over several XCDs releases with an agent-scope fence, which also
+// writes back L2.  (A workgroup-scope L1 invalidate is not enough here: a
+// launch without thread-group split need not perform it.)  A timed-out wait aborts the team and raises
 // kFlagTeamTimeout, so every wave still leaves the kernel.  The kernel needs
 // all of its workgroups resident at once; the host launches it cooperatively.
 // ---------------------------------------------------------------------------
 template <int BLOCK>
 struct TeamShared {
-  int wtot[BLOCK / 64];
   int scan[BLOCK];
   int e0[BLOCK];
   uint64_t f[BLOCK];
-  int ok;
+  int ok, team, rank, tsize, local;
 };
 
+#ifndef SBC_XCD_FENCES
+// This wave's stores and atomics have reached L2.
+__device__ __forceinline__ void xcd_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Hardware id of the XCD this wave runs on.
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15; }
+// Lanes of one wave see each other's LDS writes made before this point.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+#endif
+
+constexpr int kTeamChunk = 16;  // frontier entries per wave-sized chunk of phase A
+
+// The team control block is only ever accessed with agent-scope atomics and
+// atomic loads/stores, so it is coherent whatever fences a team uses (a plain
+// store could sit in one XCD's L2 while an agent-scope load reads memory).
 template <typename T>
 __device__ __forceinline__ T ctl_load(T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void ctl_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int WAVES, int EU, bool REACH, bool IDENT>
@@ -845,15 +868,49 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
   TeamShared<BLOCK>& S = *reinterpret_cast<TeamShared<BLOCK>*>(lds_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nteams = T.nteams;
-  if (nteams < 1 || (int)gridDim.x < nteams) return;  // every workgroup takes this exit together
-  const int team = (int)blockIdx.x % nteams, rank = (int)blockIdx.x / nteams;
-  const int tsize = ((int)gridDim.x - 1 - team) / nteams + 1;  // workgroups in this team
+  if (nteams < 1 || T.heavy_max < 1) return;  // every workgroup takes this exit together
+  // Join a team by XCD: with nteams a multiple of 8, XCD x hosts teams
+  // x, x+8, ...; otherwise teams span XCDs.  Then wait until every workgroup
+  // of the launch has joined, so that team sizes are final.
+  if (tid == 0) {
+    const int x = xcc_id();
+    int team;
+    if (nteams % 8 == 0) {
+      const int k = atomicAdd(&T.ctl[x % 8].xjoin, 1);
+      team = x % 8 + 8 * (k % (nteams / 8));
+    } else {
+      team = x % nteams;
+    }
+    S.team = team;
+    S.rank = atomicAdd(&T.ctl[team].join, 1);
+    atomicOr(&T.ctl[team].xccmask, 1 << x);
+    atomicAdd(&T.ctl[0].gjoin, 1);
+    int ok = 1;
+    const long long t0 = wall_clock64();
+    while (ctl_load(&T.ctl[0].gjoin) < (int)gridDim.x) {
+      if (wall_clock64() - t0 > T.spin_ticks) {
+        raise_flag(Q.flags, kFlagTeamTimeout);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    S.ok = ok;
+    S.tsize = ctl_load(&T.ctl[team].join);
+    S.local = T.allow_local && __builtin_popcount(ctl_load(&T.ctl[team].xccmask)) == 1;
+  }
+  __syncthreads();
+  if (!S.ok) return;  // every workgroup that timed out leaves; the others time out too
+  const int team = S.team, rank = S.rank, tsize = S.tsize;
+  const bool local = S.local != 0;
   const int gwave = rank * WAVES + wave, twaves = tsize * WAVES;
   const int gthr = rank * BLOCK + tid, tthr = tsize * BLOCK;
   const bool leader = rank == 0 && tid == 0;
   TeamCtl* ctl = T.ctl + team;
-  int32_t* hv_i = T.heavy + (size_t)team * 2 * kTeamHeavyMax;  // queue index of each split row
-  int32_t* hv_off = hv_i + kTeamHeavyMax;                      // its first slice in part[]
+  const int hmax = T.heavy_max;
+  const int split = T.split_arcs;  // rows longer than this are split into slices
+  int32_t* hv_i = T.heavy + (size_t)team * 2 * hmax;  // queue index of each split row
+  int32_t* hv_off = hv_i + hmax;                      // its first slice in part[]
   const size_t slot = team;
   double* sg = st.sg + slot * (size_t)st.stride * 64;
   int32_t* q = st.q + slot * (size_t)st.stride * 64;
@@ -861,6 +918,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
   uint64_t* vis = st.vis + slot * (size_t)st.stride;
   uint64_t* bufa = st.fa + slot * (size_t)st.stride;
   uint64_t* bufb = st.fb + slot * (size_t)st.stride;
+  uint64_t* bufc = st.fc + slot * (size_t)st.stride;
   uint64_t* bm0 = st.ba + slot * (size_t)st.stride;  // backward masks of levels = 0 mod 3
   uint64_t* bm1 = st.bb + slot * (size_t)st.stride;  // ... = 1 mod 3
   uint64_t* bm2 = st.bc + slot * (size_t)st.stride;  // ... = 2 mod 3
@@ -882,7 +940,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
   // Team barrier; false once the team has been aborted.
   auto team_sync = [&](int phase) -> bool {
     mark(phase);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (local) xcd_release();
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) {
       const int arrived = __hip_atomic_fetch_add(&ctl->arrive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -901,16 +960,18 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
         }
       }
       S.ok = ctl_load(&ctl->abort) ? 0 : 1;
+      // One invalidation serves the workgroup: its waves share the CU's L1.
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      xcd_release();
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ++gen;
     mark(kProfSync);
     return S.ok != 0;
   };
 
   for (int iter = 0;; ++iter) {
-    if (leader) ctl->item[iter & 1] = atomicAdd(Q.head, 1);
+    if (leader) ctl_store(&ctl->item[iter & 1], atomicAdd(Q.head, 1));
     if (!team_sync(kProfFetch)) break;
     const int it = ctl_load(&ctl->item[iter & 1]);
     if (it < 0 || it >= Q.nitems) break;  // the same verdict in the whole team
@@ -957,73 +1018,44 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
     if (leader) {
       lvl[0] = 0;
       lvl[1] = nsrc;
-      ctl->qtail = nsrc;
-      ctl->hcnt[0] = 0;
-      ctl->scnt[0] = 0;
+      ctl_store(&ctl->qtail, nsrc);
+      ctl_store(&ctl->hcnt[0], 0);
+      ctl_store(&ctl->scnt[0], 0);
     }
     if (!team_sync(kProfFetch)) break;
 
-    uint64_t* fcur = bufa;
-    uint64_t* fnxt = bufb;
-    int qs = 0, qe = nsrc, L = 0, hstep = 0;
+    // Frontier masks rotate over three arrays: level L's in fmask(L), level
+    // L+1's built in fmask(L+1), while fmask(L+2) = fmask(L-1) is cleared of
+    // level L-1's entries.
+    auto fmask = [&](int l) { return (l % 3 == 0) ? bufa : ((l % 3 == 1) ? bufb : bufc); };
+    int qprev = 0, qs = 0, qe = nsrc, L = 0, hstep = 0;
     bool alive = true;
     // ---------------- forward sweep ----------------
+    // Per level: A (discover level L+1, finish the split rows of level L,
+    // clear level L-1's masks) | B (sigma of level L+1; long rows registered,
+    // their masks set at once) | the slices of the long rows, if any.
     while (true) {
+      uint64_t* fcur = fmask(L);
+      uint64_t* fnxt = fmask(L + 1);
+      uint64_t* fold = fmask(L + 2);
       if (leader) {  // counters of the next registering phase (last used three phases ago)
-        ctl->hcnt[(hstep + 1) % 3] = 0;
-        ctl->scnt[(hstep + 1) % 3] = 0;
+        ctl_store(&ctl->hcnt[(hstep + 1) % 3], 0);
+        ctl_store(&ctl->scnt[(hstep + 1) % 3], 0);
       }
-      // Phase A: the team's workgroups take blocks of level-L entries in turn
-      // and spread each block's arcs evenly over their threads.
-      for (int cb = qs + rank * BLOCK; cb < qe; cb += tsize * BLOCK) {
-        const int i = cb + tid;
-        int e0 = 0, deg = 0;
-        uint64_t fu = 0;
-        if (i < qe) {
-          const int32_t u = q[i];
-          if (u >= 0 && u < np) {
-            e0 = rowp[u];
-            const int32_t e1 = rowp[u + 1];
-            if (e0 >= 0 && e1 >= e0 && e1 <= narcs) {
-              deg = e1 - e0;
-              fu = qm[i];
-            } else {
-              raise_flag(Q.flags, kFlagBadArc);
-              e0 = 0;
-            }
-          } else {
-            raise_flag(Q.flags, kFlagBadArc);
-          }
-        }
-        int total;
-        const int ex = block_excl_scan<BLOCK>(deg, S.wtot, &total);
-        S.scan[tid] = ex;
-        S.e0[tid] = e0;
-        S.f[tid] = fu;
-        __syncthreads();
-        const int nv = min(BLOCK, qe - cb);
-        for (int tb = wave * 64; tb < total; tb += BLOCK) {  // wave-uniform trip count
-          const int t = tb + lane;
-          int32_t w = -1;
+      const int nhp = L > 0 ? min(ctl_load(&ctl->hcnt[(hstep + 2) % 3]), hmax) : 0;  // level L's split rows
+      // Phase A: waves take chunks of kTeamChunk level-L entries and spread
+      // each chunk's arcs over their lanes; the split rows of level L are
+      // expanded slice by slice over all waves of the team instead.
+      {
+        // Reached-first vertices get queue slots, one reservation per wave.
+        auto discover = [&](int32_t w, uint64_t fu, bool valid) {
           uint64_t nw = 0;
-          if (t < total) {
-            int lo = 0, hi = nv - 1;
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (S.scan[mid] <= t) lo = mid;
-              else hi = mid - 1;
-            }
-            w = col_load(&col[S.e0[lo] + (t - S.scan[lo])]);
-            if (w < 0 || w >= np) {
-              raise_flag(Q.flags, kFlagBadArc);
-              w = -1;
-            } else {
-              nw = S.f[lo] & ~vis[w];
-            }
+          if (valid) {
+            if (w < 0 || w >= np) raise_flag(Q.flags, kFlagBadArc);
+            else nw = fu & ~vis[w];
           }
           bool isnew = false;
           if (nw) isnew = atomicOr((unsigned long long*)&fnxt[w], (unsigned long long)nw) == 0;
-          // One queue reservation per wave for the vertices it reached first.
           const uint64_t bal = __ballot(isnew);
           if (bal) {
             const int first = __builtin_ctzll(bal);
@@ -1036,8 +1068,91 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
               else raise_flag(Q.flags, kFlagQueueOverflow);
             }
           }
+        };
+        int* wscan = S.scan + wave * 64;
+        int* we0 = S.e0 + wave * 64;
+        uint64_t* wf = S.f + wave * 64;
+        for (int cb = qs + gwave * kTeamChunk; cb < qe; cb += twaves * kTeamChunk) {
+          const int i = cb + lane;
+          int e0 = 0, deg = 0;
+          uint64_t fu = 0;
+          if (lane < kTeamChunk && i < qe) {
+            const int32_t u = q[i];
+            if (u >= 0 && u < np) {
+              e0 = rowp[u];
+              const int32_t e1 = rowp[u + 1];
+              if (e0 >= 0 && e1 >= e0 && e1 <= narcs) {
+                deg = e1 - e0;
+                fu = qm[i];
+                if (L > 0 && deg > split) deg = 0;  // expanded by slices below
+              } else {
+                raise_flag(Q.flags, kFlagBadArc);
+                e0 = 0;
+              }
+            } else {
+              raise_flag(Q.flags, kFlagBadArc);
+            }
+          }
+          const int incl = wave_incl_scan(deg, lane);
+          const int total = __builtin_amdgcn_readlane(incl, 63);
+          wscan[lane] = incl - deg;
+          we0[lane] = e0;
+          wf[lane] = fu;
+          wave_sync();
+          const int nv = min(kTeamChunk, qe - cb);
+          for (int tb = 0; tb < total; tb += 64) {  // wave-uniform trip count
+            const int t = tb + lane;
+            int32_t w = -1;
+            uint64_t f = 0;
+            if (t < total) {
+              int lo = 0, hi = nv - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (wscan[mid] <= t) lo = mid;
+                else hi = mid - 1;
+              }
+              w = col_load(&col[we0[lo] + (t - wscan[lo])]);
+              f = wf[lo];
+            }
+            discover(w, f, t < total);
+          }
+          wave_sync();
         }
-        __syncthreads();
+        for (int h = 0; h < nhp; ++h) {
+          const int i = hv_i[h];
+          if (i < 0) continue;
+          const int32_t u = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, u, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t fu = qm[i];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const int o = hv_off[h];
+          for (int sl = ((gwave - o) % twaves + twaves) % twaves; sl < ns; sl += twaves) {
+            const int32_t a = e0 + sl * kSliceArcs;
+            const int32_t b = min(e1, a + kSliceArcs);
+            for (int32_t eb = a; eb < b; eb += 64) {
+              const int32_t e = eb + lane;
+              discover(e < b ? col_load(&col[e]) : -1, fu, e < b);
+            }
+          }
+        }
+        // Sigma of level L's split rows: the sum of their slices.
+        for (int h = gwave; h < nhp; h += twaves) {
+          const int i = hv_i[h];
+          if (i < 0) continue;
+          const int32_t w = q[i];
+          int32_t e0, e1;
+          if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
+          const uint64_t need = qm[i];
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          double acc = 0.0;
+          for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
+          if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+        }
+        for (int i = qprev + gthr; i < qs; i += tthr) {  // level L-1's masks
+          const int32_t u = q[i];
+          if (u >= 0 && u < np) fold[u] = 0;
+        }
       }
       if (!team_sync(kProfPhaseA)) {
         alive = false;
@@ -1045,8 +1160,10 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       }
       const int nt = (int)min((int64_t)ctl_load(&ctl->qtail), qcap);
       if (nt == qe) break;  // the same verdict in the whole team
+      if (leader) lvl[L + 2] = nt;
       // Phase B: sigma of the new lanes, one wave per entry, spread over the
-      // team; long rows are registered for splitting.
+      // team.  Long rows are registered for splitting; their masks are set
+      // now, their sigma when the next level is discovered.
       const bool scale = IDENT && L > 0;
       const int hs = hstep % 3;
       for (int i = qe + gwave; i < nt; i += twaves) {
@@ -1054,21 +1171,22 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
         int32_t e0, e1;
         if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
         const uint64_t need = fnxt[w];
-        if (e1 - e0 > kHubArcs) {
-          int reg = 0;
+        if (e1 - e0 > split) {
           if (lane == 0) {
             const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
             const int h = atomicAdd(&ctl->hcnt[hs], 1);
             const int o = atomicAdd(&ctl->scnt[hs], ns);
-            if (h < kTeamHeavyMax && o + ns <= st.part_cap) {
+            if (h < hmax && o + ns <= st.part_cap) {
               hv_i[h] = i;
               hv_off[h] = o;
-              reg = 1;
-            } else if (h < kTeamHeavyMax) {
-              hv_i[h] = -1;
+            } else {  // the host sizes the lists for every long row of the piece
+              raise_flag(Q.flags, kFlagHeavyOverflow);
+              if (h < hmax) hv_i[h] = -1;
             }
+            vis[w] |= need;
+            qm[i] = need;
           }
-          if (__builtin_amdgcn_readfirstlane(reg)) continue;
+          continue;
         }
         const double acc = pull_row(col, e0, e1, np, fcur, need, sg, idn, scale, lane, Q.flags);
         if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
@@ -1081,7 +1199,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
         alive = false;
         break;
       }
-      const int nh = min(ctl_load(&ctl->hcnt[hs]), kTeamHeavyMax);
+      const int nh = min(ctl_load(&ctl->hcnt[hs]), hmax);
       if (nh > 0) {  // the same verdict in the whole team
         // Slice u of all registered slices goes to team wave u mod twaves.
         for (int h = 0; h < nh; ++h) {
@@ -1090,7 +1208,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           const int32_t w = q[i];
           int32_t e0, e1;
           if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-          const uint64_t need = fnxt[w];
+          const uint64_t need = qm[i];
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
           const int o = hv_off[h];
           for (int sl = ((gwave - o) % twaves + twaves) % twaves; sl < ns; sl += twaves) {
@@ -1103,45 +1221,22 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           alive = false;
           break;
         }
-        for (int h = gwave; h < nh; h += twaves) {
-          const int i = hv_i[h];
-          if (i < 0) continue;
-          const int32_t w = q[i];
-          int32_t e0, e1;
-          if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-          const uint64_t need = fnxt[w];
-          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-          double acc = 0.0;
-          for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
-          if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
-          if (lane == 0) {
-            vis[w] |= need;
-            qm[i] = need;
-          }
-        }
       }
-      // Phase C: retire level L's frontier masks; level L+1 becomes current.
-      for (int i = qs + gthr; i < qe; i += tthr) {
-        const int32_t u = q[i];
-        if (u >= 0 && u < np) fcur[u] = 0;
-      }
-      if (leader) lvl[L + 2] = nt;
-      if (!team_sync(kProfPhaseC)) {
-        alive = false;
-        break;
-      }
-      uint64_t* t = fcur;
-      fcur = fnxt;
-      fnxt = t;
+      qprev = qs;
       qs = qe;
       qe = nt;
       ++L;
       ++hstep;
     }
     if (!alive) break;
-    for (int i = qs + gthr; i < qe; i += tthr) {
-      const int32_t u = q[i];
-      if (u >= 0 && u < np) fcur[u] = 0;
+    // The last phase A finished level L's split rows and cleared level L-1's
+    // masks; clear level L's.
+    {
+      uint64_t* fcur = fmask(L);
+      for (int i = qs + gthr; i < qe; i += tthr) {
+        const int32_t u = q[i];
+        if (u >= 0 && u < np) fcur[u] = 0;
+      }
     }
     const int total = qe;
     const int Lmax = L;
@@ -1154,8 +1249,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       uint64_t* br = bmask(l + 1);
       uint64_t* bz = bmask(l + 2);
       if (leader) {
-        ctl->hcnt[(hstep + 1) % 3] = 0;
-        ctl->scnt[(hstep + 1) % 3] = 0;
+        ctl_store(&ctl->hcnt[(hstep + 1) % 3], 0);
+        ctl_store(&ctl->scnt[(hstep + 1) % 3], 0);
       }
       const int hs = hstep % 3;
       if (l + 2 <= Lmax)
@@ -1169,21 +1264,20 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
         int32_t e0, e1;
         if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
         const uint64_t amask = qm[i];
-        if (e1 - e0 > kHubArcs) {
-          int reg = 0;
+        if (e1 - e0 > split) {
           if (lane == 0) {
             const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
             const int h = atomicAdd(&ctl->hcnt[hs], 1);
             const int o = atomicAdd(&ctl->scnt[hs], ns);
-            if (h < kTeamHeavyMax && o + ns <= st.part_cap) {
+            if (h < hmax && o + ns <= st.part_cap) {
               hv_i[h] = i;
               hv_off[h] = o;
-              reg = 1;
-            } else if (h < kTeamHeavyMax) {
-              hv_i[h] = -1;
+            } else {  // the host sizes the lists for every long row of the piece
+              raise_flag(Q.flags, kFlagHeavyOverflow);
+              if (h < hmax) hv_i[h] = -1;
             }
           }
-          if (__builtin_amdgcn_readfirstlane(reg)) continue;
+          continue;
         }
         const double acc = pull_row(col, e0, e1, np, br, amask, sg, idn, false, lane, Q.flags);
         double contrib = 0.0;
@@ -1205,7 +1299,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
         alive = false;
         break;
       }
-      const int nh = min(ctl_load(&ctl->hcnt[hs]), kTeamHeavyMax);
+      const int nh = min(ctl_load(&ctl->hcnt[hs]), hmax);
       if (nh > 0) {
         for (int h = 0; h < nh; ++h) {
           const int i = hv_i[h];

@@ -97,7 +97,7 @@ size_t Plan::device_bytes() const {
   for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
                           &d_map_off, &d_map_idx, &d_out, &d_ctl, &ms_sg, &ms_q, &ms_qm, &ms_vis, &ms_fa, &ms_fb,
                           &ms_ba, &ms_bb, &ms_lvl, &ms_part, &ms_prof, &wg_d, &wg_sig, &wg_q, &wg_lvl, &tm_sg, &tm_q,
-                          &tm_qm, &tm_vis, &tm_fa, &tm_fb, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof,
+                          &tm_qm, &tm_vis, &tm_fa, &tm_fb, &tm_fc, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof,
                           &tm_ctl, &tm_heavy})
     t += b->bytes;
   for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes;
@@ -113,6 +113,21 @@ size_t ms_slot_bytes(int64_t stride, int64_t part_cap) {
          (size_t)part_cap * 64 * 8;
 }
 size_t wg_slot_bytes(int64_t stride) { return (size_t)stride * 16 + (size_t)(stride + 2) * 4; }
+
+// Long rows (more than `split` arcs) of piece p and their slices: the team
+// kernel registers at most that many per level, since a vertex has at most
+// one entry per level.
+void long_rows(const Prepared& prob, int32_t p, int64_t split, int64_t* rows, int64_t* slices) {
+  *rows = 0;
+  *slices = 0;
+  for (int32_t v = prob.vtx_off[p]; v < prob.vtx_off[p + 1]; ++v) {
+    const int64_t d = (int64_t)prob.row[v + 1] - prob.row[v];
+    if (d > split) {
+      ++*rows;
+      *slices += (d + kMsSliceArcs - 1) / kMsSliceArcs;
+    }
+  }
+}
 
 int classify(const Params& pr, int32_t np, bool plain, int force) {
   if (force == 4) return KC_TEAM;
@@ -135,7 +150,7 @@ int classify(const Params& pr, int32_t np, bool plain, int force) {
 size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
   size_t t = (size_t)prob.V() * (4 * 4 + 8 * 2) + prob.A() * 4 + (size_t)prob.n * (8 * 2 + 4) +
              prob.map_idx.size() * 4 + (size_t)prob.pieces() * 4;
-  int64_t max_batch = 0, max_batch_arcs = 0, max_glob = 0, max_team = 0, max_team_arcs = 0;
+  int64_t max_batch = 0, max_batch_arcs = 0, max_glob = 0, max_team = 0, max_team_slices = 1;
   for (int32_t p = 0; p < prob.pieces(); ++p) {
     int32_t np = prob.vtx_off[p + 1] - prob.vtx_off[p];
     const int64_t arcs = prob.row[prob.vtx_off[p + 1]] - prob.row[prob.vtx_off[p]];
@@ -145,14 +160,16 @@ size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
       max_batch_arcs = std::max<int64_t>(max_batch_arcs, arcs);
     }
     if (k == KC_TEAM) {
+      int64_t rows = 0, slices = 0;
+      long_rows(prob, p, c->params.team_split_arcs, &rows, &slices);
       max_team = std::max<int64_t>(max_team, np);
-      max_team_arcs = std::max<int64_t>(max_team_arcs, arcs);
+      max_team_slices = std::max<int64_t>(max_team_slices, slices);
     }
     if (k == KC_GLOBAL) max_glob = std::max<int64_t>(max_glob, np);
   }
   if (max_batch) t += ms_slot_bytes(max_batch, max_batch_arcs / kMsSliceArcs + 2 * kMsHeavyMax) * 4;
   if (max_team)
-    t += (ms_slot_bytes(max_team, max_team_arcs / kMsSliceArcs + 2 * kTeamHeavyMax) + (size_t)max_team * 8) *
+    t += (ms_slot_bytes(max_team, max_team_slices) + (size_t)max_team * 16) *
          std::max<int64_t>(1, c->params.team_count);
   if (max_glob) t += wg_slot_bytes(max_glob) * 16;
   return t;
@@ -362,12 +379,15 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   if (nitems[KC_TEAM]) {
     // One slot per team; the grid is every workgroup that can be resident,
     // dealt round-robin to the teams.
-    int64_t stride = 0, max_arcs = 0;
+    int64_t stride = 0, max_rows = 1, max_slices = 1;
     for (int32_t p = 0; p < P; ++p) {
       const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
       if (piece_class[p] != KC_TEAM) continue;
       stride = std::max<int64_t>(stride, np);
-      max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
+      int64_t rows = 0, slices = 0;
+      long_rows(prob, p, pr.team_split_arcs, &rows, &slices);
+      max_rows = std::max(max_rows, rows);
+      max_slices = std::max(max_slices, slices);
     }
     team_waves = (int)pr.batch_wg_waves;
     team_eu = pr.team_waves_per_eu > 0 ? 8 : 0;
@@ -380,30 +400,30 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (!coop) return fail(SBC_E_DEVICE, "the device does not support cooperative launches (team kernel)");
     const int occ = occupancy_team(team_waves, team_eu);
     if (occ <= 0) return fail(SBC_E_INVALID_ARG, "team kernel configuration cannot be resident");
-    const int nteams = (int)std::max<int64_t>(1, std::min<int64_t>(pr.team_count, (int64_t)cus * occ));
+    const int nteams = (int)std::max<int64_t>(1, pr.team_count);
     int g = cus * occ;
     if (pr.slots > 0) g = (int)std::min<int64_t>(pr.slots, g);
-    g = std::max(nteams, g - g % nteams);
     grid[KC_TEAM] = g;
-    const int64_t part_cap = max_arcs / kMsSliceArcs + 2 * kTeamHeavyMax;
+    const int64_t part_cap = max_slices;
     tm.stride = stride;
     tm.part_cap = (int32_t)part_cap;
     const size_t T = nteams;
     if ((e = tm_sg.alloc(T * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc team sg");
     if ((e = tm_q.alloc(T * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc team q");
     if ((e = tm_qm.alloc(T * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc team qm");
-    for (DevBuf* b : {&tm_vis, &tm_fa, &tm_fb, &tm_ba, &tm_bb, &tm_bc})
+    for (DevBuf* b : {&tm_vis, &tm_fa, &tm_fb, &tm_fc, &tm_ba, &tm_bb, &tm_bc})
       if ((e = b->alloc(T * stride * 8)) != hipSuccess) return hip_fail(e, "alloc team masks");
     if ((e = tm_lvl.alloc(T * (stride + 3) * 4)) != hipSuccess) return hip_fail(e, "alloc team lvl");
     if ((e = tm_part.alloc(T * part_cap * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc team part");
     if ((e = tm_ctl.alloc(T * sizeof(TeamCtl))) != hipSuccess) return hip_fail(e, "alloc team ctl");
-    if ((e = tm_heavy.alloc(T * 2 * kTeamHeavyMax * 4)) != hipSuccess) return hip_fail(e, "alloc team heavy");
+    if ((e = tm_heavy.alloc(T * 2 * (size_t)max_rows * 4)) != hipSuccess) return hip_fail(e, "alloc team heavy");
     tm.sg = tm_sg.as<double>();
     tm.q = tm_q.as<int32_t>();
     tm.qm = tm_qm.as<uint64_t>();
     tm.vis = tm_vis.as<uint64_t>();
     tm.fa = tm_fa.as<uint64_t>();
     tm.fb = tm_fb.as<uint64_t>();
+    tm.fc = tm_fc.as<uint64_t>();
     tm.ba = tm_ba.as<uint64_t>();
     tm.bb = tm_bb.as<uint64_t>();
     tm.bc = tm_bc.as<uint64_t>();
@@ -414,11 +434,14 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       if ((e = tm_prof.alloc((size_t)g * kProfCounters * 8)) != hipSuccess) return hip_fail(e, "alloc team prof");
       tm.prof = tm_prof.as<uint64_t>();
     }
-    for (uint64_t* p : {tm.vis, tm.fa, tm.fb, tm.ba, tm.bb, tm.bc})
+    for (uint64_t* p : {tm.vis, tm.fa, tm.fb, tm.fc, tm.ba, tm.bb, tm.bc})
       if ((e = launch_fill_u64(p, 0, (int64_t)T * stride, own)) != hipSuccess) return hip_fail(e, "fill team");
     targs.ctl = tm_ctl.as<TeamCtl>();
     targs.heavy = tm_heavy.as<int32_t>();
     targs.nteams = nteams;
+    targs.heavy_max = (int32_t)max_rows;
+    targs.allow_local = pr.team_local_fences ? 1 : 0;
+    targs.split_arcs = (int32_t)pr.team_split_arcs;
     targs.spin_ticks = (int64_t)((double)pr.team_spin_ms * c->wall_khz);
   }
   if (opt.debug_single) {
@@ -598,6 +621,7 @@ sbc_status Plan::sync(sbc_run_stats* st) {
   if (flags & kFlagRangeMask)
     return fail(SBC_E_DEVICE, "device-side range check failed (flags " + std::to_string(flags) + ")");
   if (flags & kFlagQueueOverflow) return fail(SBC_E_TOO_LARGE, "traversal queue overflow");
+  if (flags & kFlagHeavyOverflow) return fail(SBC_E_DEVICE, "more long rows in a level than the split lists hold");
   if (flags & kFlagSigmaOverflow)
     return fail(SBC_E_SIGMA_OVERFLOW, "a shortest-path count exceeded the binary64 range");
   int32_t done_total = 0;

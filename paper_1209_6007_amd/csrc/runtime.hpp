@@ -50,9 +50,11 @@ struct Params {
   int64_t profile_phases = 0;         // 1: per-phase timers in the batch kernel
   int64_t order_plain = 0;            // 1: plain problems renumbered breadth-first
   int64_t team_min_vertices = 16384;  // pieces from this size: team kernel (0: never)
-  int64_t team_count = 8;             // teams of the team kernel (one per XCD)
+  int64_t team_count = 64;            // teams of the team kernel (a multiple of 8: that many per XCD / 8)
   int64_t team_waves_per_eu = 8;      // occupancy target of the team kernel (0 or 8)
   int64_t team_spin_ms = 20000;       // bound of one team barrier wait
+  int64_t team_local_fences = 1;      // 1: teams on one XCD fence through L2 only
+  int64_t team_split_arcs = 1024;     // team kernel: rows with more arcs are split into slices
 };
 
 }  // namespace sbc
@@ -124,7 +126,8 @@ struct Plan {
   int64_t prof_slots = 0;        // workgroups whose timers h_prof sums
   MsState ms{};
   // team kernel state: one slot per team, plus control blocks and split-row lists
-  DevBuf tm_sg, tm_q, tm_qm, tm_vis, tm_fa, tm_fb, tm_ba, tm_bb, tm_bc, tm_lvl, tm_part, tm_prof, tm_ctl, tm_heavy;
+  DevBuf tm_sg, tm_q, tm_qm, tm_vis, tm_fa, tm_fb, tm_fc, tm_ba, tm_bb, tm_bc, tm_lvl, tm_part, tm_prof, tm_ctl,
+      tm_heavy;
   MsState tm{};
   TeamArgs targs{};
   int team_waves = 8, team_eu = 8;

@@ -255,12 +255,20 @@ inline T atomic_load(T* p) {
 #define __hip_atomic_fetch_or(p, v, order, scope) __atomic_fetch_or((p), (v), __ATOMIC_SEQ_CST)
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+// Team-kernel fences and ids: blocks 2k and 2k+1 run on XCD k mod 8 (so teams
+// of one XCD and teams spread over several both occur with few blocks); lanes
+// of a wave meet at a wave barrier.
+#define SBC_XCD_FENCES 1
+inline void xcd_release() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline int xcc_id() { return (int)((blockIdx.x / 2) % 8); }
+inline void wave_sync() { sbc_emu::wave().bar.wait(); }
 
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
 inline int atomicCAS(int* p, int cmp, int v) {
   __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
   return cmp;
 }
+inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 inline unsigned long long atomicOr(unsigned long long* p, unsigned long long v) {
   return __atomic_fetch_or(p, v, __ATOMIC_RELAXED);
 }

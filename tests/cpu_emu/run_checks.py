@@ -126,9 +126,11 @@ def main(which):
         check("split rows", hubs)
     if "team" in which:
         def team():
-            # every piece on the team kernel; 2 teams of 2 workgroups, then one
-            # team of 3 (uneven ranks), then 3 teams of one workgroup
-            for tc, slots in ((2, 0), (1, 3), (3, 0)):
+            # every piece on the team kernel.  Emulated XCD k hosts blocks 2k and
+            # 2k+1: 2 teams of 2 workgroups on one XCD each; one team of 3 over
+            # two XCDs (uneven ranks, agent-scope fences); 8 teams by XCD, of
+            # which 6 stay empty
+            for tc, slots in ((2, 0), (1, 3), (8, 0)):
                 tctx = sbc.Context(0, {"slots": slots, "batch_wg_waves": 4, "team_count": tc,
                                        "team_min_vertices": 3})
                 sizes = (5, 65, 130) if tc == 2 or full else (65,)
@@ -163,6 +165,15 @@ def main(which):
             G = sbc.Graph(g2.n, g2.row_ptr, g2.col)
             got = sbc.sbc_betweenness_sources(tctx.h, G.h, src)
             assert_bc_close(got, want, 1e-9, "team hub rows")
+            tctx.close()
+            # a low split threshold: many rows of every level are pulled in slices
+            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
+                                   "team_split_arcs": 64})
+            for g in (gg.rmat_decorated(scale=8, seed=5), gg.complete_bipartite(70, 90)):
+                want = oracle.bc(g)
+                for mode in ("plain", "compressed"):
+                    got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=tctx)
+                    assert_bc_close(got, want, 1e-9, f"team split 64 n={g.n}/{mode}")
             tctx.close()
         check("team split rows", team_hubs)
 
