@@ -63,19 +63,26 @@ def load_traffic(workload: str, kclass: int):
         return None
 
 
+def progress(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def timed_run(sbc, ctx, G, mode, steps, warmup, use_graph=False):
+    name = "plain" if mode == sbc.SBC_PLAIN else "compressed"
     plan = sbc.sbc_plan_create(ctx.h, G.h, mode)
     try:
         if use_graph:
             sbc.sbc_plan_use_graph(plan, True)
-        for _ in range(warmup):
+        for i in range(warmup):
             sbc.sbc_plan_execute(plan)
-            sbc.sbc_plan_sync(plan)
+            st = sbc.sbc_plan_sync(plan)
+            progress(f"{name} warm-up {i}: {st['ms_device']:.1f} ms")
         stats = []
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for i in range(steps):
             sbc.sbc_plan_execute(plan)
             stats.append(sbc.sbc_plan_sync(plan))
+            progress(f"{name} step {i}: {stats[-1]['ms_device']:.1f} ms")
         t1 = time.perf_counter()
         n, _ = sbc.sbc_graph_info(G.h)
         result = sbc.sbc_plan_result(plan, n)
@@ -104,6 +111,66 @@ def cpu_baseline(g, seconds_target: float, threads: int):
                       f"{dt:.1f} s, scaled to sources x edges / s"}
 
 
+def serving(args, sbc):
+    """Continuous batching of a Poisson stream of BC jobs (R-MAT or deleted-edge
+    grid, fair coin): latency from arrival to result on the host."""
+    import threading
+    from concurrent.futures import ProcessPoolExecutor
+
+    reqs = gg.serving_stream(n_requests=args.requests, rate_per_s=args.rate)
+    progress(f"serving: generating {len(reqs)} request graphs")
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        graphs = list(ex.map(gg.request_graph, reqs, chunksize=4))
+    params = {"team_min_vertices": 0}
+    for kv in args.param:
+        k, v = kv.split("=")
+        params[k] = int(v)
+    ctx = sbc.Context(0, params)
+    Gs = [sbc.Graph(g.n, g.row_ptr, g.col) for g in graphs]
+    srv = sbc.sbc_server_create(ctx.h, args.slots, 0)
+    jobs = [None] * len(reqs)
+    progress("serving: stream starts")
+    t0 = time.perf_counter()
+
+    def submit_all():
+        for i, r in enumerate(reqs):
+            d = t0 + r.arrival_s - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            jobs[i] = sbc.sbc_server_submit(srv, Gs[i].h, sbc.SBC_COMPRESSED)
+
+    th = threading.Thread(target=submit_all)
+    th.start()
+    lat, work = [], 0.0
+    last_done = t0
+    for i in range(len(reqs)):
+        while jobs[i] is None:
+            time.sleep(0.001)
+        bc, st = sbc.sbc_job_wait(jobs[i], graphs[i].n)
+        sbc.sbc_job_release(jobs[i])
+        lat.append(st["latency_ms"])
+        work += float(graphs[i].n) * float(graphs[i].m)
+        last_done = max(last_done, time.perf_counter())
+        if i % 50 == 49:
+            progress(f"serving: {i + 1} jobs done, p50 so far {np.percentile(lat, 50):.1f} ms")
+    th.join()
+    makespan = last_done - t0
+    sbc.sbc_server_destroy(srv)
+    ctx.close()
+    span = reqs[-1].arrival_s - reqs[0].arrival_s
+    offered = work / max(span, 1e-9) / 1e9
+    out = {"metric": "serving latency (arrival to result on host) and aggregate GTEPS",
+           "value": work / makespan / 1e9, "unit": "GTEPS", "n_gpus": 1, "higher_is_better": True,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "max_ms": float(np.max(lat)), "mean_ms": float(np.mean(lat)), "requests": len(reqs),
+           "rate_per_s": args.rate, "makespan_s": makespan, "offered_gteps": offered,
+           "config": {"workload": f"Poisson stream at {args.rate}/s of {len(reqs)} jobs: R-MAT scale 10..15 "
+                                  "(decorated) or deleted-edge grid side 32..256, fair coin", "slots": args.slots,
+                      "params": params},
+           "data": "synthetic", "dtype": "f64"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +186,11 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--phases", action="store_true", help="one extra compressed run with in-kernel phase timers")
     ap.add_argument("--calibrate", action="store_true", help="also time a plain streaming copy (1 GiB)")
+    ap.add_argument("--autotune", action="store_true", help="apply the autotuner's choice (tuned now unless cached)")
+    ap.add_argument("--serving", action="store_true", help="run the Poisson serving stream instead")
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split of the work items is "
@@ -127,17 +199,26 @@ def main():
 
     import paper_1209_6007_amd as sbc  # no torch in this process: the library syncs its own streams
 
+    if args.serving:
+        serving(args, sbc)
+        return
     desc, make = WORKLOADS[args.workload]
     g = make()
     params = {}
     for kv in args.param:
         k, v = kv.split("=")
         params[k] = int(v)
-    ctx = sbc.Context(0, params)
     G = sbc.Graph(g.n, g.row_ptr, g.col)
     t0 = time.perf_counter()
     prep = G.preprocess(args.ops)
     prep_s = time.perf_counter() - t0
+    tuned = None
+    if args.autotune:
+        from paper_1209_6007_amd import autotune
+
+        tuned = autotune.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, log=progress)
+        params = dict(tuned, **params)
+    ctx = sbc.Context(0, params)
     nm = float(g.n) * float(g.m)
 
     t_c, st_c, res_c = timed_run(sbc, ctx, G, sbc.SBC_COMPRESSED, args.steps, args.warmup, args.graph)
@@ -155,7 +236,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": g.n, "m": g.m, "ops": args.ops,
-                   "parallelism": "single GPU", "hip_graph": bool(args.graph)},
+                   "parallelism": "single GPU", "hip_graph": bool(args.graph), "params": params,
+                   "autotuned": tuned is not None},
     }
     last = st_c[-1]
     # dominant traversal kernel of the compressed step
@@ -203,6 +285,7 @@ def main():
         sbc.sbc_plan_destroy(plan)
         pctx.close()
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle) starts")
         threads = min(os.cpu_count() or 1, 16)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds, threads)
     ctx.close()

@@ -51,7 +51,7 @@ typedef int32_t sbc_status;
 
 /* run modes (bit flags) */
 #define SBC_PLAIN 0u         /* Algorithm 1 on the whole graph, no preprocessing */
-#define SBC_COMPRESSED 1u    /* preprocess (default "dai" unless the graph was preprocessed) */
+#define SBC_COMPRESSED 1u    /* preprocess (default "odai" unless the graph was preprocessed) */
 #define SBC_UNORDERED 2u     /* report unordered-pair scores (Eq. (1) halved) */
 
 typedef struct sbc_context_s* sbc_context;
@@ -138,6 +138,12 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        only); 0: agent-scope fences always
  *   "team_split_arcs"    team kernel: rows with more arcs are pulled in slices
  *                        of 256 arcs spread over the team (default 1024)
+ *   "team_max_levels"    pieces whose breadth-first depth from their highest-degree
+ *                        vertex exceeds this stay on the one-workgroup batch
+ *                        kernel (0: no limit)
+ *   "sample_items"       tuning only (0: off): plans run an evenly spaced sample of
+ *                        at most this many work items per kernel class, so the
+ *                        result covers only those items' sources
  *   "team_spin_ms"       bound of one team barrier wait; a longer wait aborts
  *                        the launch with SBC_E_DEVICE instead of hanging
  *                        (0: no waiting at all, which aborts any team of more
@@ -191,7 +197,7 @@ sbc_status sbc_graph_export(sbc_graph g, int32_t* vtx_off, int32_t* row, int32_t
 /* ------------------------------------------------------------------- plan */
 
 /* Upload the problem of `mode` (SBC_PLAIN or SBC_COMPRESSED; SBC_COMPRESSED on
- * a graph not yet preprocessed runs "dai" first) to the device, build the
+ * a graph not yet preprocessed runs "odai" first) to the device, build the
  * work queue and allocate traversal state.  The plan keeps everything
  * resident, so repeated executions touch no host memory.
  * Errors: SBC_E_NO_DEVICE, SBC_E_OOM, SBC_E_DEVICE, SBC_E_INVALID_ARG. */

@@ -109,6 +109,8 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "team_spin_ms") return &p.team_spin_ms;
   if (k == "team_local_fences") return &p.team_local_fences;
   if (k == "team_split_arcs") return &p.team_split_arcs;
+  if (k == "team_max_levels") return &p.team_max_levels;
+  if (k == "sample_items") return &p.sample_items;
   return nullptr;
 }
 
@@ -256,7 +258,7 @@ static sbc_status ensure_problem(sbc_context ctx, sbc_graph g, uint32_t mode, Pr
                                  const Prepared** out) {
   if (mode & SBC_COMPRESSED) {
     if (!g->prepared) {
-      sbc_status rc = sbc_graph_preprocess(g, "dai", nullptr);
+      sbc_status rc = sbc_graph_preprocess(g, "odai", nullptr);
       if (rc != SBC_OK) return rc;
     }
     *out = &g->prep;

@@ -426,6 +426,113 @@ __device__ __forceinline__ bool wave_row(const int32_t* __restrict__ rowp, int32
   return true;
 }
 
+// Entries one wave pulls together (pull_entries).
+#ifndef SBC_PULL_GROUP
+#define SBC_PULL_GROUP 1
+#endif
+constexpr int kGroup = SBC_PULL_GROUP;
+
+// pull_row for G entries whose rows have at most 64 arcs (deg[e] = 0 skips
+// entry e): their neighbour ids, then their neighbour masks, then their rows
+// are loaded together, so that a wave has G dependent chains in flight instead
+// of one.  acc[e] gets the sum for entry e, in a fixed order.
+template <int G>
+__device__ __forceinline__ void pull_group(const int32_t* __restrict__ col, const int32_t (&e0)[G],
+                                           const int32_t (&deg)[G], const int32_t np, uint64_t* __restrict__ mk,
+                                           const uint64_t (&need)[G], const double* __restrict__ sg,
+                                           const int32_t* __restrict__ idn, const bool scale, const int lane,
+                                           int32_t* flags, double (&acc)[G]) {
+  int32_t c[G];
+  uint64_t m[G], act[G];
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    c[e] = -1;
+    if (lane < deg[e]) {
+      c[e] = col_load(&col[e0[e] + lane]);
+      if (c[e] < 0 || c[e] >= np) {
+        raise_flag(flags, kFlagBadArc);
+        c[e] = -1;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < G; ++e) m[e] = c[e] >= 0 ? group_load(&mk[c[e]]) & need[e] : 0;
+  uint64_t any = 0;
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    act[e] = __ballot(m[e] != 0);
+    any |= act[e];
+    acc[e] = 0.0;
+  }
+  // Rounds: up to two neighbours of every entry per round.
+  while (any) {  // wave-uniform
+    double x[G][2];
+#pragma unroll
+    for (int e = 0; e < G; ++e)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        x[e][j] = 0.0;
+        if (act[e]) {  // wave-uniform
+          const int k = __builtin_ctzll(act[e]);
+          act[e] &= act[e] - 1;
+          const int32_t u = __builtin_amdgcn_readlane(c[e], k);
+          const uint64_t mu = readlane64(m[e], k);
+          if ((mu >> lane) & 1) x[e][j] = row_load(&sg[(size_t)u * 64 + lane]);
+          if (scale) x[e][j] *= (double)idn[u];
+        }
+      }
+    any = 0;
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      acc[e] += x[e][0] + x[e][1];
+      any |= act[e];
+    }
+  }
+}
+
+// One wave's pull of the entries [i0, min(i0 + G, iend)) of the queue q.
+// need_of(i, v) gives an entry's lanes; defer(i, v, e0, e1, need) takes a row
+// the caller splits over many waves and returns true (it must be
+// wave-uniform); finish(i, v, need, acc) consumes each other entry's sum.
+// Rows of at most 64 arcs go through pull_group together, longer ones through
+// pull_row one by one.
+template <int G, typename NeedOf, typename Defer, typename Finish>
+__device__ __forceinline__ void pull_entries(const int i0, const int iend, const int32_t* __restrict__ q,
+                                             const int32_t* __restrict__ rowp, const int32_t np, const int32_t narcs,
+                                             const int32_t* __restrict__ col, uint64_t* __restrict__ mk,
+                                             const double* __restrict__ sg, const int32_t* __restrict__ idn,
+                                             const bool scale, const int lane, int32_t* flags, NeedOf need_of,
+                                             Defer defer, Finish finish) {
+  int32_t v[G], e0[G], e1[G], dg[G];
+  uint64_t need[G];
+  bool live[G];
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    live[e] = false;
+    v[e] = 0;
+    e0[e] = 0;
+    e1[e] = 0;
+    need[e] = 0;
+    const int i = i0 + e;
+    if (i < iend) {
+      v[e] = q[i];
+      if (wave_row(rowp, v[e], np, narcs, &e0[e], &e1[e], flags, lane)) {
+        need[e] = need_of(i, v[e]);
+        live[e] = !defer(i, v[e], e0[e], e1[e], need[e]);
+      }
+    }
+    dg[e] = (live[e] && e1[e] - e0[e] <= 64) ? e1[e] - e0[e] : 0;
+  }
+  double acc[G];
+  pull_group<G>(col, e0, dg, np, mk, need, sg, idn, scale, lane, flags, acc);
+#pragma unroll
+  for (int e = 0; e < G; ++e)
+    if (live[e] && e1[e] - e0[e] > 64) acc[e] = pull_row(col, e0[e], e1[e], np, mk, need[e], sg, idn, scale, lane, flags);
+#pragma unroll
+  for (int e = 0; e < G; ++e)
+    if (live[e]) finish(i0 + e, v[e], need[e], acc[e]);
+}
+
 // EU > 0 asks the compiler for at least EU resident waves per SIMD (it then
 // keeps the kernel within 512/EU VGPRs); the kernel is latency-bound, so more
 // waves in flight can matter more than registers.
@@ -592,34 +699,35 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       // Phase B: sigma of the new lanes, one wave per vertex, pulling from the
       // neighbours on level L (their frontier masks); long rows are deferred.
       const bool scale = IDENT && L > 0;
-      for (int i = qe + wave; i < nt; i += WAVES) {
-        const int32_t w = q[i];
-        int32_t e0, e1;
-        if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-        const uint64_t need = group_load(&fnxt[w]);  // built with atomicOr
-        if (e1 - e0 > kHubArcs) {
-          int reg = 0;
-          if (lane == 0) {
-            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-            const int h = atomicAdd(&s_nheavy, 1);
-            const int o = atomicAdd(&s_nslices, ns);
-            if (h < kHeavyMax && o + ns <= st.part_cap) {
-              s_heavy[h] = i;
-              s_hoff[h] = o;
-              reg = 1;
-            } else if (h < kHeavyMax) {
-              s_heavy[h] = -1;
-            }
-          }
-          if (__builtin_amdgcn_readfirstlane(reg)) continue;
-        }
-        const double acc = pull_row(col, e0, e1, np, fcur, need, sg, idn, scale, lane, Q.flags);
-        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+      auto defer_long = [&](int i, int32_t, int32_t e0, int32_t e1, uint64_t) -> bool {
+        if (e1 - e0 <= kHubArcs) return false;
+        int reg = 0;
         if (lane == 0) {
-          vis[w] |= need;
-          qm[i] = need;
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const int h = atomicAdd(&s_nheavy, 1);
+          const int o = atomicAdd(&s_nslices, ns);
+          if (h < kHeavyMax && o + ns <= st.part_cap) {
+            s_heavy[h] = i;
+            s_hoff[h] = o;
+            reg = 1;
+          } else if (h < kHeavyMax) {
+            s_heavy[h] = -1;
+          }
         }
-      }
+        return __builtin_amdgcn_readfirstlane(reg) != 0;
+      };
+      for (int i0 = qe + wave * kGroup; i0 < nt; i0 += WAVES * kGroup)
+        pull_entries<kGroup>(
+            i0, nt, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags,
+            [&](int, int32_t w) { return group_load(&fnxt[w]); },  // built with atomicOr
+            defer_long,
+            [&](int i, int32_t w, uint64_t need, double acc) {
+              if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+              if (lane == 0) {
+                vis[w] |= need;
+                qm[i] = need;
+              }
+            });
       __syncthreads();
       mark(kProfPhaseB);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -698,43 +806,43 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       }
       __syncthreads();
       const int b = lvl[l], e = lvl[l + 1];
-      for (int i = b + wave; i < e; i += WAVES) {
-        const int32_t v = q[i];
-        int32_t e0, e1;
-        if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-        const uint64_t amask = qm[i];
-        if (e1 - e0 > kHubArcs) {
-          int reg = 0;
-          if (lane == 0) {
-            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-            const int h = atomicAdd(&s_nheavy, 1);
-            const int o = atomicAdd(&s_nslices, ns);
-            if (h < kHeavyMax && o + ns <= st.part_cap) {
-              s_heavy[h] = i;
-              s_hoff[h] = o;
-              reg = 1;
-            } else if (h < kHeavyMax) {
-              s_heavy[h] = -1;
-            }
-          }
-          if (__builtin_amdgcn_readfirstlane(reg)) continue;
-        }
-        const double acc = pull_row(col, e0, e1, np, br, amask, sg, idn, false, lane, Q.flags);
-        double contrib = 0.0;
-        if ((amask >> lane) & 1) {
-          const size_t at = (size_t)v * 64 + lane;
-          const double sv = sg[at];
-          const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-          sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-          contrib = wsrc * dv;
-          if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
-        }
-        contrib = wave_sum(contrib);
+      auto defer_long_b = [&](int i, int32_t, int32_t e0, int32_t e1, uint64_t) -> bool {
+        if (e1 - e0 <= kHubArcs) return false;
+        int reg = 0;
         if (lane == 0) {
-          atomicAdd(&bcp[v], contrib);
-          bw[v] = amask;
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const int h = atomicAdd(&s_nheavy, 1);
+          const int o = atomicAdd(&s_nslices, ns);
+          if (h < kHeavyMax && o + ns <= st.part_cap) {
+            s_heavy[h] = i;
+            s_hoff[h] = o;
+            reg = 1;
+          } else if (h < kHeavyMax) {
+            s_heavy[h] = -1;
+          }
         }
-      }
+        return __builtin_amdgcn_readfirstlane(reg) != 0;
+      };
+      for (int i0 = b + wave * kGroup; i0 < e; i0 += WAVES * kGroup)
+        pull_entries<kGroup>(
+            i0, e, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags,
+            [&](int i, int32_t) { return qm[i]; }, defer_long_b,
+            [&](int, int32_t v, uint64_t amask, double acc) {
+              double contrib = 0.0;
+              if ((amask >> lane) & 1) {
+                const size_t at = (size_t)v * 64 + lane;
+                const double sv = sg[at];
+                const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+                sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+                contrib = wsrc * dv;
+                if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+              }
+              contrib = wave_sum(contrib);
+              if (lane == 0) {
+                atomicAdd(&bcp[v], contrib);
+                bw[v] = amask;
+              }
+            });
       __syncthreads();
       mark(kProfBackward);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -1166,35 +1274,40 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       // now, their sigma when the next level is discovered.
       const bool scale = IDENT && L > 0;
       const int hs = hstep % 3;
-      for (int i = qe + gwave; i < nt; i += twaves) {
-        const int32_t w = q[i];
-        int32_t e0, e1;
-        if (!wave_row(rowp, w, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-        const uint64_t need = fnxt[w];
-        if (e1 - e0 > split) {
-          if (lane == 0) {
-            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-            const int h = atomicAdd(&ctl->hcnt[hs], 1);
-            const int o = atomicAdd(&ctl->scnt[hs], ns);
-            if (h < hmax && o + ns <= st.part_cap) {
-              hv_i[h] = i;
-              hv_off[h] = o;
-            } else {  // the host sizes the lists for every long row of the piece
-              raise_flag(Q.flags, kFlagHeavyOverflow);
-              if (h < hmax) hv_i[h] = -1;
-            }
-            vis[w] |= need;
-            qm[i] = need;
-          }
-          continue;
+      // Register a long row for splitting (the host sizes the lists for every
+      // long row of the piece, so registration cannot run out).
+      auto register_long = [&](int i, int32_t e0, int32_t e1) {
+        const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+        const int h = atomicAdd(&ctl->hcnt[hs], 1);
+        const int o = atomicAdd(&ctl->scnt[hs], ns);
+        if (h < hmax && o + ns <= st.part_cap) {
+          hv_i[h] = i;
+          hv_off[h] = o;
+        } else {
+          raise_flag(Q.flags, kFlagHeavyOverflow);
+          if (h < hmax) hv_i[h] = -1;
         }
-        const double acc = pull_row(col, e0, e1, np, fcur, need, sg, idn, scale, lane, Q.flags);
-        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
-        if (lane == 0) {
-          vis[w] |= need;
-          qm[i] = need;
-        }
-      }
+      };
+      for (int i0 = qe + gwave * kGroup; i0 < nt; i0 += twaves * kGroup)
+        pull_entries<kGroup>(
+            i0, nt, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags,
+            [&](int, int32_t w) { return fnxt[w]; },
+            [&](int i, int32_t w, int32_t e0, int32_t e1, uint64_t need) -> bool {
+              if (e1 - e0 <= split) return false;
+              if (lane == 0) {
+                register_long(i, e0, e1);
+                vis[w] |= need;
+                qm[i] = need;
+              }
+              return true;
+            },
+            [&](int i, int32_t w, uint64_t need, double acc) {
+              if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+              if (lane == 0) {
+                vis[w] |= need;
+                qm[i] = need;
+              }
+            });
       if (!team_sync(kProfPhaseB)) {
         alive = false;
         break;
@@ -1259,42 +1372,42 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           if (u >= 0 && u < np) bz[u] = 0;
         }
       const int b = lvl[l], e = lvl[l + 1];
-      for (int i = b + gwave; i < e; i += twaves) {
-        const int32_t v = q[i];
-        int32_t e0, e1;
-        if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
-        const uint64_t amask = qm[i];
-        if (e1 - e0 > split) {
-          if (lane == 0) {
-            const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-            const int h = atomicAdd(&ctl->hcnt[hs], 1);
-            const int o = atomicAdd(&ctl->scnt[hs], ns);
-            if (h < hmax && o + ns <= st.part_cap) {
-              hv_i[h] = i;
-              hv_off[h] = o;
-            } else {  // the host sizes the lists for every long row of the piece
-              raise_flag(Q.flags, kFlagHeavyOverflow);
-              if (h < hmax) hv_i[h] = -1;
-            }
-          }
-          continue;
-        }
-        const double acc = pull_row(col, e0, e1, np, br, amask, sg, idn, false, lane, Q.flags);
-        double contrib = 0.0;
-        if ((amask >> lane) & 1) {
-          const size_t at = (size_t)v * 64 + lane;
-          const double sv = sg[at];
-          const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-          sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-          contrib = wsrc * dv;
-          if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
-        }
-        contrib = wave_sum(contrib);
-        if (lane == 0) {
-          atomicAdd(&bcp[v], contrib);
-          bw[v] = amask;
-        }
-      }
+      for (int i0 = b + gwave * kGroup; i0 < e; i0 += twaves * kGroup)
+        pull_entries<kGroup>(
+            i0, e, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags,
+            [&](int i, int32_t) { return qm[i]; },
+            [&](int i, int32_t, int32_t e0, int32_t e1, uint64_t) -> bool {
+              if (e1 - e0 <= split) return false;
+              if (lane == 0) {
+                const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+                const int h = atomicAdd(&ctl->hcnt[hs], 1);
+                const int o = atomicAdd(&ctl->scnt[hs], ns);
+                if (h < hmax && o + ns <= st.part_cap) {
+                  hv_i[h] = i;
+                  hv_off[h] = o;
+                } else {  // the host sizes the lists for every long row of the piece
+                  raise_flag(Q.flags, kFlagHeavyOverflow);
+                  if (h < hmax) hv_i[h] = -1;
+                }
+              }
+              return true;
+            },
+            [&](int, int32_t v, uint64_t amask, double acc) {
+              double contrib = 0.0;
+              if ((amask >> lane) & 1) {
+                const size_t at = (size_t)v * 64 + lane;
+                const double sv = sg[at];
+                const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
+                sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
+                contrib = wsrc * dv;
+                if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+              }
+              contrib = wave_sum(contrib);
+              if (lane == 0) {
+                atomicAdd(&bcp[v], contrib);
+                bw[v] = amask;
+              }
+            });
       if (!team_sync(kProfBackward)) {
         alive = false;
         break;

@@ -129,6 +129,33 @@ void long_rows(const Prepared& prob, int32_t p, int64_t split, int64_t* rows, in
   }
 }
 
+// Levels of a breadth-first search of piece p from its highest-degree vertex
+// (a lower bound on the piece's diameter, and at least half of it).
+int64_t bfs_depth(const Prepared& prob, int32_t p) {
+  const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
+  if (np <= 0) return 0;
+  int32_t start = 0;
+  for (int32_t v = 1; v < np; ++v)
+    if (prob.row[vb + v + 1] - prob.row[vb + v] > prob.row[vb + start + 1] - prob.row[vb + start]) start = v;
+  std::vector<int32_t> d(np, -1), q;
+  q.reserve(np);
+  q.push_back(start);
+  d[start] = 0;
+  int64_t depth = 0;
+  for (size_t h = 0; h < q.size(); ++h) {
+    const int32_t v = q[h];
+    for (int32_t e = prob.row[vb + v]; e < prob.row[vb + v + 1]; ++e) {
+      const int32_t w = prob.col[e];
+      if (w >= 0 && w < np && d[w] < 0) {
+        d[w] = d[v] + 1;
+        depth = std::max<int64_t>(depth, d[w]);
+        q.push_back(w);
+      }
+    }
+  }
+  return depth;
+}
+
 int classify(const Params& pr, int32_t np, bool plain, int force) {
   if (force == 4) return KC_TEAM;
   if (force == 3) return KC_BATCH;
@@ -234,6 +261,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
 
   // Work items by kernel class.
   std::vector<WorkItem> items[KC_COUNT];
+  std::vector<double> item_teps[KC_COUNT], item_bytes[KC_COUNT];
   std::vector<int> piece_class(P, -1);
   teps = 0;
   algo_bytes = 0;
@@ -241,6 +269,11 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
     const int64_t arcs = (int64_t)prob.row[vb + np] - prob.row[vb];
     int k = classify(pr, np, plain, opt.force_kernel);
+    // Deep pieces (many BFS levels) pay a team barrier per phase and level:
+    // with team_max_levels set they stay on the one-workgroup kernel.
+    if (k == KC_TEAM && opt.force_kernel != 4 && pr.team_max_levels > 0 &&
+        bfs_depth(prob, p) > pr.team_max_levels)
+      k = KC_BATCH;
     if (k == KC_LDS || k == KC_WAVE) {
       if (wg_lds_bytes(np) > c->lds_limit) {
         if (opt.force_kernel == 2) return fail(SBC_E_INVALID_ARG, "piece too large for the LDS kernel");
@@ -256,17 +289,40 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (k == KC_WAVE) chunk = (int32_t)pr.wave_sources_per_item;
     if (k == KC_LDS) chunk = (int32_t)pr.lds_sources_per_item;
     if (k == KC_BATCH || k == KC_TEAM) chunk = 64;
-    for (int32_t s0 = 0; s0 < nsrc; s0 += chunk) items[k].push_back({p, s0, std::min(nsrc, s0 + chunk), k});
-    max_np[k] = std::max(max_np[k], np);
-    sources_in[k] += nsrc;
-    teps += (double)nsrc * (double)arcs * 0.5;
     const double per = 8.0 * arcs + (plain ? 48.0 : (reach || ident ? 56.0 : 48.0)) * np;
-    algo_bytes += (double)nsrc * per;
-    teps_k[k] += (double)nsrc * (double)arcs * 0.5;
-    bytes_k[k] += (double)nsrc * per;
+    for (int32_t s0 = 0; s0 < nsrc; s0 += chunk) {
+      const int32_t s1 = std::min(nsrc, s0 + chunk);
+      items[k].push_back({p, s0, s1, k});
+      item_teps[k].push_back((double)(s1 - s0) * (double)arcs * 0.5);
+      item_bytes[k].push_back((double)(s1 - s0) * per);
+    }
+    max_np[k] = std::max(max_np[k], np);
   }
+  // Tuning runs may keep an evenly spaced sample of each class's items (the
+  // result then covers only their sources).
   total_items = 0;
   for (int k = 0; k < KC_COUNT; ++k) {
+    if (pr.sample_items > 0 && (int64_t)items[k].size() > pr.sample_items) {
+      const size_t total = items[k].size(), keep = (size_t)pr.sample_items;
+      std::vector<WorkItem> kept;
+      std::vector<double> kt, kb;
+      for (size_t j = 0; j < keep; ++j) {
+        const size_t idx = j * total / keep;
+        kept.push_back(items[k][idx]);
+        kt.push_back(item_teps[k][idx]);
+        kb.push_back(item_bytes[k][idx]);
+      }
+      items[k].swap(kept);
+      item_teps[k].swap(kt);
+      item_bytes[k].swap(kb);
+    }
+    for (size_t j = 0; j < items[k].size(); ++j) {
+      sources_in[k] += items[k][j].s1 - items[k][j].s0;
+      teps_k[k] += item_teps[k][j];
+      bytes_k[k] += item_bytes[k][j];
+    }
+    teps += teps_k[k];
+    algo_bytes += bytes_k[k];
     nitems[k] = (int32_t)items[k].size();
     total_items += nitems[k];
   }

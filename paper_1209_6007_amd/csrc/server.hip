@@ -69,7 +69,7 @@ static void run_job(sbc_server s, sbc_job j) {
     const Prepared* prob = nullptr;
     Prepared plain;
     if (j->mode & SBC_COMPRESSED) {
-      if (!j->g->prepared) rc = sbc_graph_preprocess(j->g, "dai", nullptr);
+      if (!j->g->prepared) rc = sbc_graph_preprocess(j->g, "odai", nullptr);
       prob = &j->g->prep;
     } else {
       plain_problem(j->g->g, &plain);

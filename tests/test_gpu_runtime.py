@@ -1,0 +1,75 @@
+"""GPU: autotuner choices, sampled tuning plans and the serving loop, through
+the C interface, against the oracle."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_1209_6007_amd as sbc
+from paper_1209_6007_amd import autotune as at
+from tests.helpers import assert_bc_close
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-9
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle():
+    oracle.build(force=False)
+
+
+def test_autotune_choice_gives_exact_result(tmp_path):
+    g = gg.rmat_decorated(scale=12, seed=31)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+    path = str(tmp_path / "tune.json")
+    best = at.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, path=path, log=print)
+    entry = next(iter(at.load_cache(path).values()))
+    assert len(entry["candidates"]) == len(at.CANDIDATES)
+    assert entry["params"] == best and all(c["estimated_ms"] > 0 for c in entry["candidates"])
+    # cached: no new timing
+    assert at.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, path=path) == best
+    ctx = sbc.Context(0)
+    at.apply(ctx, best)
+    assert_bc_close(sbc.sbc_betweenness(ctx.h, G.h, sbc.SBC_COMPRESSED), oracle.bc(g), RTOL, "autotuned")
+    ctx.close()
+
+
+@pytest.mark.parametrize("team", [0, 3])
+def test_sampled_plan_runs_the_sample(team):
+    """sample_items keeps an evenly spaced subset of each class's items (here 3
+    of the plain piece's 64-source items)."""
+    g = gg.rmat_decorated(scale=11, seed=5)
+    ctx = sbc.Context(0, {"sample_items": 3, "team_min_vertices": team})
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    plan = sbc.sbc_plan_create(ctx.h, G.h, sbc.SBC_PLAIN)
+    sbc.sbc_plan_execute(plan)
+    st = sbc.sbc_plan_sync(plan)
+    got = sbc.sbc_plan_result(plan, g.n)
+    sbc.sbc_plan_destroy(plan)
+    assert st["items"] == 3 and st["batched_sources"] == 3 * 64
+    # a partial sum of Algorithm 1: nonnegative, finite, below the full result
+    full = oracle.bc(g)
+    assert np.all(np.isfinite(got)) and np.all(got >= 0) and got.sum() > 0
+    assert np.all(got <= full * (1 + 1e-9) + 1e-9)
+    ctx.close()
+
+
+def test_server_mix_equals_alone():
+    """Jobs of different sizes and shapes served together give the results of
+    the same jobs run alone (and the oracle's)."""
+    graphs = [gg.rmat_decorated(scale=s, seed=40 + s) for s in (9, 10, 11)] + \
+             [gg.grid_deleted(side=sd, seed=50 + sd) for sd in (20, 33, 47)] + [gg.ba_pendant_triangles()]
+    ctx = sbc.Context(0)
+    alone = [sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ctx=ctx) for g in graphs]
+    Gs = [sbc.Graph(g.n, g.row_ptr, g.col) for g in graphs]
+    srv = sbc.sbc_server_create(ctx.h, 3, 0)
+    jobs = [sbc.sbc_server_submit(srv, G.h, sbc.SBC_COMPRESSED) for G in Gs]
+    for g, j, a in zip(graphs, jobs, alone):
+        got, st = sbc.sbc_job_wait(j, g.n)
+        sbc.sbc_job_release(j)
+        assert st["latency_ms"] > 0
+        assert_bc_close(got, a, 1e-12, "mix vs alone")
+        assert_bc_close(got, oracle.bc(g), RTOL, "mix vs oracle")
+    sbc.sbc_server_destroy(srv)
+    ctx.close()
