@@ -122,7 +122,9 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "batch_wg_waves"     wavefronts per workgroup of the multi-source kernel (4, 8, 16)
  *   "batch_waves_per_eu" occupancy target of the multi-source kernel: 0 (compiler default), 6 or 8 waves per SIMD
  *   "slots"              resident workgroups per traversal kernel (0 = auto)
- *   "cluster_sources"    1: order batch sources by breadth-first balls
+ *   "cluster_sources"    batch source order: 0 piece order, 1 breadth-first balls,
+ *                        2 (default) vertices grouped by a common neighbour of
+ *                        degree >= 32 first, then balls
  *   "plain_kernel"       plain mode: 0 automatic, 1 one source per workgroup
  *   "mem_budget_mb"      traversal-state budget of a plan (0: 60% of free memory)
  *   "profile_phases"     1: plans keep per-phase timers of the batch and team kernels

@@ -20,11 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libshatterbc.so")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device-code sources; counter results are tied to it."""
+    """Hash of the sources that decide what a launch does (device code, and
+    the host code that orders and batches its work); counter results are
+    tied to it."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("kernel_types.hpp", "kernels_dev.hpp", "kernels.hip"):
+    for f in ("kernel_types.hpp", "kernels_dev.hpp", "kernels.hip", "prep.cpp", "runtime.hip"):
         with open(os.path.join(_HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -125,6 +125,7 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "batch_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
   if (k == "team_waves_per_eu") ok = value == 0 || value == 8;
   if (k == "team_count") ok = value >= 1 && value <= 1024;
+  if (k == "cluster_sources") ok = value >= 0 && value <= 2;
   if (k == "team_spin_ms") ok = value <= 600000;
   if (k == "team_local_fences") ok = value == 0 || value == 1;
   if (k == "team_split_arcs") ok = value >= 64 && value <= (1 << 30);

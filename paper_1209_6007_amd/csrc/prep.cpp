@@ -687,18 +687,45 @@ void order_pieces(Prepared* P) {
   P->src_order.swap(src2);
 }
 
-void cluster_sources(Prepared* P, int group) {
-  // Greedy balls: from the lowest unassigned vertex, breadth-first search over
-  // unassigned vertices until `group` are collected; then start a new ball.
+void cluster_sources(Prepared* P, int group, int mode) {
+  // Mode 1: greedy balls: from the lowest unassigned vertex, breadth-first
+  // search over unassigned vertices until `group` are collected; then start a
+  // new ball.  Mode 2 first groups every vertex whose highest-degree
+  // neighbour (itself included) has degree >= kHubDegree by that hub, hubs in
+  // id order, so that a batch's sources are all within one hop of a common
+  // vertex; the remaining vertices form balls as in mode 1.
+  constexpr int32_t kHubDegree = 32;
   const int32_t np_total = P->pieces();
-  std::vector<int32_t> q;
+  std::vector<int32_t> q, hub, idx;
   std::vector<uint8_t> used;
   std::vector<int32_t> mark;
   for (int32_t p = 0; p < np_total; ++p) {
     const int32_t vb = P->vtx_off[p], np = P->vtx_off[p + 1] - vb;
     used.assign(np, 0);
     mark.assign(np, -1);
-    int32_t out = 0, next_seed = 0, ball = 0;
+    int32_t out = 0;
+    if (mode == 2) {
+      auto deg = [&](int32_t v) { return P->row[vb + v + 1] - P->row[vb + v]; };
+      hub.assign(np, -1);
+      idx.clear();
+      for (int32_t v = 0; v < np; ++v) {
+        int32_t best = v;
+        for (int32_t e = P->row[vb + v]; e < P->row[vb + v + 1]; ++e) {
+          const int32_t w = P->col[e];
+          if (deg(w) > deg(best) || (deg(w) == deg(best) && w < best)) best = w;
+        }
+        if (deg(best) >= kHubDegree) {
+          hub[v] = best;
+          idx.push_back(v);
+        }
+      }
+      std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return hub[a] < hub[b]; });
+      for (int32_t v : idx) {
+        used[v] = 1;
+        P->src_order[vb + out++] = v;
+      }
+    }
+    int32_t next_seed = 0, ball = 0;
     while (out < np) {
       while (used[next_seed]) ++next_seed;
       q.clear();

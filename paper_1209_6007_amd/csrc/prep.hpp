@@ -70,9 +70,11 @@ int preprocess(const HostGraph& g, const std::string& ops, Prepared* out, PrepSt
 // The plain problem: the whole graph as one piece, no attributes.
 void plain_problem(const HostGraph& g, Prepared* out);
 
-// Source order inside each piece: greedy breadth-first balls of `group`
-// vertices, so that the sources of one multi-source batch lie close together.
-void cluster_sources(Prepared* p, int group);
+// Source order inside each piece, so that the sources of one multi-source
+// batch lie close together: mode 1, greedy breadth-first balls of `group`
+// vertices; mode 2, vertices grouped by a common high-degree neighbour first
+// (few distinct distances to any vertex), then balls for the rest.
+void cluster_sources(Prepared* p, int group, int mode);
 
 // Vertex ordering of Section 4.1 ("o"), per piece: local ids are renumbered
 // in breadth-first order from the piece's highest-degree vertex, so that a

@@ -233,7 +233,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   if (opt.sources || opt.debug_single || (pr.cluster_sources && prob_in.pieces() > 0)) {
     local = prob_in;
     probp = &local;
-    if (pr.cluster_sources && !opt.sources && !opt.debug_single) cluster_sources(&local, 64);
+    if (pr.cluster_sources && !opt.sources && !opt.debug_single) cluster_sources(&local, 64, (int)pr.cluster_sources);
     if (opt.sources) {
       // plain graph, one piece: the listed sources first
       std::vector<uint8_t> seen(local.n, 0);

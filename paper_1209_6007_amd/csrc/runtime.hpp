@@ -44,7 +44,7 @@ struct Params {
   int64_t lds_sources_per_item = 32;  // sources per LDS work item
   int64_t wave_sources_per_item = 64; // sources per wavefront work item
   int64_t slots = 0;                  // resident workgroups per kernel (0: from occupancy)
-  int64_t cluster_sources = 1;        // breadth-first-ball source order for batches
+  int64_t cluster_sources = 2;        // batch source order: 0 as is, 1 balls, 2 common-hub groups then balls
   int64_t plain_kernel = 0;           // plain mode: 0 automatic, 1 one source per workgroup (global)
   int64_t mem_budget_mb = 0;          // traversal state budget (0: 60% of free memory)
   int64_t profile_phases = 0;         // 1: per-phase timers in the batch kernel
