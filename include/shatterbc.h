@@ -139,7 +139,7 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        synchronises through that XCD's L2 (L1 invalidation
  *                        only); 0: agent-scope fences always
  *   "team_split_arcs"    team kernel: rows with more arcs are pulled in slices
- *                        of 256 arcs spread over the team (default 1024)
+ *                        of 256 arcs spread over the team (default 2048)
  *   "team_max_levels"    pieces whose breadth-first depth from their highest-degree
  *                        vertex exceeds this stay on the one-workgroup batch
  *                        kernel (0: no limit)

@@ -117,7 +117,9 @@ struct TeamCtl {
   int32_t xccmask;   // XCDs the team's workgroups run on
   int32_t xjoin;     // (block of XCD x) workgroups that arrived on XCD x
   int32_t gjoin;     // (block 0) workgroups of the whole launch that arrived
-  int32_t pad[16];   // 128 bytes
+  int32_t grab[3];   // entries handed out in a pull phase, by registering phase mod 3
+  int32_t agrab[2];  // frontier entries handed out in a discovery phase, by level parity
+  int32_t pad[11];   // 128 bytes
 };
 
 struct TeamArgs {

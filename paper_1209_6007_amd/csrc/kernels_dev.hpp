@@ -464,13 +464,15 @@ __device__ __forceinline__ void pull_group(const int32_t* __restrict__ col, cons
     any |= act[e];
     acc[e] = 0.0;
   }
-  // Rounds: up to two neighbours of every entry per round.
+  // Rounds: up to kPer neighbours of every entry per round (four rows in
+  // flight for a single entry, two per entry for groups).
+  constexpr int kPer = G == 1 ? 4 : 2;
   while (any) {  // wave-uniform
-    double x[G][2];
+    double x[G][kPer];
 #pragma unroll
     for (int e = 0; e < G; ++e)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < kPer; ++j) {
         x[e][j] = 0.0;
         if (act[e]) {  // wave-uniform
           const int k = __builtin_ctzll(act[e]);
@@ -484,7 +486,10 @@ __device__ __forceinline__ void pull_group(const int32_t* __restrict__ col, cons
     any = 0;
 #pragma unroll
     for (int e = 0; e < G; ++e) {
-      acc[e] += x[e][0] + x[e][1];
+      double r = 0.0;
+#pragma unroll
+      for (int j = 0; j < kPer; j += 2) r += x[e][j] + x[e][j + 1];
+      acc[e] += r;
       any |= act[e];
     }
   }
@@ -955,6 +960,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 #endif
 
 constexpr int kTeamChunk = 16;  // frontier entries per wave-sized chunk of phase A
+constexpr int kTeamGrab = 4;    // entries a wave takes at a time in the pull phases
 
 // The team control block is only ever accessed with agent-scope atomics and
 // atomic loads/stores, so it is coherent whatever fences a team uses (a plain
@@ -1078,6 +1084,21 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
     return S.ok != 0;
   };
 
+  // Entries [b, e) of a pull phase, handed to the team's waves kTeamGrab at a
+  // time from the phase's counter; a wave asks for its next share before it
+  // works on the current one.  body(i0, i1) pulls entries [i0, i1).
+  auto grabbed = [&](int slot, int b, int e, auto&& body) {
+    int next = 0;
+    if (lane == 0) next = atomicAdd(&ctl->grab[slot], kTeamGrab);
+    while (true) {
+      const int i0 = b + __builtin_amdgcn_readfirstlane(next);
+      if (i0 >= e) break;
+      if (lane == 0) next = atomicAdd(&ctl->grab[slot], kTeamGrab);
+      const int i1 = min(e, i0 + kTeamGrab);
+      for (int i = i0; i < i1; i += kGroup) body(i, i1);
+    }
+  };
+
   for (int iter = 0;; ++iter) {
     if (leader) ctl_store(&ctl->item[iter & 1], atomicAdd(Q.head, 1));
     if (!team_sync(kProfFetch)) break;
@@ -1129,6 +1150,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       ctl_store(&ctl->qtail, nsrc);
       ctl_store(&ctl->hcnt[0], 0);
       ctl_store(&ctl->scnt[0], 0);
+      ctl_store(&ctl->grab[0], 0);
+      ctl_store(&ctl->agrab[0], 0);
     }
     if (!team_sync(kProfFetch)) break;
 
@@ -1149,11 +1172,13 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       if (leader) {  // counters of the next registering phase (last used three phases ago)
         ctl_store(&ctl->hcnt[(hstep + 1) % 3], 0);
         ctl_store(&ctl->scnt[(hstep + 1) % 3], 0);
+        ctl_store(&ctl->grab[(hstep + 1) % 3], 0);
       }
       const int nhp = L > 0 ? min(ctl_load(&ctl->hcnt[(hstep + 2) % 3]), hmax) : 0;  // level L's split rows
-      // Phase A: waves take chunks of kTeamChunk level-L entries and spread
-      // each chunk's arcs over their lanes; the split rows of level L are
-      // expanded slice by slice over all waves of the team instead.
+      // Phase A: waves take chunks of kTeamChunk level-L entries (from the
+      // phase's counter, so that fast waves take more) and spread each
+      // chunk's arcs over their lanes; the split rows of level L are expanded
+      // slice by slice over all waves of the team instead.
       {
         // Reached-first vertices get queue slots, one reservation per wave.
         auto discover = [&](int32_t w, uint64_t fu, bool valid) {
@@ -1180,7 +1205,12 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
         int* wscan = S.scan + wave * 64;
         int* we0 = S.e0 + wave * 64;
         uint64_t* wf = S.f + wave * 64;
-        for (int cb = qs + gwave * kTeamChunk; cb < qe; cb += twaves * kTeamChunk) {
+        int next = 0;
+        if (lane == 0) next = atomicAdd(&ctl->agrab[L & 1], kTeamChunk);
+        while (true) {
+          const int cb = qs + __builtin_amdgcn_readfirstlane(next);
+          if (cb >= qe) break;
+          if (lane == 0) next = atomicAdd(&ctl->agrab[L & 1], kTeamChunk);
           const int i = cb + lane;
           int e0 = 0, deg = 0;
           uint64_t fu = 0;
@@ -1268,7 +1298,10 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       }
       const int nt = (int)min((int64_t)ctl_load(&ctl->qtail), qcap);
       if (nt == qe) break;  // the same verdict in the whole team
-      if (leader) lvl[L + 2] = nt;
+      if (leader) {
+        lvl[L + 2] = nt;
+        ctl_store(&ctl->agrab[(L + 1) & 1], 0);  // for the next discovery phase
+      }
       // Phase B: sigma of the new lanes, one wave per entry, spread over the
       // team.  Long rows are registered for splitting; their masks are set
       // now, their sigma when the next level is discovered.
@@ -1288,9 +1321,9 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           if (h < hmax) hv_i[h] = -1;
         }
       };
-      for (int i0 = qe + gwave * kGroup; i0 < nt; i0 += twaves * kGroup)
+      grabbed(hs, qe, nt, [&](int i0, int i1) {
         pull_entries<kGroup>(
-            i0, nt, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags,
+            i0, i1, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags,
             [&](int, int32_t w) { return fnxt[w]; },
             [&](int i, int32_t w, int32_t e0, int32_t e1, uint64_t need) -> bool {
               if (e1 - e0 <= split) return false;
@@ -1308,6 +1341,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
                 qm[i] = need;
               }
             });
+      });
       if (!team_sync(kProfPhaseB)) {
         alive = false;
         break;
@@ -1364,6 +1398,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       if (leader) {
         ctl_store(&ctl->hcnt[(hstep + 1) % 3], 0);
         ctl_store(&ctl->scnt[(hstep + 1) % 3], 0);
+        ctl_store(&ctl->grab[(hstep + 1) % 3], 0);
       }
       const int hs = hstep % 3;
       if (l + 2 <= Lmax)
@@ -1372,9 +1407,9 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           if (u >= 0 && u < np) bz[u] = 0;
         }
       const int b = lvl[l], e = lvl[l + 1];
-      for (int i0 = b + gwave * kGroup; i0 < e; i0 += twaves * kGroup)
+      grabbed(hs, b, e, [&](int i0, int i1) {
         pull_entries<kGroup>(
-            i0, e, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags,
+            i0, i1, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags,
             [&](int i, int32_t) { return qm[i]; },
             [&](int i, int32_t, int32_t e0, int32_t e1, uint64_t) -> bool {
               if (e1 - e0 <= split) return false;
@@ -1408,6 +1443,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
                 bw[v] = amask;
               }
             });
+      });
       if (!team_sync(kProfBackward)) {
         alive = false;
         break;
