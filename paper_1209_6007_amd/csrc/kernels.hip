@@ -1,4 +1,7 @@
 // Host launchers of the traversal kernels (device code in kernels_dev.hpp).
+// SBC_EMU_FEW_VARIANTS (set only by the CPU-emulated test build) keeps the
+// shapes its checks use: 4-wave batch and team workgroups, 64- and 256-thread
+// per-source workgroups.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -147,8 +150,10 @@ int occupancy_wg(int block, bool lds, size_t dyn) {
   switch (block) {
     case 64: return lds ? occ_wg_b<64, true>(dyn) : occ_wg_b<64, false>(0);
     case 256: return lds ? occ_wg_b<256, true>(dyn) : occ_wg_b<256, false>(0);
+#ifndef SBC_EMU_FEW_VARIANTS
     case 512: return lds ? occ_wg_b<512, true>(dyn) : occ_wg_b<512, false>(0);
     case 1024: return lds ? occ_wg_b<1024, true>(dyn) : occ_wg_b<1024, false>(0);
+#endif
     default: return 1;
   }
 }
@@ -159,12 +164,14 @@ int occupancy_ms(int waves, int eu) {
     case 400: return occ_ms_w<4, 0>();
     case 406: return occ_ms_w<4, 6>();
     case 408: return occ_ms_w<4, 8>();
+#ifndef SBC_EMU_FEW_VARIANTS
     case 800: return occ_ms_w<8, 0>();
     case 806: return occ_ms_w<8, 6>();
     case 808: return occ_ms_w<8, 8>();
     case 1600: return occ_ms_w<16, 0>();
     case 1606: return occ_ms_w<16, 6>();
     case 1608: return occ_ms_w<16, 8>();
+#endif
     default: return 1;
   }
 }
@@ -179,12 +186,14 @@ hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
     case 256:
       return lds ? launch_wg_b<256, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
                  : launch_wg_b<256, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
+#ifndef SBC_EMU_FEW_VARIANTS
     case 512:
       return lds ? launch_wg_b<512, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
                  : launch_wg_b<512, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
     case 1024:
       return lds ? launch_wg_b<1024, true>(P, Q, reach, ident, grid, max_np, st, d, stream)
                  : launch_wg_b<1024, false>(P, Q, reach, ident, grid, max_np, st, d, stream);
+#endif
     default:
       return hipErrorInvalidValue;
   }
@@ -194,8 +203,10 @@ hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
                      const MsState& st, hipStream_t stream) {
   switch (waves) {
     case 4: return launch_ms_e<4>(P, Q, reach, ident, eu, grid, st, stream);
+#ifndef SBC_EMU_FEW_VARIANTS
     case 8: return launch_ms_e<8>(P, Q, reach, ident, eu, grid, st, stream);
     case 16: return launch_ms_e<16>(P, Q, reach, ident, eu, grid, st, stream);
+#endif
     default: return hipErrorInvalidValue;
   }
 }
@@ -203,10 +214,12 @@ int occupancy_team(int waves, int eu) {
   switch (waves * 100 + eu) {
     case 400: return occ_team_w<4, 0>();
     case 408: return occ_team_w<4, 8>();
+#ifndef SBC_EMU_FEW_VARIANTS
     case 800: return occ_team_w<8, 0>();
     case 808: return occ_team_w<8, 8>();
     case 1600: return occ_team_w<16, 0>();
     case 1608: return occ_team_w<16, 8>();
+#endif
     default: return 0;
   }
 }
@@ -216,10 +229,12 @@ hipError_t launch_team(const DevPieces& P, const QueueArgs& Q, bool reach, bool 
   switch (waves * 100 + eu) {
     case 400: return launch_team_w<4, 0>(P, Q, reach, ident, grid, st, T, stream);
     case 408: return launch_team_w<4, 8>(P, Q, reach, ident, grid, st, T, stream);
+#ifndef SBC_EMU_FEW_VARIANTS
     case 800: return launch_team_w<8, 0>(P, Q, reach, ident, grid, st, T, stream);
     case 808: return launch_team_w<8, 8>(P, Q, reach, ident, grid, st, T, stream);
     case 1600: return launch_team_w<16, 0>(P, Q, reach, ident, grid, st, T, stream);
     case 1608: return launch_team_w<16, 8>(P, Q, reach, ident, grid, st, T, stream);
+#endif
     default: return hipErrorInvalidValue;
   }
 }

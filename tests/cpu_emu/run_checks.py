@@ -159,9 +159,10 @@ def main(which):
             u = np.concatenate([np.zeros(1200, np.int64), r.integers(1, n, 600)])
             v = np.concatenate([np.arange(1, 1201), r.integers(1, n, 600)])
             g2 = gg.csr_from_edges(n, u, v)
-            src = np.arange(0, 70, dtype=np.int32)
+            src = np.arange(0, 16, dtype=np.int32)
             want = oracle.bc_plain(g2.n, g2.row_ptr, g2.col, sources=src)
-            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 64})
+            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 64,
+                                   "team_split_arcs": 512})
             G = sbc.Graph(g2.n, g2.row_ptr, g2.col)
             got = sbc.sbc_betweenness_sources(tctx.h, G.h, src)
             assert_bc_close(got, want, 1e-9, "team hub rows")
@@ -169,7 +170,7 @@ def main(which):
             # a low split threshold: many rows of every level are pulled in slices
             tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
                                    "team_split_arcs": 64})
-            for g in (gg.rmat_decorated(scale=8, seed=5), gg.complete_bipartite(70, 90)):
+            for g in (gg.rmat_decorated(scale=7, seed=5), gg.complete_bipartite(40, 80)):
                 want = oracle.bc(g)
                 for mode in ("plain", "compressed"):
                     got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=tctx)

@@ -32,11 +32,27 @@ def emu_lib():
     return build_emu.build(asan=True)
 
 
-@pytest.mark.parametrize("which", ["single", "pieces", "whole", "hubs", "team", "server"])
-def test_emulated_library(emu_lib, which):
+CHECKS = ["single", "pieces", "whole", "hubs", "team", "server"]
+
+
+@pytest.fixture(scope="module")
+def runs(emu_lib):
+    """All check groups start at once, each in its own process."""
     env = dict(os.environ)
     env["LD_PRELOAD"] = _asan()
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "cpu_emu", "run_checks.py"), which],
-                       cwd=ROOT, env=env, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=900)
-    assert r.returncode == 0 and "ALL OK" in r.stdout, r.stdout[-4000:]
+    procs = {w: subprocess.Popen([sys.executable, os.path.join(ROOT, "tests", "cpu_emu", "run_checks.py"), w],
+                                 cwd=ROOT, env=env, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+             for w in CHECKS}
+    yield procs
+    for p in procs.values():
+        if p.poll() is None:
+            p.kill()
+            p.wait()
+
+
+@pytest.mark.parametrize("which", CHECKS)
+def test_emulated_library(runs, which):
+    p = runs[which]
+    out, _ = p.communicate(timeout=1200)
+    assert p.returncode == 0 and "ALL OK" in out, out[-4000:]
