@@ -498,19 +498,21 @@ __device__ __forceinline__ void pull_group(const int32_t* __restrict__ col, cons
 // One wave's pull of the entries [i0, min(i0 + G, iend)) of the queue q.
 // need_of(i, v) gives an entry's lanes; defer(i, v, e0, e1, need) takes a row
 // the caller splits over many waves and returns true (it must be
-// wave-uniform); finish(i, v, need, acc) consumes each other entry's sum.
-// Rows of at most 64 arcs go through pull_group together, longer ones through
-// pull_row one by one.
-template <int G, typename NeedOf, typename Defer, typename Finish>
+// wave-uniform); early(i, v, need) issues, before the pull, the loads that
+// finish needs; finish(i, v, need, acc, early's result) consumes each other
+// entry's sum.  Rows of at most 64 arcs go through pull_group together,
+// longer ones through pull_row one by one.
+template <int G, typename NeedOf, typename Defer, typename Early, typename Finish>
 __device__ __forceinline__ void pull_entries(const int i0, const int iend, const int32_t* __restrict__ q,
                                              const int32_t* __restrict__ rowp, const int32_t np, const int32_t narcs,
                                              const int32_t* __restrict__ col, uint64_t* __restrict__ mk,
                                              const double* __restrict__ sg, const int32_t* __restrict__ idn,
                                              const bool scale, const int lane, int32_t* flags, NeedOf need_of,
-                                             Defer defer, Finish finish) {
+                                             Defer defer, Early early, Finish finish) {
   int32_t v[G], e0[G], e1[G], dg[G];
   uint64_t need[G];
   bool live[G];
+  decltype(early(0, 0, 0ull)) pre[G];
 #pragma unroll
   for (int e = 0; e < G; ++e) {
     live[e] = false;
@@ -524,6 +526,7 @@ __device__ __forceinline__ void pull_entries(const int i0, const int iend, const
       if (wave_row(rowp, v[e], np, narcs, &e0[e], &e1[e], flags, lane)) {
         need[e] = need_of(i, v[e]);
         live[e] = !defer(i, v[e], e0[e], e1[e], need[e]);
+        if (live[e]) pre[e] = early(i, v[e], need[e]);
       }
     }
     dg[e] = (live[e] && e1[e] - e0[e] <= 64) ? e1[e] - e0[e] : 0;
@@ -535,7 +538,135 @@ __device__ __forceinline__ void pull_entries(const int i0, const int iend, const
     if (live[e] && e1[e] - e0[e] > 64) acc[e] = pull_row(col, e0[e], e1[e], np, mk, need[e], sg, idn, scale, lane, flags);
 #pragma unroll
   for (int e = 0; e < G; ++e)
-    if (live[e]) finish(i0 + e, v[e], need[e], acc[e]);
+    if (live[e]) finish(i0 + e, v[e], need[e], acc[e], pre[e]);
+}
+
+#ifndef SBC_XCD_FENCES
+// This wave's stores and atomics have reached L2.
+__device__ __forceinline__ void xcd_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Hardware id of the XCD this wave runs on.
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15; }
+// Lanes of one wave see each other's LDS writes made before this point.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+#endif
+
+
+// One wave's LDS slots for pull_list: vertex, row bounds and lanes of up to
+// 64 entries.
+struct EntrySlots {
+  int32_t* v;
+  int32_t* e0;
+  int32_t* e1;
+  uint64_t* need;
+};
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// One wave's pull of the n <= 64 entries first, first + step, ...,
+// first + (n-1)*step of the queue q, with the callbacks of pull_entries and
+// early(i, v, need), whose result finish gets as a fifth argument: the loads
+// an entry's finish needs are issued before its pull, not after it.
+// Lane k first gathers entry k's vertex, row bounds and lanes into the
+// wave's slots: one round of loads for all n entries, where an entry alone
+// costs three dependent rounds (queue slot, then row bounds, then lanes).
+// The entries are then pulled one after another; a bad vertex or row is
+// flagged and skipped.
+template <typename NeedOf, typename Defer, typename Early, typename Finish>
+__device__ __forceinline__ void pull_list(const int first, const int step, const int n, const EntrySlots& sl,
+                                          const int32_t* __restrict__ q, const int32_t* __restrict__ rowp,
+                                          const int32_t np, const int32_t narcs, const int32_t* __restrict__ col,
+                                          uint64_t* __restrict__ mk, const double* __restrict__ sg,
+                                          const int32_t* __restrict__ idn, const bool scale, const int lane,
+                                          int32_t* flags, NeedOf need_of, Defer defer, Early early,
+                                          Finish finish) {
+  if (lane < n) {
+    const int i = first + lane * step;
+    int32_t v = q[i], e0 = 0, e1 = 0;
+    uint64_t need = 0;
+    if (v >= 0 && v < np) {
+      e0 = rowp[v];
+      e1 = rowp[v + 1];
+      if (e0 < 0 || e1 < e0 || e1 > narcs) {
+        raise_flag(flags, kFlagBadArc);
+        v = -1;
+      } else {
+        need = need_of(i, v);
+      }
+    } else {
+      raise_flag(flags, kFlagBadArc);
+      v = -1;
+    }
+    sl.v[lane] = v;
+    sl.e0[lane] = e0;
+    sl.e1[lane] = e1;
+    sl.need[lane] = need;
+  }
+  wave_sync();
+  for (int k = 0; k < n; ++k) {
+    const int32_t v = __builtin_amdgcn_readfirstlane(sl.v[k]);
+    if (v < 0) continue;
+    const int i = first + k * step;
+    const int32_t e0 = __builtin_amdgcn_readfirstlane(sl.e0[k]);
+    const int32_t e1 = __builtin_amdgcn_readfirstlane(sl.e1[k]);
+    const uint64_t need = uniform64(sl.need[k]);
+    if (defer(i, v, e0, e1, need)) continue;
+    const auto pre = early(i, v, need);
+    double acc;
+    if (e1 - e0 <= 64) {
+      const int32_t a[1] = {e0}, d[1] = {e1 - e0};
+      const uint64_t nd[1] = {need};
+      double r[1];
+      pull_group<1>(col, a, d, np, mk, nd, sg, idn, scale, lane, flags, r);
+      acc = r[0];
+    } else {
+      acc = pull_row(col, e0, e1, np, mk, need, sg, idn, scale, lane, flags);
+    }
+    finish(i, v, need, acc, pre);
+  }
+  wave_sync();  // every lane has read the slots before the wave's next list fills them
+}
+
+// What the backward finish of entry (v, level) reads besides the pulled sum:
+// the lane's sigma of v (lanes outside the entry get 1), reach[v]-1 and
+// ident[v].
+struct BackEarly {
+  double sv, rm1, id;
+};
+
+template <bool REACH, bool IDENT>
+__device__ __forceinline__ BackEarly back_early(const double* __restrict__ sg, const int32_t* __restrict__ rch,
+                                                const int32_t* __restrict__ idn, int32_t v, uint64_t amask,
+                                                int lane) {
+  BackEarly r;
+  r.sv = ((amask >> lane) & 1) ? sg[(size_t)v * 64 + lane] : 1.0;
+  r.rm1 = REACH ? (double)(rch[v] - 1) : 0.0;
+  r.id = IDENT ? (double)idn[v] : 1.0;
+  return r;
+}
+
+// Backward finish of entry (v, level) with lanes amask and pulled sum acc:
+// delta (Eq. (3) in pull form), the coefficient that replaces sigma, the
+// wave's contribution to bc'[v] (weighted by ident[s]*reach[s] in wsrc) and
+// the level's backward mask.
+__device__ __forceinline__ void back_finish(double* __restrict__ sg, double* __restrict__ bcp,
+                                            uint64_t* __restrict__ bw, int32_t v, uint64_t amask, double acc,
+                                            const BackEarly& pre, double wsrc, int lane, int32_t* flags) {
+  double contrib = 0.0;
+  if ((amask >> lane) & 1) {
+    const double dv = pre.rm1 + pre.sv * acc;
+    sg[(size_t)v * 64 + lane] = pre.id * (1.0 + dv) / pre.sv;
+    contrib = wsrc * dv;
+    if (!(pre.sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, kFlagSigmaOverflow);
+  }
+  contrib = wave_sum(contrib);
+  if (lane == 0) {
+    atomicAdd(&bcp[v], contrib);
+    bw[v] = amask;
+  }
 }
 
 // EU > 0 asks the compiler for at least EU resident waves per SIMD (it then
@@ -550,12 +681,15 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
   __shared__ int s_wtot[WAVES];
   __shared__ int s_scan[BLOCK];
   __shared__ int s_e0[BLOCK];
+  __shared__ int s_e1[BLOCK];
   __shared__ uint64_t s_f[BLOCK];
   __shared__ int s_nheavy, s_nslices;
   __shared__ int s_heavy[kHeavyMax];
   __shared__ int s_hoff[kHeavyMax];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // The pull phases gather entries in the phase-A scratch arrays (free then).
+  const EntrySlots slots{s_scan + wave * 64, s_e0 + wave * 64, s_e1 + wave * 64, s_f + wave * 64};
   const size_t slot = blockIdx.x;
   double* sg = st.sg + slot * (size_t)st.stride * 64;
   int32_t* q = st.q + slot * (size_t)st.stride * 64;
@@ -721,18 +855,16 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         }
         return __builtin_amdgcn_readfirstlane(reg) != 0;
       };
-      for (int i0 = qe + wave * kGroup; i0 < nt; i0 += WAVES * kGroup)
-        pull_entries<kGroup>(
-            i0, nt, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags,
-            [&](int, int32_t w) { return group_load(&fnxt[w]); },  // built with atomicOr
-            defer_long,
-            [&](int i, int32_t w, uint64_t need, double acc) {
-              if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
-              if (lane == 0) {
-                vis[w] |= need;
-                qm[i] = need;
-              }
-            });
+      auto need_f = [&](int, int32_t w) { return group_load(&fnxt[w]); };  // built with atomicOr
+      // The new lanes are marked visited in phase C, all entries at once.
+      auto early_f = [](int, int32_t, uint64_t) { return 0; };
+      auto finish_f = [&](int i, int32_t w, uint64_t need, double acc, int) {
+        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+        if (lane == 0) qm[i] = need;
+      };
+      for (int first = qe + wave; first < nt; first += WAVES * 64)
+        pull_list(first, WAVES, min(64, (nt - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, fcur, sg,
+                  idn, scale, lane, Q.flags, need_f, defer_long, early_f, finish_f);
       __syncthreads();
       mark(kProfPhaseB);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -764,18 +896,20 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
           if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
-          if (lane == 0) {
-            vis[w] |= need;
-            qm[i] = need;
-          }
+          if (lane == 0) qm[i] = need;
         }
         __syncthreads();
         mark(kProfPhaseBHeavy);
       }
-      // Phase C: retire level L's frontier masks; level L+1 becomes current.
+      // Phase C: retire level L's frontier masks, mark level L+1's lanes
+      // visited; level L+1 becomes current.
       for (int i = qs + tid; i < qe; i += BLOCK) {
         const int32_t u = q[i];
         if (u >= 0 && u < np) fcur[u] = 0;
+      }
+      for (int i = qe + tid; i < nt; i += BLOCK) {
+        const int32_t w = q[i];
+        if (w >= 0 && w < np) vis[w] |= group_load(&fnxt[w]);
       }
       if (tid == 0) lvl[L + 2] = nt;
       __syncthreads();
@@ -828,26 +962,16 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         }
         return __builtin_amdgcn_readfirstlane(reg) != 0;
       };
-      for (int i0 = b + wave * kGroup; i0 < e; i0 += WAVES * kGroup)
-        pull_entries<kGroup>(
-            i0, e, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags,
-            [&](int i, int32_t) { return qm[i]; }, defer_long_b,
-            [&](int, int32_t v, uint64_t amask, double acc) {
-              double contrib = 0.0;
-              if ((amask >> lane) & 1) {
-                const size_t at = (size_t)v * 64 + lane;
-                const double sv = sg[at];
-                const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-                sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-                contrib = wsrc * dv;
-                if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
-              }
-              contrib = wave_sum(contrib);
-              if (lane == 0) {
-                atomicAdd(&bcp[v], contrib);
-                bw[v] = amask;
-              }
-            });
+      auto need_b = [&](int i, int32_t) { return qm[i]; };
+      auto early_b = [&](int, int32_t v, uint64_t amask) {
+        return back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
+      };
+      auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, const BackEarly& pre) {
+        back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags);
+      };
+      for (int first = b + wave; first < e; first += WAVES * 64)
+        pull_list(first, WAVES, min(64, (e - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, br, sg, idn,
+                  false, lane, Q.flags, need_b, defer_long_b, early_b, finish_b);
       __syncthreads();
       mark(kProfBackward);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -876,22 +1000,10 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
           const uint64_t amask = qm[i];
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
-          double contrib = 0.0;
-          if ((amask >> lane) & 1) {
-            const size_t at = (size_t)v * 64 + lane;
-            const double sv = sg[at];
-            const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-            sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-            contrib = wsrc * dv;
-            if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
-          }
-          contrib = wave_sum(contrib);
-          if (lane == 0) {
-            atomicAdd(&bcp[v], contrib);
-            bw[v] = amask;
-          }
+          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags);
         }
         __syncthreads();
         mark(kProfBackHeavy);
@@ -950,17 +1062,8 @@ struct TeamShared {
   int ok, team, rank, tsize, local;
 };
 
-#ifndef SBC_XCD_FENCES
-// This wave's stores and atomics have reached L2.
-__device__ __forceinline__ void xcd_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-// Hardware id of the XCD this wave runs on.
-__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15; }
-// Lanes of one wave see each other's LDS writes made before this point.
-__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
-#endif
-
 constexpr int kTeamChunk = 16;  // frontier entries per wave-sized chunk of phase A
-constexpr int kTeamGrab = 4;    // entries a wave takes at a time in the pull phases
+constexpr int kTeamGrab = 4;  // entries a wave takes at a time in the pull phases
 
 // The team control block is only ever accessed with agent-scope atomics and
 // atomic loads/stores, so it is coherent whatever fences a team uses (a plain
@@ -1086,7 +1189,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
 
   // Entries [b, e) of a pull phase, handed to the team's waves kTeamGrab at a
   // time from the phase's counter; a wave asks for its next share before it
-  // works on the current one.  body(i0, i1) pulls entries [i0, i1).
+  // works on the current one.  body(i, i1) pulls the kGroup entries from i
+  // (up to i1).
   auto grabbed = [&](int slot, int b, int e, auto&& body) {
     int next = 0;
     if (lane == 0) next = atomicAdd(&ctl->grab[slot], kTeamGrab);
@@ -1321,26 +1425,32 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           if (h < hmax) hv_i[h] = -1;
         }
       };
+      auto need_f = [&](int, int32_t w) { return fnxt[w]; };
+      auto defer_f = [&](int i, int32_t w, int32_t e0, int32_t e1, uint64_t need) -> bool {
+        if (e1 - e0 <= split) return false;
+        if (lane == 0) {
+          register_long(i, e0, e1);
+          vis[w] |= need;
+          qm[i] = need;
+        }
+        return true;
+      };
+      // The visit mask is read before the pull, so that its update is a store.
+      auto early_f = [&](int, int32_t w, uint64_t) {
+        uint64_t old = 0;
+        if (lane == 0) old = vis[w];
+        return old;
+      };
+      auto finish_f = [&](int i, int32_t w, uint64_t need, double acc, uint64_t old) {
+        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+        if (lane == 0) {
+          vis[w] = old | need;
+          qm[i] = need;
+        }
+      };
       grabbed(hs, qe, nt, [&](int i0, int i1) {
-        pull_entries<kGroup>(
-            i0, i1, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags,
-            [&](int, int32_t w) { return fnxt[w]; },
-            [&](int i, int32_t w, int32_t e0, int32_t e1, uint64_t need) -> bool {
-              if (e1 - e0 <= split) return false;
-              if (lane == 0) {
-                register_long(i, e0, e1);
-                vis[w] |= need;
-                qm[i] = need;
-              }
-              return true;
-            },
-            [&](int i, int32_t w, uint64_t need, double acc) {
-              if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
-              if (lane == 0) {
-                vis[w] |= need;
-                qm[i] = need;
-              }
-            });
+        pull_entries<kGroup>(i0, i1, q, rowp, np, narcs, col, fcur, sg, idn, scale, lane, Q.flags, need_f, defer_f,
+                             early_f, finish_f);
       });
       if (!team_sync(kProfPhaseB)) {
         alive = false;
@@ -1407,42 +1517,33 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           if (u >= 0 && u < np) bz[u] = 0;
         }
       const int b = lvl[l], e = lvl[l + 1];
+      auto need_b = [&](int i, int32_t) { return qm[i]; };
+      auto defer_b = [&](int i, int32_t, int32_t e0, int32_t e1, uint64_t) -> bool {
+        if (e1 - e0 <= split) return false;
+        if (lane == 0) {
+          const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const int h = atomicAdd(&ctl->hcnt[hs], 1);
+          const int o = atomicAdd(&ctl->scnt[hs], ns);
+          if (h < hmax && o + ns <= st.part_cap) {
+            hv_i[h] = i;
+            hv_off[h] = o;
+          } else {  // the host sizes the lists for every long row of the piece
+            raise_flag(Q.flags, kFlagHeavyOverflow);
+            if (h < hmax) hv_i[h] = -1;
+          }
+        }
+        return true;
+      };
+      // Here the finish loads after the pull: loaded before it, the values
+      // would hold registers through the pull and cost more spills.
+      auto early_b = [](int, int32_t, uint64_t) { return 0; };
+      auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, int) {
+        back_finish(sg, bcp, bw, v, amask, acc, back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane), wsrc, lane,
+                    Q.flags);
+      };
       grabbed(hs, b, e, [&](int i0, int i1) {
-        pull_entries<kGroup>(
-            i0, i1, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags,
-            [&](int i, int32_t) { return qm[i]; },
-            [&](int i, int32_t, int32_t e0, int32_t e1, uint64_t) -> bool {
-              if (e1 - e0 <= split) return false;
-              if (lane == 0) {
-                const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-                const int h = atomicAdd(&ctl->hcnt[hs], 1);
-                const int o = atomicAdd(&ctl->scnt[hs], ns);
-                if (h < hmax && o + ns <= st.part_cap) {
-                  hv_i[h] = i;
-                  hv_off[h] = o;
-                } else {  // the host sizes the lists for every long row of the piece
-                  raise_flag(Q.flags, kFlagHeavyOverflow);
-                  if (h < hmax) hv_i[h] = -1;
-                }
-              }
-              return true;
-            },
-            [&](int, int32_t v, uint64_t amask, double acc) {
-              double contrib = 0.0;
-              if ((amask >> lane) & 1) {
-                const size_t at = (size_t)v * 64 + lane;
-                const double sv = sg[at];
-                const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-                sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-                contrib = wsrc * dv;
-                if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
-              }
-              contrib = wave_sum(contrib);
-              if (lane == 0) {
-                atomicAdd(&bcp[v], contrib);
-                bw[v] = amask;
-              }
-            });
+        pull_entries<kGroup>(i0, i1, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags, need_b, defer_b,
+                             early_b, finish_b);
       });
       if (!team_sync(kProfBackward)) {
         alive = false;
@@ -1477,22 +1578,10 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
           const uint64_t amask = qm[i];
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
+          const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
-          double contrib = 0.0;
-          if ((amask >> lane) & 1) {
-            const size_t at = (size_t)v * 64 + lane;
-            const double sv = sg[at];
-            const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-            sg[at] = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-            contrib = wsrc * dv;
-            if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
-          }
-          contrib = wave_sum(contrib);
-          if (lane == 0) {
-            atomicAdd(&bcp[v], contrib);
-            bw[v] = amask;
-          }
+          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags);
         }
         if (!team_sync(kProfBackHeavy)) {
           alive = false;
