@@ -41,6 +41,8 @@ WORKLOADS = {
     "grid512": ("512x512 grid, 12% of edges deleted, largest component", lambda: gg.grid_deleted()),
     "blocktree20000": ("block tree of 20,000 2-connected ER blocks (8..4,096 vertices, avg degree 6)",
                        lambda: gg.block_tree()),
+    "blocktree20000s": ("block tree of 20,000 2-connected ER blocks (8..256 vertices, avg degree 6): "
+                        "small pieces only", lambda: gg.block_tree(max_size=256)),
 }
 
 

@@ -496,5 +496,8 @@ WORKLOADS = {
     "ba1500": lambda: ba_pendant_triangles(),
     "rmat17": lambda: rmat_decorated(),
     "blocktree20000": lambda: block_tree(),
+    # the block tree's recipe with pieces of 8..256 vertices only: the
+    # small-piece kernel's workload
+    "blocktree20000s": lambda: block_tree(max_size=256),
     "grid512": lambda: grid_deleted(),
 }

@@ -90,7 +90,7 @@ typedef struct {
   int64_t lds_sources;       /* sources run by the LDS-resident kernel */
   int64_t global_sources;    /* sources run by the one-source-per-workgroup global kernel */
   int32_t overflow;          /* nonzero if a path count overflowed */
-  /* Per traversal kernel class: 0 one source per wavefront (LDS), 1 one source
+  /* Per traversal kernel class: 0 small pieces, one source per wavefront (LDS), 1 one source
    * per workgroup (LDS), 2 64-source batches (one workgroup per batch), 3 one
    * source per workgroup (global memory), 4 64-source batches run by teams of
    * workgroups (one team per XCD).  Device time of the class's persistent
@@ -116,8 +116,14 @@ sbc_status sbc_context_create(int device, sbc_context* out);
 sbc_status sbc_context_destroy(sbc_context ctx);
 
 /* Tuning knobs, by name.  Known keys:
- *   "lds_max_vertices"   largest piece run by the LDS-resident kernel
- *   "wave_max_vertices"  largest piece run one-source-per-wavefront in LDS
+ *   "wave_max_vertices"  largest piece run by the small-piece kernel (default
+ *                        256, at most 4096; 0: never): one source per
+ *                        wavefront, the piece's CSR and every source's levels,
+ *                        path counts and dependencies in LDS.  Pieces whose
+ *                        arcs do not fit 64 KB of LDS go to the batch kernel
+ *   "wave_wg_waves"      wavefronts per small-piece workgroup (4 or 8)
+ *   "wave_sources_per_item" sources per small-piece work item (1..64)
+ *   "lds_max_vertices"   largest piece run by the one-source-per-workgroup LDS kernel
  *   "batch_min_vertices" smallest piece run by the 64-lane multi-source kernel
  *   "batch_wg_waves"     wavefronts per workgroup of the multi-source kernel (4, 8, 16)
  *   "batch_waves_per_eu" occupancy target of the multi-source kernel: 0 (compiler default), 6 or 8 waves per SIMD
@@ -150,7 +156,7 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        the launch with SBC_E_DEVICE instead of hanging
  *                        (0: no waiting at all, which aborts any team of more
  *                        than one workgroup: a test of the abort path)
- *   "lds_block", "lds_sources_per_item", "wave_sources_per_item"
+ *   "lds_block", "lds_sources_per_item"
  * Read-only (get only): "cus" compute units, "lds_limit_bytes" LDS per workgroup.
  * Errors: SBC_E_INVALID_ARG for an unknown key or out-of-range value. */
 sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value);
@@ -260,7 +266,9 @@ sbc_status sbc_betweenness_sources(sbc_context ctx, sbc_graph g, int64_t nsrc, c
  * starts at reach[v]-1.  reach/ident may be NULL (all ones).  `kernel` forces
  * one traversal kernel: 0 automatic, 1 one-source-per-workgroup in global
  * memory, 2 LDS-resident, 3 64-lane multi-source, 4 64-lane multi-source run
- * by teams of workgroups.
+ * by teams of workgroups, 5 small-piece kernel (one source per wavefront,
+ * everything in LDS).  1 and 2 are switched off in GPU builds
+ * (SBC_E_INVALID_ARG).
  * Errors: SBC_E_INVALID_ARG (shape, or a piece too large for the forced kernel). */
 sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
                         const int32_t* reach, const int32_t* ident, int kernel, double* bc_host,

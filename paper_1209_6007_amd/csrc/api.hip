@@ -97,6 +97,7 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "lds_block") return &p.lds_block;
   if (k == "lds_sources_per_item") return &p.lds_sources_per_item;
   if (k == "wave_sources_per_item") return &p.wave_sources_per_item;
+  if (k == "wave_wg_waves") return &p.wave_wg_waves;
   if (k == "slots") return &p.slots;
   if (k == "cluster_sources") return &p.cluster_sources;
   if (k == "plain_kernel") return &p.plain_kernel;
@@ -131,8 +132,10 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "team_split_arcs") ok = value >= 64 && value <= (1 << 30);
   if (k == "lds_block") ok = value == 64 || value == 256 || value == 512 || value == 1024;
   if (k == "lds_max_vertices") ok = value >= 1 && wg_lds_bytes((int32_t)value) <= ctx->lds_limit;
-  if (k == "wave_max_vertices") ok = value >= 1 && value <= 1024;
-  if (k == "lds_sources_per_item" || k == "wave_sources_per_item") ok = value >= 1 && value <= (1 << 20);
+  if (k == "wave_max_vertices") ok = value >= 0 && value <= kWaveMaxVertices;
+  if (k == "wave_wg_waves") ok = value == 4 || value == 8;
+  if (k == "wave_sources_per_item") ok = value >= 1 && value <= 64;
+  if (k == "lds_sources_per_item") ok = value >= 1 && value <= (1 << 20);
   if (k == "batch_min_vertices") ok = value >= 2;
   if (!ok) return fail(SBC_E_INVALID_ARG, std::string("value out of range for ") + key);
   *slot = value;
@@ -464,7 +467,7 @@ static sbc_status piece_problem(int32_t n, const int32_t* row_ptr, const int32_t
 sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* reach,
                         const int32_t* ident, int kernel, double* bc_host, sbc_run_stats* st) {
   if (!ctx || !bc_host) return fail(SBC_E_INVALID_ARG, "NULL argument");
-  if (kernel < 0 || kernel > 4) return fail(SBC_E_INVALID_ARG, "kernel must be 0..4");
+  if (kernel < 0 || kernel > 5) return fail(SBC_E_INVALID_ARG, "kernel must be 0..5");
   SBC_TRY({
     Prepared prob;
     sbc_status rc = piece_problem(n, row_ptr, col, reach, ident, &prob);

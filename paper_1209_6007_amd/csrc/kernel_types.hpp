@@ -132,6 +132,56 @@ struct TeamArgs {
   int32_t split_arcs;   // rows with more arcs are pulled in slices over the team
 };
 
+// Dynamic LDS of the small-piece kernel (one source per wavefront, the piece
+// in LDS) for pieces of at most np vertices and `arcs` arcs, with `waves`
+// waves per workgroup.  Shared by the workgroup: per-vertex bc' sums (f64),
+// row offsets, reach and ident (i32), column ids (u16).  Then one slice per
+// wave: sigma / backward coefficient (f64), level (i32), BFS order and level
+// starts (u16), and a 64-entry scratch of the frontier's arc prefix sums, row
+// starts and weighted path counts.  Offsets are multiples of 16 bytes.
+struct WaveLds {
+  uint64_t bc, row, rch, idn, col;  // shared arrays
+  uint64_t wave0, wave_bytes;       // first wave slice, bytes per slice
+  uint64_t sig, d, q, lvl, scan, fe0, fsu;  // offsets inside a slice
+  uint64_t total;
+};
+constexpr uint64_t wave_lds_align(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+constexpr WaveLds wave_lds_layout(int64_t np, int64_t arcs, int64_t waves) {
+  WaveLds L{};
+  uint64_t o = 0;
+  L.bc = o;
+  o = wave_lds_align(o + 8 * (uint64_t)np);
+  L.row = o;
+  o = wave_lds_align(o + 4 * (uint64_t)(np + 1));
+  L.rch = o;
+  o = wave_lds_align(o + 4 * (uint64_t)np);
+  L.idn = o;
+  o = wave_lds_align(o + 4 * (uint64_t)np);
+  L.col = o;
+  o = wave_lds_align(o + 2 * (uint64_t)arcs);
+  L.wave0 = o;
+  uint64_t w = 0;
+  L.sig = w;
+  w = wave_lds_align(w + 8 * (uint64_t)np);
+  L.fsu = w;
+  w += 8 * 64;
+  L.d = w;
+  w = wave_lds_align(w + 4 * (uint64_t)np);
+  L.scan = w;
+  w += 4 * 64;
+  L.fe0 = w;
+  w += 4 * 64;
+  L.q = w;
+  w = wave_lds_align(w + 2 * (uint64_t)np);
+  L.lvl = w;
+  w = wave_lds_align(w + 2 * (uint64_t)(np + 2));
+  L.wave_bytes = w;
+  L.total = o + (uint64_t)waves * w;
+  return L;
+}
+// Largest piece the small-piece kernel takes (its BFS order is 16-bit).
+constexpr int32_t kWaveMaxVertices = 4096;
+
 struct QueueArgs {
   const WorkItem* items;
   int32_t nitems;

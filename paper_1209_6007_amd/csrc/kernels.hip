@@ -56,6 +56,50 @@ hipError_t launch_wg_b(const DevPieces& P, const QueueArgs& Q, bool r, bool i, i
   return launch_wg_t<BLOCK, false, false, LDS>(P, Q, grid, max_np, st, dbg, stream);
 }
 
+template <int WAVES, bool R, bool I>
+hipError_t launch_wave_t(const DevPieces& P, const QueueArgs& Q, int grid, int32_t np_max, int32_t arcs_max,
+                         hipStream_t stream) {
+  const size_t lds = (size_t)wave_lds_layout(np_max, arcs_max, WAVES).total;
+  if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)wave_kernel<WAVES, R, I>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((wave_kernel<WAVES, R, I>), dim3(grid), dim3(WAVES * 64), lds, stream, P, Q, np_max, arcs_max);
+  return hipGetLastError();
+}
+
+template <int WAVES>
+hipError_t launch_wave_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, int32_t np_max,
+                         int32_t arcs_max, hipStream_t stream) {
+  if (r && i) return launch_wave_t<WAVES, true, true>(P, Q, grid, np_max, arcs_max, stream);
+  if (r) return launch_wave_t<WAVES, true, false>(P, Q, grid, np_max, arcs_max, stream);
+  if (i) return launch_wave_t<WAVES, false, true>(P, Q, grid, np_max, arcs_max, stream);
+  return launch_wave_t<WAVES, false, false>(P, Q, grid, np_max, arcs_max, stream);
+}
+
+template <int WAVES>
+int occ_wave_w(size_t dyn) {
+  int nb = 0;
+  if (dyn > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)wave_kernel<WAVES, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)dyn) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)wave_kernel<WAVES, true, true>, WAVES * 64,
+                                                   dyn) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
 template <int WAVES, int EU>
 hipError_t launch_ms_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
                        hipStream_t stream) {
@@ -210,6 +254,29 @@ hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
     default: return hipErrorInvalidValue;
   }
 }
+hipError_t launch_wave(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
+                       int32_t np_max, int32_t arcs_max, hipStream_t stream) {
+  switch (waves) {
+    case 4: return launch_wave_w<4>(P, Q, reach, ident, grid, np_max, arcs_max, stream);
+#ifndef SBC_EMU_FEW_VARIANTS
+    case 8: return launch_wave_w<8>(P, Q, reach, ident, grid, np_max, arcs_max, stream);
+#endif
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int occupancy_wave(int waves, int32_t np_max, int32_t arcs_max) {
+  const size_t dyn = (size_t)wave_lds_layout(np_max, arcs_max, waves).total;
+  if (dyn > kMaxLdsBytes) return 0;
+  switch (waves) {
+    case 4: return occ_wave_w<4>(dyn);
+#ifndef SBC_EMU_FEW_VARIANTS
+    case 8: return occ_wave_w<8>(dyn);
+#endif
+    default: return 0;
+  }
+}
+
 int occupancy_team(int waves, int eu) {
   switch (waves * 100 + eu) {
     case 400: return occ_team_w<4, 0>();

@@ -20,6 +20,10 @@ hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool id
 // waves in {4, 8, 16}, eu in {0, 8}.
 hipError_t launch_team(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
                        const MsState& st, const TeamArgs& T, hipStream_t stream);
+// Small-piece kernel: one source per wavefront, pieces of at most np_max
+// vertices and arcs_max arcs in LDS; waves in {4, 8}.
+hipError_t launch_wave(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
+                       int32_t np_max, int32_t arcs_max, hipStream_t stream);
 hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
                           const double* bcp, const double* corr, const double* bcx, double scale, double* out,
                           hipStream_t stream);
@@ -33,6 +37,7 @@ int occupancy_wg(int block, bool lds, size_t dyn_lds_bytes);
 int occupancy_ms(int waves, int eu);
 // 0 when the configuration is not built or cannot be resident.
 int occupancy_team(int waves, int eu);
+int occupancy_wave(int waves, int32_t np_max, int32_t arcs_max);
 
 // LDS bytes the LDS-resident kernel needs for a piece of np vertices.
 size_t wg_lds_bytes(int32_t max_np);

@@ -1616,6 +1616,229 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small pieces: one source per wavefront, the piece and every source's state
+// in LDS.  A workgroup of WAVES waves takes an item (a piece and up to 64 of
+// its sources), copies the piece's rows, column ids (16-bit, piece-local),
+// reach and ident into LDS, and each wave runs the item's sources
+// j = wave, wave + WAVES, ... one after another with the source's levels,
+// path counts (then backward coefficients) and BFS order in its own LDS
+// slice.  A level is one wave's work: the lanes share the level's arcs, and
+// the wave's LDS fences order one level after the other, so waves never wait
+// for each other inside an item.  bc' contributions are summed per vertex in
+// LDS by all waves and added to global memory once per item.
+// Forward: the frontier's arcs are spread over the lanes (prefix sums of the
+// row lengths); a lane that reaches an unseen vertex claims it with a
+// compare-and-swap on its level and appends it to the BFS order, and every
+// arc into the next level adds the frontier vertex's weighted path count
+// (sigma[u] * ident[u], the source unweighted) to the target's sigma with an
+// LDS atomic add (path counts are integers, so the order of the additions
+// does not change them).  Backward: one lane per vertex of the level pulls
+// the coefficients of its neighbours one level deeper (Eq. (3) in pull
+// form).
+// ---------------------------------------------------------------------------
+// LDS writes of the wave's lanes before this point are seen by its lanes after it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+}
+
+template <int WAVES, bool REACH, bool IDENT>
+__global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs Q, int32_t np_max,
+                                                          int32_t arcs_max) {
+  if (Q.magic != kArgMagic) return;
+  if (np_max < 1 || np_max > kWaveMaxVertices || arcs_max < 0) return;  // every workgroup leaves together
+  constexpr int BLOCK = WAVES * 64;
+  SBC_DYNAMIC_LDS(lds);
+  __shared__ int s_item, s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const WaveLds Lo = wave_lds_layout(np_max, arcs_max, WAVES);
+  double* s_bc = reinterpret_cast<double*>(lds + Lo.bc);
+  int32_t* s_row = reinterpret_cast<int32_t*>(lds + Lo.row);
+  int32_t* s_rch = reinterpret_cast<int32_t*>(lds + Lo.rch);
+  int32_t* s_idn = reinterpret_cast<int32_t*>(lds + Lo.idn);
+  uint16_t* s_col = reinterpret_cast<uint16_t*>(lds + Lo.col);
+  unsigned char* ws = lds + Lo.wave0 + (size_t)wave * Lo.wave_bytes;
+  double* sig = reinterpret_cast<double*>(ws + Lo.sig);
+  double* fsu = reinterpret_cast<double*>(ws + Lo.fsu);
+  int32_t* d = reinterpret_cast<int32_t*>(ws + Lo.d);
+  int32_t* scan = reinterpret_cast<int32_t*>(ws + Lo.scan);
+  int32_t* fe0 = reinterpret_cast<int32_t*>(ws + Lo.fe0);
+  uint16_t* q = reinterpret_cast<uint16_t*>(ws + Lo.q);
+  uint16_t* lvl = reinterpret_cast<uint16_t*>(ws + Lo.lvl);
+
+  while (true) {
+    if (tid == 0) {
+      s_item = atomicAdd(Q.head, 1);
+      s_bad = 0;
+    }
+    __syncthreads();
+    const int it = s_item;
+    if (it < 0 || it >= Q.nitems) break;  // the same verdict in the whole workgroup
+    const WorkItem W = Q.items[it];
+    int32_t vb, np;
+    bool good = item_ok(P, Q, W, np_max, &vb, &np) && W.s1 - W.s0 >= 1 && W.s1 - W.s0 <= 64;
+    int32_t a0 = 0, na = 0;
+    if (good) {
+      a0 = P.row[vb];
+      const int32_t a1 = P.row[vb + np];
+      na = a1 - a0;
+      if (a0 < 0 || a1 > P.narcs || na < 0 || na > arcs_max) {
+        if (tid == 0) raise_flag(Q.flags, kFlagBadPiece);
+        good = false;
+      }
+    }
+    if (!good) {
+      if (tid == 0) {
+        raise_flag(Q.flags, kFlagBadItem);
+        atomicAdd(Q.done, 1);
+      }
+      __syncthreads();  // s_item is read by every thread before thread 0 takes the next item
+      continue;
+    }
+    // Stage the piece: rows relative to the piece's first arc, checked to be
+    // nondecreasing and within its arcs; column ids checked to be in range.
+    for (int v = tid; v <= np; v += BLOCK) {
+      const int32_t r = P.row[vb + v] - a0;
+      const int32_t rn = v < np ? P.row[vb + v + 1] - a0 : na;
+      if (r < 0 || rn < r || rn > na) s_bad = 1;
+      s_row[v] = r;
+      if (v < np) {
+        s_bc[v] = 0.0;
+        if (REACH) s_rch[v] = P.reach[vb + v];
+        if (IDENT) s_idn[v] = P.ident[vb + v];
+      }
+    }
+    for (int e = tid; e < na; e += BLOCK) {
+      const int32_t c = P.col[a0 + e];
+      if (c < 0 || c >= np) s_bad = 1;
+      s_col[e] = (uint16_t)(c >= 0 && c < np ? c : 0);
+    }
+    for (int v = lane; v < np; v += 64) {
+      d[v] = -1;
+      sig[v] = 0.0;
+    }
+    __syncthreads();
+    if (s_bad) {  // the same verdict in the whole workgroup
+      if (tid == 0) {
+        raise_flag(Q.flags, kFlagBadArc);
+        atomicAdd(Q.done, 1);
+      }
+      __syncthreads();
+      continue;
+    }
+    const int nsrc = W.s1 - W.s0;
+    for (int j = wave; j < nsrc; j += WAVES) {
+      const int32_t s = P.src_order[vb + W.s0 + j];  // the same in every lane
+      if (s < 0 || s >= np) {
+        if (lane == 0) raise_flag(Q.flags, kFlagBadSource);
+        continue;
+      }
+      const double wsrc = (REACH ? (double)s_rch[s] : 1.0) * (IDENT ? (double)s_idn[s] : 1.0);
+      if (lane == 0) {
+        d[s] = 0;
+        sig[s] = 1.0;
+        q[0] = (uint16_t)s;
+        lvl[0] = 0;
+        lvl[1] = 1;
+      }
+      wave_lds_sync();
+      // ---------------- forward sweep ----------------
+      int qs = 0, qe = 1, L = 0;
+      while (true) {
+        int cnt = 0;  // vertices of level L+1 found so far (wave-uniform)
+        for (int cb = qs; cb < qe; cb += 64) {
+          const int i = cb + lane;
+          int32_t e0 = 0, deg = 0;
+          double su = 0.0;
+          if (i < qe) {
+            const int u = q[i];
+            e0 = s_row[u];
+            deg = s_row[u + 1] - e0;
+            su = sig[u];
+            if (IDENT && L > 0) su *= (double)s_idn[u];
+          }
+          const int incl = wave_incl_scan(deg, lane);
+          const int total = __builtin_amdgcn_readlane(incl, 63);
+          scan[lane] = incl - deg;
+          fe0[lane] = e0;
+          fsu[lane] = su;
+          wave_lds_sync();
+          const int nv = min(64, qe - cb);
+          for (int tb = 0; tb < total; tb += 64) {  // wave-uniform trip count
+            const int t = tb + lane;
+            bool won = false;
+            int w = 0;
+            if (t < total) {
+              int lo = 0, hi = nv - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (scan[mid] <= t) lo = mid;
+                else hi = mid - 1;
+              }
+              w = s_col[fe0[lo] + (t - scan[lo])];
+              int dw = d[w];
+              if (dw < 0) {
+                const int old = atomicCAS(&d[w], -1, L + 1);
+                won = old == -1;
+                dw = won ? L + 1 : old;
+              }
+              if (dw == L + 1) atomicAdd(&sig[w], fsu[lo]);
+            }
+            const uint64_t bal = __ballot(won);
+            if (won) {
+              const int pos = qe + cnt + (int)__builtin_popcountll(bal & ((1ull << lane) - 1));
+              if (pos < np) q[pos] = (uint16_t)w;
+              else raise_flag(Q.flags, kFlagQueueOverflow);
+            }
+            cnt += (int)__builtin_popcountll(bal);
+          }
+          wave_lds_sync();  // the scratch is refilled by the next chunk
+        }
+        if (cnt == 0) break;
+        qs = qe;
+        qe = min(np, qe + cnt);
+        ++L;
+        if (lane == 0) lvl[L + 1] = (uint16_t)qe;
+        wave_lds_sync();
+      }
+      // ---------------- backward sweep ----------------
+      for (int l = L; l >= 1; --l) {
+        const int b = lvl[l], e = lvl[l + 1];
+        for (int i = b + lane; i < e; i += 64) {
+          const int v = q[i];
+          double acc = 0.0;
+          const int32_t x1 = s_row[v + 1];
+          for (int32_t x = s_row[v]; x < x1; ++x) {
+            const int w = s_col[x];
+            if (d[w] == l + 1) acc += sig[w];
+          }
+          const double sv = sig[v];
+          const double dv = (REACH ? (double)(s_rch[v] - 1) : 0.0) + sv * acc;
+          sig[v] = (IDENT ? (double)s_idn[v] : 1.0) * (1.0 + dv) / sv;
+          atomicAdd(&s_bc[v], wsrc * dv);
+          if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+        }
+        wave_lds_sync();
+      }
+      // Restore the unseen state of every vertex this source reached.
+      for (int i = lane; i < qe; i += 64) {
+        const int v = q[i];
+        d[v] = -1;
+        sig[v] = 0.0;
+      }
+      wave_lds_sync();
+    }
+    __syncthreads();
+    for (int v = tid; v < np; v += BLOCK) {
+      const double x = s_bc[v];
+      if (x != 0.0) atomicAdd(&P.bcp[vb + v], x);
+    }
+    if (tid == 0) atomicAdd(Q.done, 1);
+    __syncthreads();  // LDS is refilled by the next item
+  }
+}
+
 __global__ void mapback_kernel(int32_t n, int32_t nverts, int32_t nmap, const int32_t* __restrict__ map_off,
                                const int32_t* __restrict__ map_idx, const double* __restrict__ bcp,
                                const double* __restrict__ corr, const double* __restrict__ bcx, double scale,

@@ -156,21 +156,28 @@ int64_t bfs_depth(const Prepared& prob, int32_t p) {
   return depth;
 }
 
+// Kernel class of a piece of np vertices (before the LDS-size checks).
 int classify(const Params& pr, int32_t np, bool plain, int force) {
+  if (force == 5) return KC_WAVE;
   if (force == 4) return KC_TEAM;
   if (force == 3) return KC_BATCH;
   const bool team = pr.team_min_vertices > 0 && np >= pr.team_min_vertices;
+  // The team threshold wins where the two overlap.
+  const bool small = force == 0 && !team && !(plain && pr.plain_kernel == 1) && np <= pr.wave_max_vertices;
+  if (small) return KC_WAVE;
   if (!kPerSourceKernelsEnabled) return team ? KC_TEAM : KC_BATCH;
   if (force == 1) return KC_GLOBAL;
-  if (force == 2) return np <= pr.wave_max_vertices ? KC_WAVE : KC_LDS;
-  if (force == 3) return KC_BATCH;
+  if (force == 2) return KC_LDS;
   if (plain && pr.plain_kernel == 1) return KC_GLOBAL;
   if (team) return KC_TEAM;
   if (np >= pr.batch_min_vertices) return KC_BATCH;
-  if (np <= pr.wave_max_vertices) return KC_WAVE;
   if (np <= pr.lds_max_vertices) return KC_LDS;
   return KC_GLOBAL;
 }
+
+// LDS the small-piece kernel may give one workgroup (at most 64 KB, so that
+// at least two workgroups fit a compute unit).
+size_t wave_lds_budget(const sbc_context_s* c) { return std::min<size_t>(c->lds_limit, 64 * 1024); }
 
 }  // namespace
 
@@ -274,7 +281,16 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (k == KC_TEAM && opt.force_kernel != 4 && pr.team_max_levels > 0 &&
         bfs_depth(prob, p) > pr.team_max_levels)
       k = KC_BATCH;
-    if (k == KC_LDS || k == KC_WAVE) {
+    // A small piece must fit LDS with the class's largest vertex count: then
+    // any mix of the class's pieces fits one launch.
+    if (k == KC_WAVE &&
+        (np > kWaveMaxVertices ||
+         wave_lds_layout(std::max<int64_t>(np, pr.wave_max_vertices), arcs, pr.wave_wg_waves).total >
+             wave_lds_budget(c))) {
+      if (opt.force_kernel == 5) return fail(SBC_E_INVALID_ARG, "piece too large for the small-piece kernel");
+      k = (pr.team_min_vertices > 0 && np >= pr.team_min_vertices) ? KC_TEAM : KC_BATCH;
+    }
+    if (k == KC_LDS) {
       if (wg_lds_bytes(np) > c->lds_limit) {
         if (opt.force_kernel == 2) return fail(SBC_E_INVALID_ARG, "piece too large for the LDS kernel");
         k = (np >= 64) ? KC_BATCH : KC_GLOBAL;
@@ -286,7 +302,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (opt.debug_single) nsrc = 1;
     if (nsrc <= 0) continue;
     int32_t chunk = 1;
-    if (k == KC_WAVE) chunk = (int32_t)pr.wave_sources_per_item;
+    if (k == KC_WAVE) chunk = (int32_t)std::min<int64_t>(64, pr.wave_sources_per_item);
     if (k == KC_LDS) chunk = (int32_t)pr.lds_sources_per_item;
     if (k == KC_BATCH || k == KC_TEAM) chunk = 64;
     const double per = 8.0 * arcs + (plain ? 48.0 : (reach || ident ? 56.0 : 48.0)) * np;
@@ -354,11 +370,32 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   (void)hipMemGetInfo(&freeb, &totalb);
   size_t budget = pr.mem_budget_mb > 0 ? (size_t)pr.mem_budget_mb << 20 : (size_t)(freeb * 0.6);
   const int cus = c->cus;
-  block[KC_WAVE] = 64;
   block[KC_LDS] = (int)pr.lds_block;
   block[KC_GLOBAL] = 256;
   block[KC_BATCH] = (int)pr.batch_wg_waves * 64;
-  for (int k : {KC_WAVE, KC_LDS}) {
+  if (nitems[KC_WAVE]) {
+    // The launch's LDS holds the largest piece's vertices and the most arcs
+    // of any piece of the class; each fits, and both together must too.
+    wave_waves = (int)pr.wave_wg_waves;
+    block[KC_WAVE] = wave_waves * 64;
+    int32_t mnp = 0, marcs = 0;
+    for (int32_t p = 0; p < P; ++p)
+      if (piece_class[p] == KC_WAVE) {
+        const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
+        mnp = std::max(mnp, np);
+        marcs = std::max<int32_t>(marcs, prob.row[vb + np] - prob.row[vb]);
+      }
+    wave_np = mnp;
+    wave_arcs = marcs;
+    if (wave_lds_layout(mnp, marcs, wave_waves).total > wave_lds_budget(c))
+      return fail(SBC_E_INVALID_ARG, "small-piece class does not fit LDS");
+    const int occ = occupancy_wave(wave_waves, mnp, marcs);
+    if (occ <= 0) return fail(SBC_E_INVALID_ARG, "small-piece kernel configuration cannot be resident");
+    int g = cus * occ;
+    if (pr.slots > 0) g = (int)pr.slots;
+    grid[KC_WAVE] = std::max(1, std::min(g, nitems[KC_WAVE]));
+  }
+  for (int k : {KC_LDS}) {
     if (!nitems[k]) continue;
     const int occ = occupancy_wg(block[k], true, wg_lds_bytes(max_np[k]));
     int g = cus * occ;
@@ -546,8 +583,10 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
       e = launch_team(dp, qa, reach, ident, team_waves, team_eu, grid[k], tm, targs, ks);
     } else if (k == KC_BATCH) {
       e = launch_ms(dp, qa, reach, ident, block[k] / 64, (int)ctx->params.batch_waves_per_eu, grid[k], ms, ks);
+    } else if (k == KC_WAVE) {
+      e = launch_wave(dp, qa, reach, ident, wave_waves, grid[k], wave_np, wave_arcs, ks);
     } else {
-      const bool lds = (k == KC_WAVE || k == KC_LDS);
+      const bool lds = k == KC_LDS;
       e = launch_wg(dp, qa, reach, ident, lds, block[k], grid[k], max_np[k], wg, dbg.dist ? &dbg : nullptr, ks);
     }
     if (e != hipSuccess) return hip_fail(e, "launch traversal");

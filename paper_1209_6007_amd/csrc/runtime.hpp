@@ -35,14 +35,15 @@ struct DevBuf {
 };
 
 struct Params {
-  int64_t wave_max_vertices = 128;    // pieces up to this size: one source per wavefront, LDS state
+  int64_t wave_max_vertices = 256;    // pieces up to this size: small-piece kernel (0: never)
+  int64_t wave_wg_waves = 4;          // wavefronts per small-piece workgroup (4 or 8)
   int64_t lds_max_vertices = 4096;    // pieces up to this size: one source per workgroup, LDS state
   int64_t batch_min_vertices = 4097;  // pieces from this size: 64-source batches
   int64_t batch_wg_waves = 8;         // wavefronts per multi-source workgroup
   int64_t batch_waves_per_eu = 8;     // occupancy target of the batch kernel (0, 6 or 8 waves per SIMD)
   int64_t lds_block = 256;            // threads per LDS workgroup
   int64_t lds_sources_per_item = 32;  // sources per LDS work item
-  int64_t wave_sources_per_item = 64; // sources per wavefront work item
+  int64_t wave_sources_per_item = 64; // sources per small-piece work item (at most 64)
   int64_t slots = 0;                  // resident workgroups per kernel (0: from occupancy)
   int64_t cluster_sources = 2;        // batch source order: 0 as is, 1 balls, 2 common-hub groups then balls
   int64_t plain_kernel = 0;           // plain mode: 0 automatic, 1 one source per workgroup (global)
@@ -81,6 +82,10 @@ struct sbc_graph_s {
 
 namespace sbc {
 
+// KC_WAVE: small-piece kernel (one source per wavefront, the piece in LDS).
+// KC_LDS, KC_GLOBAL: one source per workgroup, state in LDS / global memory.
+// KC_BATCH: 64-source batches, one workgroup per batch.  KC_TEAM: 64-source
+// batches, one team of workgroups per batch.
 enum KernelClass { KC_WAVE = 0, KC_LDS = 1, KC_BATCH = 2, KC_GLOBAL = 3, KC_TEAM = 4, KC_COUNT = 5 };
 
 // The one-source-per-workgroup kernels (LDS and global-memory state) are
@@ -96,7 +101,7 @@ constexpr bool kPerSourceKernelsEnabled = false;
 #endif
 
 struct PlanOptions {
-  int force_kernel = 0;                 // 0 automatic, 1 global, 2 LDS, 3 batch, 4 team
+  int force_kernel = 0;                 // 0 automatic, 1 global, 2 LDS, 3 batch, 4 team, 5 small-piece
   const int32_t* sources = nullptr;     // plain-mode source subset (host), or null
   int64_t nsrc = 0;
   bool debug_single = false;            // one source, keep per-vertex outputs
@@ -133,6 +138,8 @@ struct Plan {
   MsState tm{};
   TeamArgs targs{};
   int team_waves = 8, team_eu = 8;
+  int wave_waves = 4;                       // small-piece kernel: waves per workgroup
+  int32_t wave_np = 0, wave_arcs = 0;       // its LDS is sized for these
   DevBuf wg_d, wg_sig, wg_q, wg_lvl;
   WgState wg{};
   DebugOut dbg{nullptr, nullptr, nullptr};

@@ -80,12 +80,15 @@ def main(which):
                 assert_bc_close(sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ops="odai", ctx=ctx), want,
                                 1e-9, f"{name}/odai")
                 sbc.sbc_context_set_param(ctx.h, "order_plain", 0)
-                for batch_min in (4097, 2):  # default routing, then every piece on the batch kernel
+                # default routing, then every piece on the batch kernel
+                for batch_min, wave_max in ((4097, 256), (2, 0)):
                     sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", batch_min)
+                    sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", wave_max)
                     for mode in ("plain", "compressed"):
                         got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=ctx)
                         assert_bc_close(got, want, 1e-9, f"{name}/{mode}/batch_min={batch_min}")
                 sbc.sbc_context_set_param(ctx.h, "batch_min_vertices", 4097)
+                sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", 256)
                 print(f"   {name} n={g.n} ok", flush=True)
         check("whole graphs", whole)
 
@@ -96,7 +99,8 @@ def main(which):
 
         def phases():
             g = gg.rmat_decorated(scale=7, seed=3)
-            pctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4, "profile_phases": 1, "batch_min_vertices": 2})
+            pctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4, "profile_phases": 1, "batch_min_vertices": 2,
+                                   "wave_max_vertices": 0})
             G = sbc.Graph(g.n, g.row_ptr, g.col)
             G.preprocess("dai")
             plan = sbc.sbc_plan_create(pctx.h, G.h, sbc.SBC_COMPRESSED)
@@ -210,6 +214,54 @@ def main(which):
                 raise AssertionError("aborted team run reported success")
             actx.close()
         check("team abort path", team_abort)
+    if "wave" in which:
+        def wave():
+            # the small-piece kernel: forced on single pieces (few and many
+            # levels, a hub, items of a few sources), and by default routing
+            # on graphs that shatter into small pieces
+            wctx = sbc.Context(0, {"slots": 2})
+            cases = [("er3", gg.erdos_renyi(3, 0.9, 1)), ("er5", gg.erdos_renyi(5, 0.9, 2)),
+                     ("er65", gg.erdos_renyi(65, 0.1, 3)), ("er130", gg.erdos_renyi(130, 0.05, 4)),
+                     ("cycle40", gg.cycle(40)), ("K9", gg.complete(9)), ("K3,70", gg.complete_bipartite(3, 70))]
+            if full:
+                cases += [("er256", gg.erdos_renyi(256, 0.03, 5)), ("path200", gg.path(200))]
+            for name, g in cases:
+                r = gg.rng(g.n)
+                reach, ident = gg.random_attributes(g.n, int(r.integers(1 << 30)), rmax=5, kmax=3)
+                for rr, kk in ((None, None), (reach, ident)):
+                    want = oracle.bc_weighted(g.n, g.row_ptr, g.col, rr, kk)
+                    got = sbc.sbc_piece_bc(wctx.h, g.n, g.row_ptr, g.col, rr, kk, kernel=5)
+                    assert_bc_close(got, want, 1e-9, f"wave piece {name}")
+                print(f"   {name} n={g.n} ok", flush=True)
+            sbc.sbc_context_set_param(wctx.h, "wave_sources_per_item", 7)
+            g = gg.erdos_renyi(40, 0.15, 8)
+            want = oracle.bc_weighted(g.n, g.row_ptr, g.col, None, None)
+            assert_bc_close(sbc.sbc_piece_bc(wctx.h, g.n, g.row_ptr, g.col, None, None, kernel=5), want, 1e-9,
+                            "wave piece, 7-source items")
+            sbc.sbc_context_set_param(wctx.h, "wave_sources_per_item", 64)
+            big = gg.erdos_renyi(2100, 0.003, 9)
+            try:
+                sbc.sbc_piece_bc(wctx.h, big.n, big.row_ptr, big.col, None, None, kernel=5)
+            except sbc.SbcError as e:
+                assert e.status == -1, e
+            else:
+                raise AssertionError("a piece beyond the small-piece LDS was accepted")
+            for name, g in (("blocks", gg.block_tree(n_pieces=12, max_size=90, seed=13)),
+                            ("rmat7", gg.rmat_decorated(scale=7, seed=3))):
+                want = oracle.bc(g)
+                for mode in ("plain", "compressed"):
+                    G = sbc.Graph(g.n, g.row_ptr, g.col)
+                    if mode == "compressed":
+                        G.preprocess("odai")
+                    plan = sbc.sbc_plan_create(wctx.h, G.h, sbc._mode(mode))
+                    sbc.sbc_plan_execute(plan)
+                    st = sbc.sbc_plan_sync(plan)
+                    assert_bc_close(sbc.sbc_plan_result(plan, g.n), want, 1e-9, f"wave routing {name}/{mode}")
+                    sbc.sbc_plan_destroy(plan)
+                    assert mode == "plain" and g.n > 256 or st["items_class"][0] >= 1, st
+                print(f"   routed {name} ok", flush=True)
+            wctx.close()
+        check("small-piece kernel", wave)
     if "server" in which:
         def server():
             gs = [gg.rmat_decorated(scale=7, seed=s) for s in range(3)] + [gg.grid_deleted(side=10, seed=4)]
@@ -226,4 +278,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "server"])
+    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "wave", "server"])

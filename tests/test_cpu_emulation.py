@@ -32,7 +32,7 @@ def emu_lib():
     return build_emu.build(asan=True)
 
 
-CHECKS = ["single", "pieces", "whole", "hubs", "team", "server"]
+CHECKS = ["single", "pieces", "whole", "hubs", "team", "wave", "server"]
 
 
 @pytest.fixture(scope="module")

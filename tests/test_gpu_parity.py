@@ -71,15 +71,21 @@ PIECE_SIZES = [3, 5, 63, 64, 65, 130, 257, 700, 2100]
 
 
 @pytest.mark.parametrize("kernel", [pytest.param(1, marks=pytest.mark.skip(reason=PER_SOURCE_OFF)),
-                                    pytest.param(2, marks=pytest.mark.skip(reason=PER_SOURCE_OFF)), 3, 4])
+                                    pytest.param(2, marks=pytest.mark.skip(reason=PER_SOURCE_OFF)), 3, 4, 5])
 @pytest.mark.parametrize("n", PIECE_SIZES)
 def test_piece_kernels_weighted(ctx, kernel, n):
-    """Each traversal kernel on an attributed piece vs Algorithm 2 + ident."""
+    """Each traversal kernel on an attributed piece vs Algorithm 2 + ident.
+    Kernel 5 (small pieces, everything in LDS) refuses pieces beyond its LDS."""
     r = gg.rng(n * 7 + kernel)
     p = min(0.9, 6.0 / max(n - 1, 1))
     g = gg.erdos_renyi(n, p, int(r.integers(1 << 30)))
     reach, ident = gg.random_attributes(n, int(r.integers(1 << 30)), rmax=5, kmax=3)
     print(f"piece n={n} m={g.m} kernel={kernel}", flush=True)
+    if kernel == 5 and n > 300:
+        with pytest.raises(sbc.SbcError) as ei:
+            sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, reach, ident, kernel=kernel)
+        assert ei.value.status == -1
+        return
     for rr, kk in ((None, None), (reach, None), (None, ident), (reach, ident)):
         want = oracle.bc_weighted(g.n, g.row_ptr, g.col, rr, kk)
         got = sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, rr, kk, kernel=kernel)
@@ -202,6 +208,61 @@ def test_sigma_overflow_is_reported(ctx):
     with pytest.raises(sbc.SbcError) as ei:
         run(ctx, g, "plain")
     assert ei.value.status == -9
+
+
+@pytest.mark.parametrize("kernel", [3, 5])
+def test_sigma_overflow_in_piece_kernels(ctx, kernel):
+    """ident weights of 2^30 along a 40-vertex path: path counts reach
+    2^(30*38), beyond binary64; both piece kernels report the overflow."""
+    g = gg.path(40)
+    ident = np.full(g.n, 1 << 30, np.int32)
+    with pytest.raises(sbc.SbcError) as ei:
+        sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, None, ident, kernel=kernel)
+    assert ei.value.status == -9
+
+
+# ---------------------------------------------------------- small-piece kernel
+# Pieces of at most wave_max_vertices (default 256) run one source per
+# wavefront with the piece and every source's state in LDS.
+
+@pytest.mark.parametrize("waves", [4, 8])
+def test_small_piece_routing(waves):
+    """A block tree of 150 pieces of 8..600 vertices: the small pieces on the
+    small-piece kernel, the rest on the batch kernel, against the oracle and
+    against every piece on the batch kernel; items of a few sources too."""
+    g = gg.block_tree(n_pieces=150, max_size=600, seed=31)
+    want = oracle.bc(g)
+    print(f"block tree n={g.n} m={g.m} waves={waves}", flush=True)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+    for params in ({"wave_wg_waves": waves}, {"wave_wg_waves": waves, "wave_sources_per_item": 5},
+                   {"wave_max_vertices": 0}):
+        c = sbc.Context(0, params)
+        plan = sbc.sbc_plan_create(c.h, G.h, sbc.SBC_COMPRESSED)
+        try:
+            sbc.sbc_plan_execute(plan)
+            st = sbc.sbc_plan_sync(plan)
+            assert_bc_close(sbc.sbc_plan_result(plan, g.n), want, RTOL, f"{params}")
+            small = params.get("wave_max_vertices", 256) > 0
+            assert (st["items_class"][0] > 0) == small, st["items_class"]
+            assert st["items_class"][2] > 0, st["items_class"]
+        finally:
+            sbc.sbc_plan_destroy(plan)
+            c.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_small_piece_whole_graphs(seed):
+    """Graphs of at most 256 vertices run whole on the small-piece kernel in
+    plain mode; decorated graphs shatter into small pieces."""
+    r = gg.rng(100 + seed)
+    g = gg.decorated_random(int(r.integers(40, 200)), float(r.uniform(0.02, 0.2)), int(r.integers(0, 30)),
+                            int(r.integers(0, 20)), int(r.integers(0, 10)), 9100 + seed)
+    c = sbc.Context(0, {"wave_max_vertices": 4096})
+    want = oracle.bc(g)
+    for mode in ("plain", "compressed"):
+        assert_bc_close(run(c, g, mode), want, RTOL, f"seed={seed}/{mode}")
+    c.close()
 
 
 # ---------------------------------------------------------------- team kernel
