@@ -10,7 +10,11 @@ keeps the fastest:
   XCD share one 64-source batch) or one workgroup per batch, i.e. the
   small/large threshold ``team_min_vertices``, and ``team_max_levels``, which
   keeps deep pieces off the team kernel;
-* the workgroup shape (``batch_wg_waves``) and the number of teams.
+* the workgroup shape (``batch_wg_waves``) and the number of teams;
+* then, with that choice fixed, whether small pieces run on the small-piece
+  kernel (one source per wavefront, the piece in LDS) and its workgroup
+  shape (``wave_max_vertices``, ``wave_wg_waves``), when the workload has
+  pieces small enough for it.
 
 Runs are sampled (``sample_items``: an evenly spaced subset of each kernel
 class's work items) yet keep the device fully loaded: about two rounds of the
@@ -39,17 +43,27 @@ DEEP_LEVELS = 32          # depth above this: "deep"
 BATCH_SAMPLE = 2048       # items of a one-workgroup-per-batch run: about two rounds of resident workgroups
 TEAM_ROUNDS = 4           # items per team in a team-kernel run
 
-# Candidate configurations.  Every one sets every tuned key, so that the
-# choice does not depend on the context it is applied to.
-CANDIDATES = [
+# Candidate configurations of the large pieces' kernels.  Every one sets
+# every tuned key, so that the choice does not depend on the context it is
+# applied to; the small-piece keys are at their defaults here.
+_WAVE_DEFAULT = {"wave_max_vertices": 256, "wave_wg_waves": 4}
+CANDIDATES = [dict(c, **_WAVE_DEFAULT) for c in (
     {"team_min_vertices": 0, "batch_wg_waves": 8, "batch_waves_per_eu": 8, "team_count": 64, "team_max_levels": 0},
     {"team_min_vertices": 0, "batch_wg_waves": 16, "batch_waves_per_eu": 8, "team_count": 64, "team_max_levels": 0},
     {"team_min_vertices": 0, "batch_wg_waves": 4, "batch_waves_per_eu": 8, "team_count": 64, "team_max_levels": 0},
     {"team_min_vertices": 4096, "batch_wg_waves": 8, "batch_waves_per_eu": 8, "team_count": 32, "team_max_levels": 0},
     {"team_min_vertices": 4096, "batch_wg_waves": 8, "batch_waves_per_eu": 8, "team_count": 64, "team_max_levels": 0},
     {"team_min_vertices": 4096, "batch_wg_waves": 8, "batch_waves_per_eu": 8, "team_count": 128, "team_max_levels": 0},
-]
+)]
 TUNED_KEYS = sorted(CANDIDATES[0])
+# Second stage: the small-piece kernel off, or on with 4 or 8 waves per
+# workgroup and a lower size threshold.
+SMALL_CANDIDATES = [
+    {"wave_max_vertices": 0, "wave_wg_waves": 4},
+    {"wave_max_vertices": 256, "wave_wg_waves": 4},
+    {"wave_max_vertices": 256, "wave_wg_waves": 8},
+    {"wave_max_vertices": 128, "wave_wg_waves": 8},
+]
 
 
 def cache_path() -> str:
@@ -96,6 +110,15 @@ def workload_bucket(graph: Graph, mode: int = SBC_COMPRESSED, n: int = 0, row_pt
     cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int64)
     depth = bfs_depth(rp, cl)
     return bucket_of(ve - vb, depth), ve - vb, depth
+
+
+def smallest_piece(graph: Graph, mode: int, n: int) -> int:
+    """Vertices of the smallest piece with at least one source."""
+    if mode == SBC_PLAIN:
+        return n
+    sizes = np.diff(sbc_graph_export(graph.h)["vtx_off"])
+    sizes = sizes[sizes > 0]
+    return int(sizes.min()) if len(sizes) else 0
 
 
 def total_items(graph: Graph, mode: int, n: int) -> int:
@@ -169,8 +192,20 @@ def tune(graph: Graph, mode: int = SBC_COMPRESSED, device: int = 0, row_ptr=None
         if log:
             log(f"autotune {key}: {cand} -> {ms:.1f} ms estimated ({time.perf_counter() - t0:.1f} s)")
     ms, best = min(results, key=lambda r: r[0])
+    small = []
+    smin = smallest_piece(graph, mode, n)
+    if 0 < smin <= max(c["wave_max_vertices"] for c in SMALL_CANDIDATES):
+        for opt in SMALL_CANDIDATES:
+            cand = dict(best, **opt)
+            t0 = time.perf_counter()
+            m = _time_candidate(cand, graph, mode, device, full)
+            small.append((m, cand))
+            if log:
+                log(f"autotune {key}: small pieces {opt} -> {m:.1f} ms estimated ({time.perf_counter() - t0:.1f} s)")
+        ms, best = min(small, key=lambda r: r[0])
     cache[key] = {"params": best, "estimated_ms": ms, "piece_vertices": int(np_max), "depth": int(depth),
-                  "items": full, "candidates": [{"params": c, "estimated_ms": m} for m, c in results]}
+                  "items": full, "candidates": [{"params": c, "estimated_ms": m} for m, c in results],
+                  "small_candidates": [{"params": c, "estimated_ms": m} for m, c in small]}
     save_cache(cache, path)
     return dict(best)
 

@@ -42,6 +42,21 @@ def test_candidates_set_every_tuned_key_and_sample_sizes():
         assert s == (at.TEAM_ROUNDS * c["team_count"] if c["team_min_vertices"] > 0 else at.BATCH_SAMPLE)
 
 
+def test_small_stage_keys_are_tuned_keys():
+    for c in at.SMALL_CANDIDATES:
+        assert set(c) <= set(at.TUNED_KEYS)
+    assert any(c["wave_max_vertices"] == 0 for c in at.SMALL_CANDIDATES)  # the kernel off is a choice
+
+
+def test_smallest_piece():
+    g = gg.block_tree(n_pieces=30, max_size=200, seed=5)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+    sizes = np.diff(sbc.sbc_graph_export(G.h)["vtx_off"])
+    assert at.smallest_piece(G, sbc.SBC_COMPRESSED, g.n) == int(sizes[sizes > 0].min())
+    assert at.smallest_piece(G, sbc.SBC_PLAIN, g.n) == g.n
+
+
 def test_total_items_matches_pieces():
     g = gg.rmat_decorated(scale=10, seed=4)
     G = sbc.Graph(g.n, g.row_ptr, g.col)

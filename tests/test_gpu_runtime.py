@@ -26,12 +26,30 @@ def test_autotune_choice_gives_exact_result(tmp_path):
     best = at.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, path=path, log=print)
     entry = next(iter(at.load_cache(path).values()))
     assert len(entry["candidates"]) == len(at.CANDIDATES)
+    assert entry["small_candidates"] == []  # one piece, far above the small-piece sizes
     assert entry["params"] == best and all(c["estimated_ms"] > 0 for c in entry["candidates"])
     # cached: no new timing
     assert at.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, path=path) == best
     ctx = sbc.Context(0)
     at.apply(ctx, best)
     assert_bc_close(sbc.sbc_betweenness(ctx.h, G.h, sbc.SBC_COMPRESSED), oracle.bc(g), RTOL, "autotuned")
+    ctx.close()
+
+
+def test_autotune_small_piece_stage(tmp_path):
+    """A block tree of small pieces: the second stage times the small-piece
+    options with the first stage's choice, and its pick is exact."""
+    g = gg.block_tree(n_pieces=200, max_size=300, seed=41)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+    path = str(tmp_path / "tune.json")
+    best = at.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, path=path, log=print)
+    entry = next(iter(at.load_cache(path).values()))
+    assert len(entry["small_candidates"]) == len(at.SMALL_CANDIDATES)
+    assert entry["params"] == best and sorted(best) == at.TUNED_KEYS
+    ctx = sbc.Context(0)
+    at.apply(ctx, best)
+    assert_bc_close(sbc.sbc_betweenness(ctx.h, G.h, sbc.SBC_COMPRESSED), oracle.bc(g), RTOL, "autotuned small")
     ctx.close()
 
 
