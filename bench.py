@@ -195,8 +195,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split of the work items is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); splitting the work items over several "
+              "GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import paper_1209_6007_amd as sbc  # no torch in this process: the library syncs its own streams

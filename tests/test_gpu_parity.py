@@ -148,8 +148,13 @@ def test_source_subset(ctx):
     assert_bc_close(got, want, RTOL, "sources")
 
 
-def test_plan_reexecute_and_graph_replay(ctx):
-    g = gg.rmat_decorated(scale=11, seed=23)
+@pytest.mark.parametrize("name", ["rmat11", "blocks"])
+def test_plan_reexecute_and_graph_replay(ctx, name):
+    """Eager re-execution, then HIP-graph replays with eager work between
+    them; the block tree's plan holds both the small-piece and the batch
+    launch."""
+    g = gg.rmat_decorated(scale=11, seed=23) if name == "rmat11" else gg.block_tree(n_pieces=80, max_size=600,
+                                                                                    seed=29)
     want = oracle.bc(g)
     G = sbc.Graph(g.n, g.row_ptr, g.col)
     G.preprocess("dai")
