@@ -168,7 +168,9 @@ def serving(args, sbc):
            "rate_per_s": args.rate, "makespan_s": makespan, "offered_gteps": offered,
            "config": {"workload": f"Poisson stream at {args.rate}/s of {len(reqs)} jobs: R-MAT scale 10..15 "
                                   "(decorated) or deleted-edge grid side 32..256, fair coin", "slots": args.slots,
-                      "params": params},
+                      "params": params,
+                      "order": ("least estimated work first" if params.get("server_order", 1) == 1
+                                else "oldest first")},
            "data": "synthetic", "dtype": "f64"}
     print(json.dumps(out), flush=True)
 

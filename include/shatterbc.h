@@ -149,6 +149,8 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "team_max_levels"    pieces whose breadth-first depth from their highest-degree
  *                        vertex exceeds this stay on the one-workgroup batch
  *                        kernel (0: no limit)
+ *   "server_order"       serving: 1 (default) least estimated work first, 0 oldest first
+ *   "server_max_wait_ms" serving: a job waiting longer is taken first (default 30000)
  *   "sample_items"       tuning only (0: off): plans run an evenly spaced sample of
  *                        at most this many work items per kernel class, so the
  *                        result covers only those items' sources
@@ -295,6 +297,10 @@ sbc_status sbc_copy_bandwidth(sbc_context ctx, size_t bytes, int reps, double* g
  * and a slot is free; admitted jobs run concurrently on `slots` streams, so a
  * job that arrives while others run starts as soon as a slot and memory free
  * up.  Graph data and scores stay resident until the job is released.
+ * A free slot takes the waiting job with the least estimated work
+ * (n x arcs x (1 + breadth-first depth / 16)), or the oldest job once it has
+ * waited server_max_wait_ms; context parameter server_order = 0 takes the
+ * oldest job always.
  * Errors: SBC_E_INVALID_ARG, SBC_E_DEVICE. */
 sbc_status sbc_server_create(sbc_context ctx, int slots, size_t hbm_budget_bytes, sbc_server* out);
 /* Drains every submitted job, then stops the loop and frees the server. */

@@ -112,6 +112,8 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "team_split_arcs") return &p.team_split_arcs;
   if (k == "team_max_levels") return &p.team_max_levels;
   if (k == "sample_items") return &p.sample_items;
+  if (k == "server_order") return &p.server_order;
+  if (k == "server_max_wait_ms") return &p.server_max_wait_ms;
   return nullptr;
 }
 
@@ -129,6 +131,7 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "cluster_sources") ok = value >= 0 && value <= 2;
   if (k == "team_spin_ms") ok = value <= 600000;
   if (k == "team_local_fences") ok = value == 0 || value == 1;
+  if (k == "server_order") ok = value == 0 || value == 1;
   if (k == "team_split_arcs") ok = value >= 64 && value <= (1 << 30);
   if (k == "lds_block") ok = value == 64 || value == 256 || value == 512 || value == 1024;
   if (k == "lds_max_vertices") ok = value >= 1 && wg_lds_bytes((int32_t)value) <= ctx->lds_limit;

@@ -1,10 +1,17 @@
 // Continuously batching request loop.
 //
-// `slots` worker threads each take the oldest waiting job, preprocess it on
-// the host, then wait until its device footprint fits in the memory budget
-// (a job that arrives while others run is admitted the moment a slot and
-// enough memory are free).  Admitted jobs upload, run and copy back on their
-// own streams, so the device overlaps the work of every admitted job.
+// `slots` worker threads each take a waiting job, preprocess it on the host,
+// then wait until its device footprint fits in the memory budget (a job that
+// arrives while others run is admitted the moment a slot and enough memory
+// are free).  Admitted jobs upload, run and copy back on their own streams,
+// so the device overlaps the work of every admitted job.
+//
+// Which waiting job a free worker takes (context parameter server_order):
+// the oldest, or the one with the least estimated work, unless the oldest
+// has waited longer than server_max_wait_ms.  The estimate is sources x arcs
+// scaled by the graph's breadth-first depth from its highest-degree vertex:
+// every level of a traversal costs barriers and, for 64-source batches, the
+// sources' levels spread wider on deep graphs.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -27,6 +34,33 @@ double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
+
+// n x arcs x (1 + depth / 16), depth from a breadth-first search of the
+// highest-degree vertex's component.
+double work_estimate(const HostGraph& g) {
+  const int32_t n = g.n;
+  if (n <= 0) return 0.0;
+  int32_t start = 0;
+  for (int32_t v = 1; v < n; ++v)
+    if (g.row_ptr[v + 1] - g.row_ptr[v] > g.row_ptr[start + 1] - g.row_ptr[start]) start = v;
+  std::vector<int32_t> d(n, -1), q;
+  q.reserve(n);
+  d[start] = 0;
+  q.push_back(start);
+  int32_t depth = 0;
+  for (size_t h = 0; h < q.size(); ++h) {
+    const int32_t v = q[h];
+    for (int32_t e = g.row_ptr[v]; e < g.row_ptr[v + 1]; ++e) {
+      const int32_t w = g.col[e];
+      if (d[w] < 0) {
+        d[w] = d[v] + 1;
+        depth = d[w];
+        q.push_back(w);
+      }
+    }
+  }
+  return (double)n * (double)g.arcs() * (1.0 + depth / 16.0);
+}
 }  // namespace
 
 struct sbc_job_s {
@@ -36,6 +70,7 @@ struct sbc_job_s {
   sbc_status status = SBC_E_NOT_READY;
   std::string error;
   sbc_job_stats stats{};
+  double est = 0;  // estimated work, for ordering the waiting jobs
   double t_submit = 0, t_start = 0, t_done = 0;
   bool done = false;
   std::mutex mu;
@@ -137,8 +172,13 @@ static void worker_loop(sbc_server s) {
         if (s->stopping) return;
         continue;
       }
-      j = s->pending.front();
-      s->pending.pop_front();
+      auto pick = s->pending.begin();
+      const Params& pr = s->ctx->params;
+      if (pr.server_order == 1 && now_ms() - (*pick)->t_submit <= (double)pr.server_max_wait_ms)
+        for (auto it = s->pending.begin(); it != s->pending.end(); ++it)
+          if ((*it)->est < (*pick)->est) pick = it;  // ties: the older job
+      j = *pick;
+      s->pending.erase(pick);
     }
     run_job(s, j);
     job_unref(j);
@@ -187,6 +227,11 @@ sbc_status sbc_server_submit(sbc_server s, sbc_graph g, uint32_t mode, sbc_job* 
   j->g = g;
   j->mode = mode;
   j->t_submit = now_ms();
+  try {
+    j->est = work_estimate(g->g);
+  } catch (...) {
+    j->est = 0.0;
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) {

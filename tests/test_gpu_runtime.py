@@ -91,3 +91,31 @@ def test_server_mix_equals_alone():
         assert_bc_close(got, oracle.bc(g), RTOL, "mix vs oracle")
     sbc.sbc_server_destroy(srv)
     ctx.close()
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_server_order(order):
+    """One slot, busy with a deep grid job while two more grid jobs and two
+    small R-MAT jobs arrive: least-estimated-work-first runs the small jobs
+    before the waiting grid jobs; oldest-first runs them in arrival order.
+    Every result equals the oracle's either way."""
+    graphs = [gg.grid_deleted(side=120, seed=61), gg.grid_deleted(side=110, seed=62),
+              gg.grid_deleted(side=100, seed=63), gg.rmat_decorated(scale=8, seed=64),
+              gg.rmat_decorated(scale=8, seed=65)]
+    ctx = sbc.Context(0, {"server_order": order})
+    Gs = [sbc.Graph(g.n, g.row_ptr, g.col) for g in graphs]
+    for G in Gs:
+        G.preprocess("odai")  # before submission, so that the first job is still running at the last submit
+    srv = sbc.sbc_server_create(ctx.h, 1, 0)
+    jobs = [sbc.sbc_server_submit(srv, G.h, sbc.SBC_COMPRESSED) for G in Gs]
+    starts = []
+    for g, j in zip(graphs, jobs):
+        got, st = sbc.sbc_job_wait(j, g.n)
+        sbc.sbc_job_release(j)
+        starts.append(st["submit_to_start_ms"])
+        assert_bc_close(got, oracle.bc(g), RTOL, f"order {order}")
+    sbc.sbc_server_destroy(srv)
+    ctx.close()
+    print("waits before start (ms):", [round(x, 1) for x in starts], flush=True)
+    small_first = max(starts[3], starts[4]) < min(starts[1], starts[2])
+    assert small_first == (order == 1), starts
