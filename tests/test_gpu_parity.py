@@ -270,6 +270,18 @@ def test_small_piece_whole_graphs(seed):
     c.close()
 
 
+def test_small_piece_source_subset():
+    """A source subset of a small plain graph (one piece, on the small-piece
+    kernel): Algorithm 1 restricted to those sources."""
+    g = gg.erdos_renyi(200, 0.04, 77)
+    src = np.array([3, 150, 7, 99, 0, 199, 42], dtype=np.int32)
+    want = oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src)
+    c = sbc.Context(0)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    assert_bc_close(sbc.sbc_betweenness_sources(c.h, G.h, src), want, RTOL, "small-piece sources")
+    c.close()
+
+
 # ---------------------------------------------------------------- team kernel
 # All workgroups of one XCD share one 64-source batch; pieces from
 # team_min_vertices on use it (every piece, with the threshold at 3).
