@@ -123,7 +123,10 @@ def serving(args, sbc):
     progress(f"serving: generating {len(reqs)} request graphs")
     with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         graphs = list(ex.map(gg.request_graph, reqs, chunksize=4))
-    params = {"team_min_vertices": 0}
+    # Jobs share the device, so none takes the team kernel (a cooperative
+    # launch holds every CU); the deep grid jobs carry most of the work, and
+    # 16-wave batch workgroups are the tuned shape for deep pieces.
+    params = {"team_min_vertices": 0, "batch_wg_waves": 16}
     for kv in args.param:
         k, v = kv.split("=")
         params[k] = int(v)
