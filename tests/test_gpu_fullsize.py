@@ -101,3 +101,39 @@ def test_block_tree_200_pieces_vs_oracle(ctx):
     G.preprocess("odai")
     got = sbc.sbc_betweenness(ctx.h, G.h, sbc.SBC_COMPRESSED)
     assert_bc_close(got, oracle.bc(g), RTOL, "block tree 200 pieces")
+
+
+def test_small_piece_block_tree_full_run(ctx):
+    """The 20,000-piece block tree of 8..256-vertex blocks (the small-piece
+    workload), in the launch configuration the bench times: equal to the same
+    run with every piece on the batch kernel, and a sample of its pieces
+    checked one by one against Algorithm 2 with ident weights on the oracle."""
+    g = gg.block_tree(max_size=256)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    st = G.preprocess("odai")
+    print(f"small-piece block tree n={g.n} m={g.m} pieces={st['pieces']}", flush=True)
+    plan = sbc.sbc_plan_create(ctx.h, G.h, sbc.SBC_COMPRESSED)
+    try:
+        sbc.sbc_plan_execute(plan)
+        rs = sbc.sbc_plan_sync(plan)
+        bc = sbc.sbc_plan_result(plan, g.n)
+    finally:
+        sbc.sbc_plan_destroy(plan)
+    assert rs["items_class"][0] > 0 and rs["items_class"][2] == 0, rs["items_class"]
+    batch = sbc.Context(0, {"wave_max_vertices": 0})
+    ref = sbc.sbc_betweenness(batch.h, G.h, sbc.SBC_COMPRESSED)
+    batch.close()
+    assert_bc_close(bc, ref, 1e-12, "small-piece kernel vs batch kernel")
+    ex = sbc.sbc_graph_export(G.h)
+    vo = ex["vtx_off"]
+    sizes = np.diff(vo)
+    r = gg.rng(17)
+    picks = list(r.choice(len(sizes), size=8, replace=False)) + [int(np.argmax(sizes))]
+    for p in picks:
+        vb, ve = int(vo[p]), int(vo[p + 1])
+        rp = (ex["row"][vb:ve + 1] - ex["row"][vb]).astype(np.int32)
+        cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int32)
+        reach, ident = ex["reach"][vb:ve], ex["ident"][vb:ve]
+        got = sbc.sbc_piece_bc(ctx.h, ve - vb, rp, cl, reach, ident, kernel=5)
+        want = oracle.bc_weighted(ve - vb, rp, cl, reach, ident)
+        assert_bc_close(got, want, RTOL, f"small-piece block tree piece {p} (n={ve - vb})")
