@@ -210,6 +210,11 @@ def main():
         serving(args, sbc)
         return
     desc, make = WORKLOADS[args.workload]
+    if args.workload.startswith("blocktree") and not args.no_plain:
+        # plain Brandes on the whole block tree (millions of vertices as one
+        # piece) runs for minutes to hours: only the compressed path is timed
+        progress("plain run skipped on the block tree (whole graph as one piece)")
+        args.no_plain = True
     g = make()
     params = {}
     for kv in args.param:
