@@ -17,7 +17,7 @@ keeps the fastest:
   pieces small enough for it.
 
 Runs are sampled (``sample_items``: an evenly spaced subset of each kernel
-class's work items) yet keep the device fully loaded: about two rounds of the
+class's work items) yet keep the device fully loaded: eight rounds of the
 resident workgroups for one workgroup per batch, four items per team for the
 team kernel.  The sampled time is scaled by the number of items to estimate a
 full run.  Results are cached in a JSON file
@@ -35,12 +35,13 @@ import time
 
 import numpy as np
 
-from . import (SBC_COMPRESSED, SBC_PLAIN, Context, Graph, sbc_context_device_name, sbc_graph_export,
-               sbc_plan_create, sbc_plan_destroy, sbc_plan_execute, sbc_plan_sync)
+from . import (SBC_COMPRESSED, SBC_PLAIN, Context, Graph, sbc_context_device_name, sbc_context_get_param,
+               sbc_graph_export, sbc_plan_create, sbc_plan_destroy, sbc_plan_execute, sbc_plan_sync)
 
 SIZE_CLASSES = ((4096, "s"), (32768, "m"), (None, "l"))  # largest piece < bound -> class
 DEEP_LEVELS = 32          # depth above this: "deep"
-BATCH_SAMPLE = 2048       # items of a one-workgroup-per-batch run: about two rounds of resident workgroups
+BATCH_ROUNDS = 8          # rounds of resident workgroups in a one-workgroup-per-batch run
+WAVES_PER_CU = 32         # resident waves per compute unit at eight waves per SIMD
 TEAM_ROUNDS = 4           # items per team in a team-kernel run
 
 # Candidate configurations of the large pieces' kernels.  Every one sets
@@ -129,15 +130,19 @@ def total_items(graph: Graph, mode: int, n: int) -> int:
     return int(np.sum((sizes + 63) // 64))
 
 
-def sample_for(params: dict) -> int:
+def sample_for(params: dict, cus: int = 256) -> int:
+    """Items per kernel class of a sampled run: several rounds of the resident
+    workgroups (a run of one or two rounds measures its slowest item, not the
+    throughput), or TEAM_ROUNDS items per team."""
     if params.get("team_min_vertices", 0) > 0:
         return TEAM_ROUNDS * int(params.get("team_count", 64))
-    return BATCH_SAMPLE
+    waves = int(params.get("batch_wg_waves", 8))
+    return BATCH_ROUNDS * cus * max(1, WAVES_PER_CU // waves)
 
 
-def _time_candidate(params: dict, graph: Graph, mode: int, device: int, full_items: int) -> float:
+def _time_candidate(params: dict, graph: Graph, mode: int, device: int, full_items: int, cus: int = 256) -> float:
     """Estimated milliseconds of a full run under params."""
-    ctx = Context(device, dict(params, sample_items=sample_for(params)))
+    ctx = Context(device, dict(params, sample_items=sample_for(params, cus)))
     try:
         plan = sbc_plan_create(ctx.h, graph.h, mode)
         try:
@@ -177,6 +182,7 @@ def tune(graph: Graph, mode: int = SBC_COMPRESSED, device: int = 0, row_ptr=None
     bucket, np_max, depth = workload_bucket(graph, mode, row_ptr=row_ptr, col=col)
     probe = Context(device)
     name = sbc_context_device_name(probe.h)
+    cus = int(sbc_context_get_param(probe.h, "cus"))
     probe.close()
     key = cache_key(name, bucket, mode)
     cache = load_cache(path)
@@ -187,7 +193,7 @@ def tune(graph: Graph, mode: int = SBC_COMPRESSED, device: int = 0, row_ptr=None
     results = []
     for cand in CANDIDATES:
         t0 = time.perf_counter()
-        ms = _time_candidate(cand, graph, mode, device, full)
+        ms = _time_candidate(cand, graph, mode, device, full, cus)
         results.append((ms, cand))
         if log:
             log(f"autotune {key}: {cand} -> {ms:.1f} ms estimated ({time.perf_counter() - t0:.1f} s)")
@@ -198,7 +204,7 @@ def tune(graph: Graph, mode: int = SBC_COMPRESSED, device: int = 0, row_ptr=None
         for opt in SMALL_CANDIDATES:
             cand = dict(best, **opt)
             t0 = time.perf_counter()
-            m = _time_candidate(cand, graph, mode, device, full)
+            m = _time_candidate(cand, graph, mode, device, full, cus)
             small.append((m, cand))
             if log:
                 log(f"autotune {key}: small pieces {opt} -> {m:.1f} ms estimated ({time.perf_counter() - t0:.1f} s)")

@@ -38,8 +38,10 @@ def test_buckets():
 def test_candidates_set_every_tuned_key_and_sample_sizes():
     for c in at.CANDIDATES:
         assert sorted(c) == at.TUNED_KEYS
-        s = at.sample_for(c)
-        assert s == (at.TEAM_ROUNDS * c["team_count"] if c["team_min_vertices"] > 0 else at.BATCH_SAMPLE)
+        s = at.sample_for(c, cus=256)
+        want = (at.TEAM_ROUNDS * c["team_count"] if c["team_min_vertices"] > 0
+                else at.BATCH_ROUNDS * 256 * (at.WAVES_PER_CU // c["batch_wg_waves"]))
+        assert s == want
 
 
 def test_small_stage_keys_are_tuned_keys():
