@@ -28,9 +28,9 @@ import graphgen as gg  # noqa: E402
 
 METRIC = "exact-BC GTEPS (sources×edges/s) + HBM roofline %, compressed-batched vs plain"
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["small_lds", "wg_lds", "batch64", "wg_global", "team64"]
-KERNEL_SYMBOLS = {0: "wave_kernel<WAVES,*,*>", 1: "wg_kernel<256,*,*,LDS>", 2: "ms_kernel<WAVES,EU,*,*>",
-                  3: "wg_kernel<256,*,*,global>", 4: "ms_team_kernel<WAVES,EU,*,*>"}
+CLASS_NAMES = ["small_lds", "unused1", "batch64", "unused3", "team64"]
+KERNEL_SYMBOLS = {0: "wave_kernel<WAVES,*,*>", 1: "", 2: "ms_kernel<WAVES,EU,*,*>", 3: "",
+                  4: "ms_team_kernel<WAVES,EU,*,*>"}
 
 WORKLOADS = {
     "rmat17": ("R-MAT scale 17 (131,072 labels), edge factor 8, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "
@@ -93,24 +93,49 @@ def timed_run(sbc, ctx, G, mode, steps, warmup, use_graph=False):
     return (t1 - t0) / steps, stats, result
 
 
-def cpu_baseline(g, seconds_target: float, threads: int):
-    """Oracle (Algorithm 1, FP64) on a bounded random sample of sources."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(g, sources_pool, seconds_target: float, threads: int, r):
+    """Sources x edges per second of the oracle on about seconds_target of work."""
     import oracle
 
-    oracle.build(force=False)
-    r = gg.rng(99)
-    probe = r.choice(g.n, size=min(g.n, 32), replace=False).astype(np.int32)
+    probe = r.choice(sources_pool, size=min(len(sources_pool), 8 * threads), replace=False).astype(np.int32)
     t0 = time.perf_counter()
     oracle.bc_plain(g.n, g.row_ptr, g.col, sources=probe, threads=threads)
     dt = max(time.perf_counter() - t0, 1e-6)
-    k = int(min(g.n, max(64, len(probe) * seconds_target / dt)))
-    src = r.choice(g.n, size=k, replace=False).astype(np.int32)
+    k = int(min(len(sources_pool), max(4 * threads, len(probe) * seconds_target / dt)))
+    src = r.choice(sources_pool, size=k, replace=False).astype(np.int32)
     t0 = time.perf_counter()
     oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": k * g.m / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
-            "sample": f"{k} uniformly sampled sources of the same graph (Algorithm 1, FP64, {threads} threads), "
-                      f"{dt:.1f} s, scaled to sources x edges / s"}
+    return k * g.m / dt, k, dt
+
+
+def cpu_baseline(g, seconds_target: float, threads: int):
+    """Oracle (Algorithm 1, FP64) on bounded random samples of the graph's
+    non-isolated sources: with `threads` threads, and with one thread (a
+    per-core rate comparable with the paper's single-core runs)."""
+    import oracle
+
+    oracle.build(force=False)
+    pool = np.flatnonzero(np.diff(g.row_ptr) > 0)
+    rate, k, dt = oracle_rate(g, pool, seconds_target, threads, gg.rng(99))
+    rate1, k1, dt1 = oracle_rate(g, pool, seconds_target / 3, 1, gg.rng(98))
+    return {"value": rate / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_thread_gteps": rate1 / 1e9,
+            "sample": f"{k} sources drawn uniformly from the {len(pool)} non-isolated vertices of the same graph "
+                      f"(Algorithm 1, FP64, {threads} threads, {dt:.1f} s), scaled to sources x edges / s; "
+                      f"single thread: {k1} sources, {dt1:.1f} s"}
 
 
 def serving(args, sbc):
@@ -178,6 +203,56 @@ def serving(args, sbc):
     print(json.dumps(out), flush=True)
 
 
+def roofline_of(stats, args_graph: bool, workload: str):
+    """Roofline of the dominant traversal kernel of a compressed step: the
+    class with the most algorithmic bytes (the classes' launches overlap in
+    time, so the longest launch need not be the one doing the work), its
+    bytes over its mean launch duration from the plan's HIP events."""
+    last = stats[-1]
+    k_dom = int(np.argmax(last["bytes_class"]))
+    ms_dom = float(np.mean([s["ms_class"][k_dom] for s in stats]))
+    bytes_dom = last["bytes_class"][k_dom]
+    timing = "HIP events around the kernel's launch on its stream"
+    if ms_dom <= 0 and args_graph:
+        # a replayed graph records no per-launch events: the whole traversal span instead
+        ms_dom = float(np.mean([s["ms_traverse"] for s in stats]))
+        bytes_dom = last["algo_bytes"]
+        timing = "graph replay: every traversal launch together (no per-launch events)"
+    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9 if ms_dom > 0 else None
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": load_traffic(workload, k_dom),
+            "kernel": KERNEL_SYMBOLS[k_dom], "kernel_class": CLASS_NAMES[k_dom], "launch_ms": ms_dom,
+            "algo_bytes_per_launch": bytes_dom, "timing": timing}
+
+
+def active_sources(g) -> int:
+    """Vertices with at least one edge: the sources that traverse anything."""
+    return int(np.count_nonzero(np.diff(g.row_ptr) > 0))
+
+
+def compressed_leg(sbc, params, name, steps, warmup, ops):
+    """Compressed step of another workload, for the same JSON line."""
+    desc, make = WORKLOADS[name]
+    progress(f"leg {name}: generating")
+    g = make()
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    t0 = time.perf_counter()
+    prep = G.preprocess(ops)
+    prep_s = time.perf_counter() - t0
+    ctx = sbc.Context(0, params)
+    try:
+        t_c, st_c, _ = timed_run(sbc, ctx, G, sbc.SBC_COMPRESSED, steps, warmup)
+    finally:
+        ctx.close()
+        G.close()
+    na = active_sources(g)
+    return {"workload": f"{name}: {desc}", "n": g.n, "m": g.m, "non_isolated": na, "steps": steps,
+            "warmup": warmup, "ms_per_step": t_c * 1e3, "gteps": na * g.m / t_c / 1e9,
+            "raw_gteps": st_c[-1]["teps"] / t_c / 1e9, "preprocess_s": prep_s, "pieces": prep["pieces"],
+            "class_ms": st_c[-1]["ms_class"], "class_items": st_c[-1]["items_class"],
+            "roofline": roofline_of(st_c, False, name)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +263,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--legs", default="blocktree20000,grid512",
+                    help="comma-separated workloads timed after the main one (compressed only); '' for none")
+    ap.add_argument("--leg-steps", type=int, default=3)
+    ap.add_argument("--leg-warmup", type=int, default=1)
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
     ap.add_argument("--param", action="append", default=[], help="key=value tuning knob")
     ap.add_argument("--verbose", action="store_true")
@@ -231,12 +310,15 @@ def main():
         tuned = autotune.tune(G, sbc.SBC_COMPRESSED, row_ptr=g.row_ptr, col=g.col, log=progress)
         params = dict(tuned, **params)
     ctx = sbc.Context(0, params)
-    nm = float(g.n) * float(g.m)
+    na = active_sources(g)
+    # Sources x edges: every non-isolated vertex is a source that traverses
+    # its component; isolated vertices do no work and are not counted.
+    work = float(na) * float(g.m)
 
     t_c, st_c, res_c = timed_run(sbc, ctx, G, sbc.SBC_COMPRESSED, args.steps, args.warmup, args.graph)
     out = {
         "metric": METRIC,
-        "value": nm / t_c / 1e9,
+        "value": work / t_c / 1e9,
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -247,29 +329,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "n": g.n, "m": g.m, "ops": args.ops,
-                   "parallelism": "single GPU", "hip_graph": bool(args.graph), "params": params,
-                   "autotuned": tuned is not None},
+        "config": {"workload": f"{args.workload}: {desc}", "n": g.n, "m": g.m, "non_isolated": na,
+                   "isolated": g.n - na, "ops": args.ops, "parallelism": "single GPU", "hip_graph": bool(args.graph),
+                   "params": params, "autotuned": tuned is not None,
+                   "value_definition": "non-isolated vertices x undirected edges / step time"},
     }
     last = st_c[-1]
-    # dominant traversal kernel of the compressed step: the class with the
-    # most algorithmic bytes (the classes' launches overlap in time, so the
-    # longest launch need not be the one doing the work)
-    k_dom = int(np.argmax(last["bytes_class"]))
-    ms_dom = float(np.mean([s["ms_class"][k_dom] for s in st_c]))
-    bytes_dom = last["bytes_class"][k_dom]
-    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9 if ms_dom > 0 else 0.0
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                       "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic(args.workload, k_dom),
-                       "kernel": KERNEL_SYMBOLS[k_dom], "kernel_class": CLASS_NAMES[k_dom],
-                       "launch_ms": ms_dom, "algo_bytes_per_launch": bytes_dom}
+    out["roofline"] = roofline_of(st_c, args.graph, args.workload)
     out["compressed"] = {
-        "effective_gteps": nm / t_c / 1e9,
+        "effective_gteps": work / t_c / 1e9,
+        "gteps_all_labels": float(g.n) * float(g.m) / t_c / 1e9,
         "raw_gteps": last["teps"] / t_c / 1e9,
         "kernel_ms": float(np.mean([s["ms_traverse"] for s in st_c])),
         "device_ms": float(np.mean([s["ms_device"] for s in st_c])),
         "preprocess_s": prep_s,
-        "end_to_end_gteps_incl_preprocess": nm / (t_c + prep_s) / 1e9,
+        "end_to_end_gteps_incl_preprocess": work / (t_c + prep_s) / 1e9,
         "prep": {k: prep[k] for k in ("stripped", "blocks", "bridges", "twin_classes", "twins_merged", "pieces",
                                        "piece_vertices", "piece_arcs", "work_teps")},
         "class_ms": last["ms_class"], "class_items": last["items_class"], "class_grid": last["grid_class"],
@@ -280,10 +354,10 @@ def main():
         rel = float(np.max(np.abs(res_c[nz] - res_p[nz]) / np.abs(res_p[nz]))) if nz.any() else 0.0
         lp = st_p[-1]
         kp = int(np.argmax(lp["bytes_class"]))
-        out["plain"] = {"gteps": nm / t_p / 1e9, "ms_per_step": t_p * 1e3,
+        out["plain"] = {"gteps": work / t_p / 1e9, "ms_per_step": t_p * 1e3,
                         "kernel_class": CLASS_NAMES[kp],
                         "hbm_frac": lp["bytes_class"][kp] / (lp["ms_class"][kp] * 1e-3) / 1e9 / PEAK_HBM_GBS
-                        if lp["ms_class"][kp] > 0 else 0.0}
+                        if lp["ms_class"][kp] > 0 else None}
         out["compressed_vs_plain"] = {"speedup": t_p / t_c, "max_rel_diff": rel,
                                       "zero_mismatch": int(np.sum((res_p == 0) != (res_c == 0)))}
     if args.calibrate:
@@ -298,11 +372,18 @@ def main():
         out["phases"] = dict(sbc.sbc_plan_phase_profile(plan), kernel_ms=pst["ms_traverse"])
         sbc.sbc_plan_destroy(plan)
         pctx.close()
+    ctx.close()
+    G.close()
+    legs = [w for w in args.legs.split(",") if w and w != args.workload]
+    if legs:
+        out["legs"] = {}
+        for w in legs:
+            out["legs"][w] = compressed_leg(sbc, params, w, args.leg_steps, args.leg_warmup, args.ops)
+            progress(f"leg {w}: {out['legs'][w]['ms_per_step']:.1f} ms per step")
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle) starts")
         threads = min(os.cpu_count() or 1, 16)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds, threads)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -87,14 +87,14 @@ typedef struct {
   double algo_bytes;         /* streaming-model bytes: per (source, piece) 8*arcs + 56*vertices */
   int64_t items;             /* work items drained from the device queue */
   int64_t batched_sources;   /* sources run by the 64-lane multi-source kernels (batch and team) */
-  int64_t lds_sources;       /* sources run by the LDS-resident kernel */
-  int64_t global_sources;    /* sources run by the one-source-per-workgroup global kernel */
-  int32_t overflow;          /* nonzero if a path count overflowed */
-  /* Per traversal kernel class: 0 small pieces, one source per wavefront (LDS), 1 one source
-   * per workgroup (LDS), 2 64-source batches (one workgroup per batch), 3 one
-   * source per workgroup (global memory), 4 64-source batches run by teams of
-   * workgroups (one team per XCD).  Device time of the class's persistent
-   * launch, its streaming-model bytes, and its sources x edges. */
+  int64_t lds_sources;       /* sources run by the small-piece kernel (state in LDS) */
+  int64_t global_sources;    /* always 0 (no other traversal kernel) */
+  int32_t overflow;          /* device flags of the run (nonzero: a check failed or a path count overflowed) */
+  /* Per traversal kernel class: 0 small pieces, one source per wavefront (LDS),
+   * 2 64-source batches (one workgroup per batch), 4 64-source batches run by
+   * teams of workgroups (one team per XCD); 1 and 3 are not used and stay 0.
+   * Device time of the class's persistent launch, its streaming-model bytes,
+   * and its sources x edges. */
   double ms_class[5];
   double bytes_class[5];
   double teps_class[5];
@@ -123,15 +123,12 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        arcs do not fit 64 KB of LDS go to the batch kernel
  *   "wave_wg_waves"      wavefronts per small-piece workgroup (4 or 8)
  *   "wave_sources_per_item" sources per small-piece work item (1..64)
- *   "lds_max_vertices"   largest piece run by the one-source-per-workgroup LDS kernel
- *   "batch_min_vertices" smallest piece run by the 64-lane multi-source kernel
  *   "batch_wg_waves"     wavefronts per workgroup of the multi-source kernel (4, 8, 16)
  *   "batch_waves_per_eu" occupancy target of the multi-source kernel: 0 (compiler default), 6 or 8 waves per SIMD
  *   "slots"              resident workgroups per traversal kernel (0 = auto)
  *   "cluster_sources"    batch source order: 0 piece order, 1 breadth-first balls,
  *                        2 (default) vertices grouped by a common neighbour of
  *                        degree >= 32 first, then balls
- *   "plain_kernel"       plain mode: 0 automatic, 1 one source per workgroup
  *   "mem_budget_mb"      traversal-state budget of a plan (0: 60% of free memory)
  *   "profile_phases"     1: plans keep per-phase timers of the batch and team kernels
  *   "order_plain"        1: plain plans run on the graph renumbered breadth-first
@@ -158,7 +155,6 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        the launch with SBC_E_DEVICE instead of hanging
  *                        (0: no waiting at all, which aborts any team of more
  *                        than one workgroup: a test of the abort path)
- *   "lds_block", "lds_sources_per_item"
  * Read-only (get only): "cus" compute units, "lds_limit_bytes" LDS per workgroup.
  * Errors: SBC_E_INVALID_ARG for an unknown key or out-of-range value. */
 sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value);
@@ -266,18 +262,37 @@ sbc_status sbc_betweenness_sources(sbc_context ctx, sbc_graph g, int64_t nsrc, c
  * bc_host[v] = sum over sources s of ident[s]*reach[s]*delta_s(v), v != s,
  * where sigma counts paths through v != s with weight ident[v] and delta
  * starts at reach[v]-1.  reach/ident may be NULL (all ones).  `kernel` forces
- * one traversal kernel: 0 automatic, 1 one-source-per-workgroup in global
- * memory, 2 LDS-resident, 3 64-lane multi-source, 4 64-lane multi-source run
- * by teams of workgroups, 5 small-piece kernel (one source per wavefront,
- * everything in LDS).  1 and 2 are switched off in GPU builds
- * (SBC_E_INVALID_ARG).
+ * one traversal kernel: 0 automatic, 3 64-lane multi-source, 4 64-lane
+ * multi-source run by teams of workgroups, 5 small-piece kernel (one source
+ * per wavefront, everything in LDS).  1 and 2 name one-source-per-workgroup
+ * kernels this library does not have (SBC_E_INVALID_ARG).
  * Errors: SBC_E_INVALID_ARG (shape, or a piece too large for the forced kernel). */
 sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
                         const int32_t* reach, const int32_t* ident, int kernel, double* bc_host,
                         sbc_run_stats* st);
 
-/* One source of the same traversal, for verification: dist[n] (int32, -1
- * unreachable), sigma[n], delta[n] (host).  Any output may be NULL. */
+/* Verification of the traversal's per-source state (Algorithm 1's BFS phase,
+ * Section 2.1, and its back propagation, Eq. (3), in the weighted form of
+ * Algorithm 2 with ident, Sections 3.2.1 and 3.3.3) on the same attributed
+ * piece form as sbc_piece_bc.  The sources sources[0..nsrc) (distinct, in
+ * [0, n)) run through traversal kernel `kernel` (0 automatic, 3 batch, 4 team,
+ * 5 small-piece), built with a step that also writes each source's state;
+ * the bc' arithmetic is the same code the other calls run.  Row k of each
+ * output (host, nsrc x n values, any may be NULL) belongs to sources[k]:
+ *   dist[k*n + v]   BFS level of v from sources[k], -1 when unreachable
+ *   sigma[k*n + v]  shortest-path count (ident-weighted through v != source)
+ *   delta[k*n + v]  dependency of v (0 at the source itself and where
+ *                   unreachable)
+ * Errors: SBC_E_INVALID_ARG (shape, kernel, nsrc outside 1..n, duplicate
+ * sources, a piece too large for the forced kernel), SBC_E_INDEX_RANGE (a
+ * source outside [0, n)), SBC_E_TOO_LARGE (nsrc x n >= 2^31). */
+sbc_status sbc_sources_state(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             const int32_t* reach, const int32_t* ident, int32_t nsrc, const int32_t* sources,
+                             int kernel, int32_t* dist, double* sigma, double* delta);
+
+/* sbc_sources_state for the single source s with the automatic kernel choice:
+ * dist[n], sigma[n], delta[n] (host).  Any output may be NULL.
+ * Errors: as sbc_sources_state; SBC_E_INDEX_RANGE when s is outside [0, n). */
 sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
                              const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist,
                              double* sigma, double* delta);

@@ -8,6 +8,7 @@ It shares no code with ``paper_1209_6007_amd`` and never imports it.
 * ``bc_weighted``     Algorithm 2 (Bc-Reach, Section 3.2.1) with the
                       identical-vertex weights of Section 3.3.3, in C, FP64.
 * ``single_source``   per-source levels / path counts / dependencies.
+* ``bc_pieces``       ``bc_weighted`` on every piece of a packed set of pieces.
 * ``brute.bc_bruteforce`` Eq. (1) evaluated pair by pair (tiny graphs).
 
 All scores are over ordered pairs, unnormalised (Eq. (1)).
@@ -51,6 +52,8 @@ def _load():
         lib.oracle_single_source.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int32, i32p,
                                              f64p, f64p]
         lib.oracle_single_source.restype = ctypes.c_int
+        lib.oracle_bc_pieces.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p, ctypes.c_int, f64p]
+        lib.oracle_bc_pieces.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -115,6 +118,26 @@ def single_source(n, row_ptr, col, s: int, reach=None, ident=None):
     if rc != 0:
         raise RuntimeError(f"oracle_single_source failed: {rc}")
     return dist, sig, dl
+
+
+def bc_pieces(vtx_off, row, col, reach=None, ident=None, threads: int | None = None) -> np.ndarray:
+    """bc_weighted of every piece of a packed set (piece p owns packed vertices
+    vtx_off[p]..vtx_off[p+1]-1; row holds absolute arc offsets into col, col
+    piece-local ids); returns bc' per packed vertex."""
+    lib = _load()
+    vo, vop = _i32(vtx_off)
+    rw, rwp = _i32(row)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    re, rep = _i32(reach)
+    idn, idp = _i32(ident)
+    P = len(vo) - 1
+    V = int(vo[-1]) if P > 0 else 0
+    out = np.zeros(max(V, 1), dtype=np.float64)
+    rc = lib.oracle_bc_pieces(int(P), vop, rwp, clp, rep, idp, threads or default_threads(),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise RuntimeError(f"oracle_bc_pieces failed: {rc}")
+    return out[:V]
 
 
 def bc(g, sources=None, threads=None) -> np.ndarray:

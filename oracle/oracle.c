@@ -19,6 +19,9 @@
  *                          by ident).  Returns bc' of the attributed graph.
  *   oracle_single_source-- one source of the weighted algorithm, returning the
  *                          BFS levels, path counts and dependencies.
+ *   oracle_bc_pieces    -- oracle_bc_weighted on every piece of a packed set of
+ *                          pieces (all sources of each piece), for checking a
+ *                          whole shattered graph piece by piece.
  *
  * Threads split the source list into contiguous static blocks; each thread
  * keeps private arrays and the per-thread scores are added in thread order,
@@ -225,4 +228,148 @@ int oracle_single_source(int32_t n, const int32_t *row_ptr, const int32_t *col, 
     }
     ws_free(&w);
     return 0;
+}
+
+/*
+ * Algorithm 2 with identical-vertex weights on every piece of a packed set of
+ * pieces.  Piece p owns packed vertices [vtx_off[p], vtx_off[p+1]); row[] holds
+ * arc offsets into col[] (absolute), col[] piece-local ids; reach/ident are per
+ * packed vertex.  bc_out[V] receives, for each packed vertex, the sum over the
+ * sources of its own piece -- the same quantity oracle_bc_weighted gives for
+ * the piece on its own.
+ *
+ * Threads take contiguous ranges of packed source ids with about equal work
+ * (arcs + vertices of the source's piece); each keeps a private accumulator
+ * over the vertices of the pieces its range touches, and the accumulators are
+ * added in thread order.
+ */
+typedef struct {
+    const int32_t *vtx_off, *row, *col, *reach, *ident;
+    int32_t P;
+    int64_t g0, g1;      /* packed source ids [g0, g1) */
+    int64_t span0;       /* first packed vertex of the accumulator */
+    double *acc;         /* accumulator over [span0, span0 + span) */
+    int32_t maxnp;
+    int64_t maxarcs;
+    int status;
+} pieces_job;
+
+static int32_t piece_of(const int32_t *vtx_off, int32_t P, int64_t g) {
+    int32_t lo = 0, hi = P - 1;
+    while (lo < hi) {               /* last p with vtx_off[p] <= g */
+        int32_t mid = (lo + hi + 1) / 2;
+        if (vtx_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+static void *pieces_worker(void *arg) {
+    pieces_job *J = (pieces_job *)arg;
+    oracle_ws w;
+    int32_t *rel = malloc(((size_t)J->maxnp + 1) * sizeof(int32_t));
+    if (!rel || !ws_alloc(&w, J->maxnp, J->maxarcs)) {
+        free(rel);
+        J->status = -7;
+        return NULL;
+    }
+    int64_t g = J->g0;
+    while (g < J->g1) {
+        int32_t p = piece_of(J->vtx_off, J->P, g);
+        int32_t vb = J->vtx_off[p], np = J->vtx_off[p + 1] - vb;
+        int64_t a0 = J->row[vb];
+        for (int32_t v = 0; v <= np; ++v) rel[v] = (int32_t)(J->row[vb + v] - a0);
+        oracle_job pj;
+        memset(&pj, 0, sizeof pj);
+        pj.n = np;
+        pj.row_ptr = rel;
+        pj.col = J->col + a0;
+        pj.reach = J->reach ? J->reach + vb : NULL;
+        pj.ident = J->ident ? J->ident + vb : NULL;
+        pj.weighted = 1;
+        int64_t gend = (int64_t)vb + np < J->g1 ? (int64_t)vb + np : J->g1;
+        double *acc = J->acc + ((int64_t)vb - J->span0);
+        for (; g < gend; ++g) one_source(&pj, &w, (int32_t)(g - vb), acc);
+    }
+    ws_free(&w);
+    free(rel);
+    J->status = 0;
+    return NULL;
+}
+
+int oracle_bc_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row, const int32_t *col,
+                     const int32_t *reach, const int32_t *ident, int nthreads, double *bc_out) {
+    if (P < 0 || !vtx_off || !row || !bc_out) return -1;
+    int64_t V = P > 0 ? vtx_off[P] : 0;
+    for (int64_t v = 0; v < V; ++v) bc_out[v] = 0.0;
+    if (V == 0) return 0;
+    int32_t maxnp = 1;
+    int64_t maxarcs = 1;
+    double total = 0.0;
+    for (int32_t p = 0; p < P; ++p) {
+        int32_t np = vtx_off[p + 1] - vtx_off[p];
+        int64_t arcs = (int64_t)row[vtx_off[p + 1]] - row[vtx_off[p]];
+        if (np > maxnp) maxnp = np;
+        if (arcs > maxarcs) maxarcs = arcs;
+        total += (double)np * (double)(arcs + np);
+    }
+    if (nthreads < 1) nthreads = 1;
+    if ((int64_t)nthreads > V) nthreads = (int)V;
+    pieces_job *jobs = calloc((size_t)nthreads, sizeof(pieces_job));
+    pthread_t *tid = calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !tid) {
+        free(jobs); free(tid);
+        return -7;
+    }
+    /* equal-work ranges of packed source ids */
+    int64_t g = 0;
+    double done = 0.0;
+    int32_t p = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pieces_job *J = &jobs[t];
+        J->vtx_off = vtx_off; J->row = row; J->col = col; J->reach = reach; J->ident = ident;
+        J->P = P; J->maxnp = maxnp; J->maxarcs = maxarcs; J->status = -1;
+        J->g0 = g;
+        double target = total * (double)(t + 1) / (double)nthreads;
+        while (g < V && (t == nthreads - 1 || done < target)) {
+            while (vtx_off[p + 1] <= g) ++p;
+            int32_t np = vtx_off[p + 1] - vtx_off[p];
+            int64_t arcs = (int64_t)row[vtx_off[p + 1]] - row[vtx_off[p]];
+            done += (double)(arcs + np);
+            ++g;
+        }
+        J->g1 = g;
+    }
+    int rc = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pieces_job *J = &jobs[t];
+        if (J->g1 > J->g0) {
+            int32_t pa = piece_of(vtx_off, P, J->g0), pb = piece_of(vtx_off, P, J->g1 - 1);
+            J->span0 = vtx_off[pa];
+            J->acc = calloc((size_t)(vtx_off[pb + 1] - vtx_off[pa]), sizeof(double));
+            if (!J->acc) rc = -7;
+        }
+    }
+    if (rc == 0) {
+        for (int t = 1; t < nthreads; ++t)
+            if (jobs[t].g1 > jobs[t].g0 && pthread_create(&tid[t], NULL, pieces_worker, &jobs[t]) != 0)
+                jobs[t].status = -99;
+        if (jobs[0].g1 > jobs[0].g0) pieces_worker(&jobs[0]);
+        for (int t = 1; t < nthreads; ++t)
+            if (jobs[t].g1 > jobs[t].g0 && jobs[t].status != -99) pthread_join(tid[t], NULL);
+        for (int t = 0; t < nthreads; ++t) {
+            pieces_job *J = &jobs[t];
+            if (J->g1 <= J->g0) continue;
+            if (J->status == -99) pieces_worker(J); /* thread creation failed: run inline */
+            if (J->status != 0) rc = J->status;
+        }
+        for (int t = 0; t < nthreads && rc == 0; ++t) {
+            pieces_job *J = &jobs[t];
+            if (J->g1 <= J->g0) continue;
+            int32_t pb = piece_of(vtx_off, P, J->g1 - 1);
+            for (int64_t v = J->span0; v < vtx_off[pb + 1]; ++v) bc_out[v] += J->acc[v - J->span0];
+        }
+    }
+    for (int t = 0; t < nthreads; ++t) free(jobs[t].acc);
+    free(jobs); free(tid);
+    return rc;
 }

@@ -123,6 +123,8 @@ _SIGS = {
                       ctypes.POINTER(RunStats)], ctypes.c_int32),
     "sbc_single_source": ([_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p, _f64p, _f64p],
                           ctypes.c_int32),
+    "sbc_sources_state": ([_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int,
+                           _i32p, _f64p, _f64p], ctypes.c_int32),
     "sbc_copy_bandwidth": ([_vp, ctypes.c_size_t, ctypes.c_int, _f64p], ctypes.c_int32),
     "sbc_server_create": ([_vp, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int32),
     "sbc_server_destroy": ([_vp], ctypes.c_int32),
@@ -348,6 +350,22 @@ def sbc_single_source(ctx, n, row_ptr, col, s: int, reach=None, ident=None):
     dl = np.zeros(n, np.float64)
     _check(lib().sbc_single_source(ctx, int(n), rpp, clp, rep, idp, int(s), dist.ctypes.data_as(_i32p),
                                    sig.ctypes.data_as(_f64p), dl.ctypes.data_as(_f64p)))
+    return dist, sig, dl
+
+
+def sbc_sources_state(ctx, n, row_ptr, col, sources, kernel: int = 0, reach=None, ident=None):
+    """(dist, sigma, delta), each [len(sources), n]: row k belongs to sources[k]."""
+    rp, rpp = _i32(row_ptr)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    re, rep = _i32(reach)
+    idn, idp = _i32(ident)
+    sv, svp = _i32(sources)
+    k = len(sv)
+    dist = np.zeros((k, n), np.int32)
+    sig = np.zeros((k, n), np.float64)
+    dl = np.zeros((k, n), np.float64)
+    _check(lib().sbc_sources_state(ctx, int(n), rpp, clp, rep, idp, k, svp, int(kernel),
+                                   dist.ctypes.data_as(_i32p), sig.ctypes.data_as(_f64p), dl.ctypes.data_as(_f64p)))
     return dist, sig, dl
 
 

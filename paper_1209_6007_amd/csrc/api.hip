@@ -90,17 +90,12 @@ sbc_status sbc_context_destroy(sbc_context ctx) {
 static int64_t* param_slot(Params& p, const char* key) {
   const std::string k(key);
   if (k == "wave_max_vertices") return &p.wave_max_vertices;
-  if (k == "lds_max_vertices") return &p.lds_max_vertices;
-  if (k == "batch_min_vertices") return &p.batch_min_vertices;
   if (k == "batch_wg_waves") return &p.batch_wg_waves;
   if (k == "batch_waves_per_eu") return &p.batch_waves_per_eu;
-  if (k == "lds_block") return &p.lds_block;
-  if (k == "lds_sources_per_item") return &p.lds_sources_per_item;
   if (k == "wave_sources_per_item") return &p.wave_sources_per_item;
   if (k == "wave_wg_waves") return &p.wave_wg_waves;
   if (k == "slots") return &p.slots;
   if (k == "cluster_sources") return &p.cluster_sources;
-  if (k == "plain_kernel") return &p.plain_kernel;
   if (k == "mem_budget_mb") return &p.mem_budget_mb;
   if (k == "profile_phases") return &p.profile_phases;
   if (k == "order_plain") return &p.order_plain;
@@ -133,13 +128,9 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "team_local_fences") ok = value == 0 || value == 1;
   if (k == "server_order") ok = value == 0 || value == 1;
   if (k == "team_split_arcs") ok = value >= 64 && value <= (1 << 30);
-  if (k == "lds_block") ok = value == 64 || value == 256 || value == 512 || value == 1024;
-  if (k == "lds_max_vertices") ok = value >= 1 && wg_lds_bytes((int32_t)value) <= ctx->lds_limit;
   if (k == "wave_max_vertices") ok = value >= 0 && value <= kWaveMaxVertices;
   if (k == "wave_wg_waves") ok = value == 4 || value == 8;
   if (k == "wave_sources_per_item") ok = value >= 1 && value <= 64;
-  if (k == "lds_sources_per_item") ok = value >= 1 && value <= (1 << 20);
-  if (k == "batch_min_vertices") ok = value >= 2;
   if (!ok) return fail(SBC_E_INVALID_ARG, std::string("value out of range for ") + key);
   *slot = value;
   return SBC_OK;
@@ -470,7 +461,9 @@ static sbc_status piece_problem(int32_t n, const int32_t* row_ptr, const int32_t
 sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* reach,
                         const int32_t* ident, int kernel, double* bc_host, sbc_run_stats* st) {
   if (!ctx || !bc_host) return fail(SBC_E_INVALID_ARG, "NULL argument");
-  if (kernel < 0 || kernel > 5) return fail(SBC_E_INVALID_ARG, "kernel must be 0..5");
+  if (kernel == 1 || kernel == 2)
+    return fail(SBC_E_INVALID_ARG, "kernels 1 and 2 (one source per workgroup) are not part of this library");
+  if (kernel < 0 || kernel > 5) return fail(SBC_E_INVALID_ARG, "kernel must be 0, 3, 4 or 5");
   SBC_TRY({
     Prepared prob;
     sbc_status rc = piece_problem(n, row_ptr, col, reach, ident, &prob);
@@ -489,31 +482,44 @@ sbc_status sbc_piece_bc(sbc_context ctx, int32_t n, const int32_t* row_ptr, cons
   })
 }
 
-sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
-                             const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist, double* sigma,
-                             double* delta) {
-  if (!ctx) return fail(SBC_E_INVALID_ARG, "NULL context");
-  if (s < 0 || s >= n) return fail(SBC_E_INDEX_RANGE, "source out of range");
+sbc_status sbc_sources_state(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             const int32_t* reach, const int32_t* ident, int32_t nsrc, const int32_t* sources,
+                             int kernel, int32_t* dist, double* sigma, double* delta) {
+  if (!ctx || !sources) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  if (n < 1 || nsrc < 1 || nsrc > n) return fail(SBC_E_INVALID_ARG, "need 1 <= nsrc <= n");
+  if (kernel != 0 && kernel != 3 && kernel != 4 && kernel != 5)
+    return fail(SBC_E_INVALID_ARG, "kernel must be 0, 3, 4 or 5");
+  if ((int64_t)nsrc * (int64_t)n >= ((int64_t)1 << 31)) return fail(SBC_E_TOO_LARGE, "nsrc x n must stay below 2^31");
   SBC_TRY({
     Prepared prob;
     sbc_status rc = piece_problem(n, row_ptr, col, reach, ident, &prob);
     if (rc != SBC_OK) return rc;
     PlanOptions opt;
-    opt.force_kernel = 1;
-    opt.debug_single = true;
-    opt.debug_source = s;
+    opt.force_kernel = kernel;
+    opt.sources = sources;
+    opt.nsrc = nsrc;
+    opt.dump = true;
     Plan plan;
     rc = plan.build(ctx, prob, SBC_COMPRESSED, opt);
     if (rc != SBC_OK) return rc;
     if ((rc = plan.execute(nullptr, nullptr)) != SBC_OK) return rc;
     if ((rc = plan.sync(nullptr)) != SBC_OK) return rc;
+    const size_t cells = (size_t)nsrc * (size_t)n;
     hipError_t e = hipSuccess;
-    if (dist && e == hipSuccess) e = hipMemcpy(dist, plan.dbg.dist, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
-    if (sigma && e == hipSuccess) e = hipMemcpy(sigma, plan.dbg.sigma, sizeof(double) * n, hipMemcpyDeviceToHost);
-    if (delta && e == hipSuccess) e = hipMemcpy(delta, plan.dbg.delta, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (dist && e == hipSuccess) e = hipMemcpy(dist, plan.dump.dist, sizeof(int32_t) * cells, hipMemcpyDeviceToHost);
+    if (sigma && e == hipSuccess) e = hipMemcpy(sigma, plan.dump.sigma, sizeof(double) * cells, hipMemcpyDeviceToHost);
+    if (delta && e == hipSuccess) e = hipMemcpy(delta, plan.dump.delta, sizeof(double) * cells, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "copy result");
     return SBC_OK;
   })
+}
+
+sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist, double* sigma,
+                             double* delta) {
+  if (!ctx) return fail(SBC_E_INVALID_ARG, "NULL context");
+  if (s < 0 || s >= n) return fail(SBC_E_INDEX_RANGE, "source out of range");
+  return sbc_sources_state(ctx, n, row_ptr, col, reach, ident, 1, &s, 0, dist, sigma, delta);
 }
 
 }  // extern "C"

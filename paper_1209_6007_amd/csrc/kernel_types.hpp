@@ -49,20 +49,18 @@ struct WorkItem {
   int32_t kind;
 };
 
-// Optional per-source outputs for the verification entry point.
-struct DebugOut {
+// Per-source state written by the dump variants of the traversal kernels
+// (the verification entry point).  The source with ordinal k in the run's
+// source list and piece vertex v share index k*np + v.  The host fills dist
+// with -1 and delta with 0 first; a kernel writes the level and path count of
+// every vertex a source reaches, and the dependency of every vertex but the
+// source itself.
+struct DumpOut {
   int32_t* dist;
   double* sigma;
   double* delta;
-};
-
-// Per-slot state of the one-source-per-workgroup kernel in global memory.
-struct WgState {
-  int32_t* d;      // [slots][stride]   BFS level, -1 unseen
-  double* sig;     // [slots][stride]   sigma, then the backward coefficient
-  int32_t* q;      // [slots][stride]   BFS order
-  int32_t* lvl;    // [slots][stride+2] level starts
-  int64_t stride;  // vertices per slot
+  int32_t np;
+  int32_t pad_;
 };
 
 // Per-slot state of the 64-source batch kernel in global memory.

@@ -10,20 +10,18 @@
 
 namespace sbc {
 
-// Launchers.  `lds` selects LDS-resident state (max_np vertices per block)
-// or the global-memory state `st`.  `block` in {64, 256, 512, 1024}.
-hipError_t launch_wg(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, bool lds, int block,
-                     int grid, int32_t max_np, const WgState& st, const DebugOut* dbg, hipStream_t stream);
+// Launchers.  `dump`, when not null, runs the kernel's verification variant,
+// which also writes every source's levels, path counts and dependencies there.
 hipError_t launch_ms(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
-                     const MsState& st, hipStream_t stream);
+                     const MsState& st, const DumpOut* dump, hipStream_t stream);
 // Team kernel (a cooperative launch of `grid` workgroups in T.nteams teams);
-// waves in {4, 8, 16}, eu in {0, 8}.
+// waves in {4, 8, 16}, eu in {0, 8} (0 for the dump variant).
 hipError_t launch_team(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int eu, int grid,
-                       const MsState& st, const TeamArgs& T, hipStream_t stream);
+                       const MsState& st, const TeamArgs& T, const DumpOut* dump, hipStream_t stream);
 // Small-piece kernel: one source per wavefront, pieces of at most np_max
 // vertices and arcs_max arcs in LDS; waves in {4, 8}.
 hipError_t launch_wave(const DevPieces& P, const QueueArgs& Q, bool reach, bool ident, int waves, int grid,
-                       int32_t np_max, int32_t arcs_max, hipStream_t stream);
+                       int32_t np_max, int32_t arcs_max, const DumpOut* dump, hipStream_t stream);
 hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
                           const double* bcp, const double* corr, const double* bcx, double scale, double* out,
                           hipStream_t stream);
@@ -33,14 +31,11 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t stream);
 
 // Resident workgroups per compute unit (from the HIP occupancy calculator).
-int occupancy_wg(int block, bool lds, size_t dyn_lds_bytes);
 int occupancy_ms(int waves, int eu);
 // 0 when the configuration is not built or cannot be resident.
-int occupancy_team(int waves, int eu);
+int occupancy_team(int waves, int eu, bool dump);
 int occupancy_wave(int waves, int32_t np_max, int32_t arcs_max);
 
-// LDS bytes the LDS-resident kernel needs for a piece of np vertices.
-size_t wg_lds_bytes(int32_t max_np);
 // Largest LDS allocation a block may use on this device.
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 

@@ -135,135 +135,6 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s_wtot, int* total) {
   return before + incl - x;
 }
 
-// ---------------------------------------------------------------------------
-// One source per workgroup.  State (levels, sigma/coefficient, BFS order,
-// level starts) lives in LDS for pieces that fit, else in a per-workgroup
-// slot of global memory.  Level-synchronous: one barrier per level.
-// ---------------------------------------------------------------------------
-// Row bounds of vertex u, or false (with a flag) when they leave [0, narcs].
-__device__ __forceinline__ bool row_bounds(const int32_t* __restrict__ rowp, int32_t u, int32_t narcs, int32_t* e0,
-                                           int32_t* e1, int32_t* flags) {
-  *e0 = rowp[u];
-  *e1 = rowp[u + 1];
-  if (*e0 < 0 || *e1 < *e0 || *e1 > narcs) {
-    raise_flag(flags, kFlagBadArc);
-    return false;
-  }
-  return true;
-}
-
-// Every value read from memory and then used as an index is range-checked:
-// a bad one raises a flag and is skipped, so corrupted input cannot send a
-// kernel outside its buffers.
-template <int BLOCK, bool REACH, bool IDENT>
-__device__ __forceinline__ void one_source(const int32_t* __restrict__ rowp, const int32_t* __restrict__ col,
-                                           const int32_t narcs, const int32_t* __restrict__ rch,
-                                           const int32_t* __restrict__ idn, const int32_t np, const int32_t s,
-                                           int32_t* d, double* sig, int32_t* q, int32_t* lvl, int* s_cnt,
-                                           double* __restrict__ bcp, int32_t* flags, const DebugOut& dbg) {
-  const int tid = threadIdx.x;
-  double wsrc = 1.0;
-  if (REACH) wsrc *= (double)rch[s];
-  if (IDENT) wsrc *= (double)idn[s];
-  if (tid == 0) {
-    d[s] = 0;
-    sig[s] = 1.0;
-    q[0] = s;
-    lvl[0] = 0;
-    lvl[1] = 1;
-    s_cnt[0] = 0;
-    s_cnt[1] = 0;
-    s_cnt[2] = 0;
-  }
-  __syncthreads();
-  int qs = 0, qe = 1, L = 0;
-  // Forward sweep: expand level L = q[qs, qe) into level L+1.
-  while (true) {
-    if (tid == 0) s_cnt[(L + 1) % 3] = 0;  // counter of level L+1; last read two levels ago
-    for (int i = qs + tid; i < qe; i += BLOCK) {
-      const int32_t u = q[i];
-      int32_t e0, e1;
-      if (u < 0 || u >= np) {
-        raise_flag(flags, kFlagBadArc);
-        continue;
-      }
-      if (!row_bounds(rowp, u, narcs, &e0, &e1, flags)) continue;
-      double su = coherent_load(&sig[u]);  // summed with atomics during the previous level
-      if (IDENT && L > 0) su *= (double)idn[u];
-      for (int32_t e = e0; e < e1; ++e) {
-        const int32_t w = col[e];
-        if (w < 0 || w >= np) {
-          raise_flag(flags, kFlagBadArc);
-          continue;
-        }
-        int32_t dw = coherent_load(&d[w]);
-        if (dw < 0) {
-          const int32_t old = atomicCAS(&d[w], -1, L + 1);
-          if (old == -1) {
-            const int pos = atomicAdd(&s_cnt[L % 3], 1);
-            if (qe + pos < np) q[qe + pos] = w;
-            else raise_flag(flags, kFlagQueueOverflow);
-            dw = L + 1;
-          } else {
-            dw = old;
-          }
-        }
-        if (dw == L + 1) atomicAdd(&sig[w], su);
-      }
-    }
-    __syncthreads();
-    const int nt = min(qe + s_cnt[L % 3], np);
-    if (nt == qe) break;
-    qs = qe;
-    qe = nt;
-    ++L;
-    if (tid == 0) lvl[L + 1] = qe;
-  }
-  if (dbg.dist) {
-    for (int v = tid; v < np; v += BLOCK) {
-      dbg.dist[v] = coherent_load(&d[v]);
-      dbg.sigma[v] = coherent_load(&sig[v]);
-    }
-    __syncthreads();
-  }
-  // Backward sweep, deepest level first.
-  for (int l = L; l >= 1; --l) {
-    const int b = lvl[l], e = lvl[l + 1];
-    for (int i = b + tid; i < e; i += BLOCK) {
-      const int32_t v = q[i];
-      int32_t e0, e1;
-      if (v < 0 || v >= np) {
-        raise_flag(flags, kFlagBadArc);
-        continue;
-      }
-      if (!row_bounds(rowp, v, narcs, &e0, &e1, flags)) continue;
-      double acc = 0.0;
-      for (int32_t x = e0; x < e1; ++x) {
-        const int32_t w = col[x];
-        if (w < 0 || w >= np) continue;  // flagged in the forward sweep
-        // sig[w] now holds w's coefficient; the line may have held atomics' results
-        if (coherent_load(&d[w]) == l + 1) acc += coherent_load(&sig[w]);
-      }
-      const double sv = coherent_load(&sig[v]);
-      const double dv = (REACH ? (double)(rch[v] - 1) : 0.0) + sv * acc;
-      const double coef = (IDENT ? (double)idn[v] : 1.0) * (1.0 + dv) / sv;
-      sig[v] = coef;
-      atomicAdd(&bcp[v], wsrc * dv);
-      if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, kFlagSigmaOverflow);
-      if (dbg.delta) dbg.delta[v] = dv;
-    }
-    __syncthreads();
-  }
-  // Restore the untouched state (-1 / 0) for the next source.
-  for (int i = tid; i < qe; i += BLOCK) {
-    const int32_t v = q[i];
-    if (v < 0 || v >= np) continue;
-    d[v] = -1;
-    sig[v] = 0.0;
-  }
-  __syncthreads();
-}
-
 // Checks shared by the persistent kernels: the item, its piece and its
 // source range.  All values are read by every thread from the same address,
 // so the verdict is uniform across the workgroup.
@@ -285,63 +156,6 @@ __device__ __forceinline__ bool item_ok(const DevPieces& P, const QueueArgs& Q, 
   *vb = b;
   *np = e - b;
   return true;
-}
-
-template <int BLOCK, bool REACH, bool IDENT, bool LDS>
-__global__ __launch_bounds__(BLOCK) void wg_kernel(DevPieces P, QueueArgs Q, WgState st, int32_t max_np,
-                                                   DebugOut dbg) {
-  if (Q.magic != kArgMagic) return;
-  SBC_DYNAMIC_LDS(dyn);
-  __shared__ int s_item;
-  __shared__ int s_cnt[3];
-  const int tid = threadIdx.x;
-  double* sig;
-  int32_t *d, *q, *lvl;
-  if constexpr (LDS) {
-    sig = reinterpret_cast<double*>(dyn);
-    d = reinterpret_cast<int32_t*>(sig + max_np);
-    q = d + max_np;
-    lvl = q + max_np;
-  } else {
-    const size_t b = blockIdx.x;
-    sig = st.sig + b * st.stride;
-    d = st.d + b * st.stride;
-    q = st.q + b * st.stride;
-    lvl = st.lvl + b * (st.stride + 2);
-  }
-  const int64_t cap = LDS ? (int64_t)max_np : st.stride;
-  while (true) {
-    if (tid == 0) s_item = atomicAdd(Q.head, 1);
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it < 0 || it >= Q.nitems) break;
-    const WorkItem W = Q.items[it];
-    int32_t vb, np;
-    if (item_ok(P, Q, W, cap, &vb, &np)) {
-      const int32_t* rowp = P.row + vb;
-      const int32_t* rch = REACH ? P.reach + vb : nullptr;
-      const int32_t* idn = IDENT ? P.ident + vb : nullptr;
-      double* bcp = P.bcp + vb;
-      if constexpr (LDS) {
-        for (int v = tid; v < np; v += BLOCK) {
-          d[v] = -1;
-          sig[v] = 0.0;
-        }
-        __syncthreads();
-      }
-      for (int32_t k = W.s0; k < W.s1; ++k) {
-        const int32_t s = P.src_order[vb + k];
-        if (s < 0 || s >= np) {
-          if (tid == 0) raise_flag(Q.flags, kFlagBadSource);
-          continue;
-        }
-        one_source<BLOCK, REACH, IDENT>(rowp, P.col, P.narcs, rch, idn, np, s, d, sig, q, lvl, s_cnt, bcp, Q.flags,
-                                        dbg);
-      }
-    }
-    if (tid == 0) atomicAdd(Q.done, 1);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -651,15 +465,18 @@ __device__ __forceinline__ BackEarly back_early(const double* __restrict__ sg, c
 // Backward finish of entry (v, level) with lanes amask and pulled sum acc:
 // delta (Eq. (3) in pull form), the coefficient that replaces sigma, the
 // wave's contribution to bc'[v] (weighted by ident[s]*reach[s] in wsrc) and
-// the level's backward mask.
+// the level's backward mask.  drow, when not null, is the lane's row of the
+// dependency dump.
 __device__ __forceinline__ void back_finish(double* __restrict__ sg, double* __restrict__ bcp,
                                             uint64_t* __restrict__ bw, int32_t v, uint64_t amask, double acc,
-                                            const BackEarly& pre, double wsrc, int lane, int32_t* flags) {
+                                            const BackEarly& pre, double wsrc, int lane, int32_t* flags,
+                                            double* drow) {
   double contrib = 0.0;
   if ((amask >> lane) & 1) {
     const double dv = pre.rm1 + pre.sv * acc;
     sg[(size_t)v * 64 + lane] = pre.id * (1.0 + dv) / pre.sv;
     contrib = wsrc * dv;
+    if (drow) drow[v] = dv;
     if (!(pre.sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, kFlagSigmaOverflow);
   }
   contrib = wave_sum(contrib);
@@ -672,8 +489,10 @@ __device__ __forceinline__ void back_finish(double* __restrict__ sg, double* __r
 // EU > 0 asks the compiler for at least EU resident waves per SIMD (it then
 // keeps the kernel within 512/EU VGPRs); the kernel is latency-bound, so more
 // waves in flight can matter more than registers.
-template <int WAVES, int EU, bool REACH, bool IDENT>
-__global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueArgs Q, MsState st) {
+// DUMP builds the verification variant: it also writes every source's
+// levels, path counts and dependencies to `dump` (null otherwise).
+template <int WAVES, int EU, bool REACH, bool IDENT, bool DUMP = false>
+__global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueArgs Q, MsState st, DumpOut dump) {
   if (Q.magic != kArgMagic) return;
   constexpr int BLOCK = WAVES * 64;
   __shared__ int s_item;
@@ -929,6 +748,24 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
     mark(kProfPhaseC);
     const int total = qe;
     const int Lmax = L;
+    // Lane j's dump row is that of source ordinal s0 + j.
+    double* drow = nullptr;
+    if constexpr (DUMP) {
+      if (lane < nsrc) drow = dump.delta + (size_t)(W.s0 + lane) * dump.np;
+      // Levels and path counts of every entry, before the backward sweep
+      // overwrites sigma with coefficients.
+      for (int l = 0; l <= Lmax; ++l)
+        for (int i = lvl[l] + wave; i < lvl[l + 1]; i += WAVES) {
+          const int32_t v = q[i];
+          const uint64_t m = qm[i];
+          if (v >= 0 && v < np && lane < nsrc && ((m >> lane) & 1)) {
+            const size_t o = (size_t)(W.s0 + lane) * dump.np + v;
+            dump.dist[o] = l;
+            dump.sigma[o] = sg[(size_t)v * 64 + lane];
+          }
+        }
+      __syncthreads();
+    }
 
     // ---------------- backward sweep ----------------
     for (int l = Lmax; l >= 1; --l) {
@@ -967,7 +804,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         return back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
       };
       auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, const BackEarly& pre) {
-        back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags);
+        back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
       };
       for (int first = b + wave; first < e; first += WAVES * 64)
         pull_list(first, WAVES, min(64, (e - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, br, sg, idn,
@@ -1003,7 +840,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
-          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags);
+          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
         }
         __syncthreads();
         mark(kProfBackHeavy);
@@ -1077,8 +914,9 @@ __device__ __forceinline__ void ctl_store(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int WAVES, int EU, bool REACH, bool IDENT>
-__global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, QueueArgs Q, MsState st, TeamArgs T) {
+template <int WAVES, int EU, bool REACH, bool IDENT, bool DUMP = false>
+__global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, QueueArgs Q, MsState st, TeamArgs T,
+                                                                 DumpOut dump) {
   if (Q.magic != kArgMagic) return;
   constexpr int BLOCK = WAVES * 64;
   SBC_DYNAMIC_LDS(lds_raw);
@@ -1497,6 +1335,22 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
     }
     const int total = qe;
     const int Lmax = L;
+    double* drow = nullptr;  // lane j's dump row: source ordinal s0 + j
+    if constexpr (DUMP) {
+      if (lane < nsrc) drow = dump.delta + (size_t)(W.s0 + lane) * dump.np;
+      for (int l = 0; l <= Lmax; ++l)
+        for (int i = lvl[l] + gwave; i < lvl[l + 1]; i += twaves) {
+          const int32_t v = q[i];
+          const uint64_t m = qm[i];
+          if (v >= 0 && v < np && lane < nsrc && ((m >> lane) & 1)) {
+            const size_t o = (size_t)(W.s0 + lane) * dump.np + v;
+            dump.dist[o] = l;
+            dump.sigma[o] = sg[(size_t)v * 64 + lane];
+          }
+        }
+      // the backward sweep overwrites sigma only after every wave has dumped it
+      if (!team_sync(kProfPhaseC)) break;
+    }
 
     // ---------------- backward sweep ----------------
     // Level l writes the masks of array l mod 3 and reads those of level l+1;
@@ -1539,7 +1393,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       auto early_b = [](int, int32_t, uint64_t) { return 0; };
       auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, int) {
         back_finish(sg, bcp, bw, v, amask, acc, back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane), wsrc, lane,
-                    Q.flags);
+                    Q.flags, drow);
       };
       grabbed(hs, b, e, [&](int i0, int i1) {
         pull_entries<kGroup>(i0, i1, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags, need_b, defer_b,
@@ -1581,7 +1435,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
-          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags);
+          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
         }
         if (!team_sync(kProfBackHeavy)) {
           alive = false;
@@ -1643,9 +1497,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   wave_sync();
 }
 
-template <int WAVES, bool REACH, bool IDENT>
-__global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs Q, int32_t np_max,
-                                                          int32_t arcs_max) {
+template <int WAVES, bool REACH, bool IDENT, bool DUMP = false>
+__global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs Q, int32_t np_max, int32_t arcs_max,
+                                                          DumpOut dump) {
   if (Q.magic != kArgMagic) return;
   if (np_max < 1 || np_max > kWaveMaxVertices || arcs_max < 0) return;  // every workgroup leaves together
   constexpr int BLOCK = WAVES * 64;
@@ -1802,6 +1656,17 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
         if (lane == 0) lvl[L + 1] = (uint16_t)qe;
         wave_lds_sync();
       }
+      double* drow = nullptr;  // this source's dump row
+      if constexpr (DUMP) {
+        const size_t o = (size_t)(W.s0 + j) * dump.np;
+        drow = dump.delta + o;
+        for (int i = lane; i < qe; i += 64) {
+          const int v = q[i];
+          dump.dist[o + v] = d[v];
+          dump.sigma[o + v] = sig[v];
+        }
+        wave_lds_sync();  // every lane has read sigma before the backward sweep overwrites it
+      }
       // ---------------- backward sweep ----------------
       for (int l = L; l >= 1; --l) {
         const int b = lvl[l], e = lvl[l + 1];
@@ -1817,6 +1682,7 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
           const double dv = (REACH ? (double)(s_rch[v] - 1) : 0.0) + sv * acc;
           sig[v] = (IDENT ? (double)s_idn[v] : 1.0) * (1.0 + dv) / sv;
           atomicAdd(&s_bc[v], wsrc * dv);
+          if constexpr (DUMP) drow[v] = dv;
           if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
         }
         wave_lds_sync();

@@ -96,9 +96,9 @@ size_t Plan::device_bytes() const {
   size_t t = 0;
   for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
                           &d_map_off, &d_map_idx, &d_out, &d_ctl, &ms_sg, &ms_q, &ms_qm, &ms_vis, &ms_fa, &ms_fb,
-                          &ms_ba, &ms_bb, &ms_lvl, &ms_part, &ms_prof, &wg_d, &wg_sig, &wg_q, &wg_lvl, &tm_sg, &tm_q,
-                          &tm_qm, &tm_vis, &tm_fa, &tm_fb, &tm_fc, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof,
-                          &tm_ctl, &tm_heavy})
+                          &ms_ba, &ms_bb, &ms_lvl, &ms_part, &ms_prof, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
+                          &tm_fc, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof, &tm_ctl, &tm_heavy, &dump_dist,
+                          &dump_sigma, &dump_delta})
     t += b->bytes;
   for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes;
   return t;
@@ -112,7 +112,6 @@ size_t ms_slot_bytes(int64_t stride, int64_t part_cap) {
   return (size_t)stride * 64 * (8 + 4 + 8) + (size_t)stride * 8 * 5 + (size_t)(stride + 3) * 4 +
          (size_t)part_cap * 64 * 8;
 }
-size_t wg_slot_bytes(int64_t stride) { return (size_t)stride * 16 + (size_t)(stride + 2) * 4; }
 
 // Long rows (more than `split` arcs) of piece p and their slices: the team
 // kernel registers at most that many per level, since a vertex has at most
@@ -157,22 +156,14 @@ int64_t bfs_depth(const Prepared& prob, int32_t p) {
 }
 
 // Kernel class of a piece of np vertices (before the LDS-size checks).
-int classify(const Params& pr, int32_t np, bool plain, int force) {
+int classify(const Params& pr, int32_t np, int force) {
   if (force == 5) return KC_WAVE;
   if (force == 4) return KC_TEAM;
   if (force == 3) return KC_BATCH;
   const bool team = pr.team_min_vertices > 0 && np >= pr.team_min_vertices;
   // The team threshold wins where the two overlap.
-  const bool small = force == 0 && !team && !(plain && pr.plain_kernel == 1) && np <= pr.wave_max_vertices;
-  if (small) return KC_WAVE;
-  if (!kPerSourceKernelsEnabled) return team ? KC_TEAM : KC_BATCH;
-  if (force == 1) return KC_GLOBAL;
-  if (force == 2) return KC_LDS;
-  if (plain && pr.plain_kernel == 1) return KC_GLOBAL;
-  if (team) return KC_TEAM;
-  if (np >= pr.batch_min_vertices) return KC_BATCH;
-  if (np <= pr.lds_max_vertices) return KC_LDS;
-  return KC_GLOBAL;
+  if (!team && np <= pr.wave_max_vertices) return KC_WAVE;
+  return team ? KC_TEAM : KC_BATCH;
 }
 
 // LDS the small-piece kernel may give one workgroup (at most 64 KB, so that
@@ -184,11 +175,11 @@ size_t wave_lds_budget(const sbc_context_s* c) { return std::min<size_t>(c->lds_
 size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
   size_t t = (size_t)prob.V() * (4 * 4 + 8 * 2) + prob.A() * 4 + (size_t)prob.n * (8 * 2 + 4) +
              prob.map_idx.size() * 4 + (size_t)prob.pieces() * 4;
-  int64_t max_batch = 0, max_batch_arcs = 0, max_glob = 0, max_team = 0, max_team_slices = 1;
+  int64_t max_batch = 0, max_batch_arcs = 0, max_team = 0, max_team_slices = 1;
   for (int32_t p = 0; p < prob.pieces(); ++p) {
     int32_t np = prob.vtx_off[p + 1] - prob.vtx_off[p];
     const int64_t arcs = prob.row[prob.vtx_off[p + 1]] - prob.row[prob.vtx_off[p]];
-    int k = classify(c->params, np, false, 0);
+    int k = classify(c->params, np, 0);
     if (k == KC_BATCH) {
       max_batch = std::max<int64_t>(max_batch, np);
       max_batch_arcs = std::max<int64_t>(max_batch_arcs, arcs);
@@ -199,13 +190,11 @@ size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
       max_team = std::max<int64_t>(max_team, np);
       max_team_slices = std::max<int64_t>(max_team_slices, slices);
     }
-    if (k == KC_GLOBAL) max_glob = std::max<int64_t>(max_glob, np);
   }
   if (max_batch) t += ms_slot_bytes(max_batch, max_batch_arcs / kMsSliceArcs + 2 * kMsHeavyMax) * 4;
   if (max_team)
     t += (ms_slot_bytes(max_team, max_team_slices) + (size_t)max_team * 16) *
          std::max<int64_t>(1, c->params.team_count);
-  if (max_glob) t += wg_slot_bytes(max_glob) * 16;
   return t;
 }
 
@@ -217,8 +206,10 @@ sbc_status Plan::build(sbc_context c, const Prepared& prob, uint32_t mode, const
 
 sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mode, const PlanOptions& opt) {
   ctx = c;
-  if (!kPerSourceKernelsEnabled && (opt.force_kernel == 1 || opt.force_kernel == 2 || opt.debug_single))
-    return fail(SBC_E_INVALID_ARG, "the one-source-per-workgroup kernels are switched off in this build");
+  if (opt.force_kernel != 0 && opt.force_kernel != 3 && opt.force_kernel != 4 && opt.force_kernel != 5)
+    return fail(SBC_E_INVALID_ARG, "kernel must be 0 (automatic), 3 (batch), 4 (team) or 5 (small-piece)");
+  if ((opt.sources || opt.dump) && prob_in.pieces() != 1)
+    return fail(SBC_E_INVALID_ARG, "a source list needs a one-piece problem");
   const Params& pr = c->params;
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -237,10 +228,10 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   const bool plain = !(mode & SBC_COMPRESSED);
   const Prepared* probp = &prob_in;
   Prepared local;
-  if (opt.sources || opt.debug_single || (pr.cluster_sources && prob_in.pieces() > 0)) {
+  if (opt.sources || (pr.cluster_sources && prob_in.pieces() > 0)) {
     local = prob_in;
     probp = &local;
-    if (pr.cluster_sources && !opt.sources && !opt.debug_single) cluster_sources(&local, 64, (int)pr.cluster_sources);
+    if (pr.cluster_sources && !opt.sources) cluster_sources(&local, 64, (int)pr.cluster_sources);
     if (opt.sources) {
       // plain graph, one piece: the listed sources first
       std::vector<uint8_t> seen(local.n, 0);
@@ -255,7 +246,6 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       for (int32_t v = 0; v < local.n; ++v)
         if (!seen[v]) local.src_order[k++] = v;
     }
-    if (opt.debug_single) local.src_order[0] = opt.debug_source;
   }
   const Prepared& prob = *probp;
   n = prob.n;
@@ -275,7 +265,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   for (int32_t p = 0; p < P; ++p) {
     const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
     const int64_t arcs = (int64_t)prob.row[vb + np] - prob.row[vb];
-    int k = classify(pr, np, plain, opt.force_kernel);
+    int k = classify(pr, np, opt.force_kernel);
     // Deep pieces (many BFS levels) pay a team barrier per phase and level:
     // with team_max_levels set they stay on the one-workgroup kernel.
     if (k == KC_TEAM && opt.force_kernel != 4 && pr.team_max_levels > 0 &&
@@ -290,21 +280,11 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       if (opt.force_kernel == 5) return fail(SBC_E_INVALID_ARG, "piece too large for the small-piece kernel");
       k = (pr.team_min_vertices > 0 && np >= pr.team_min_vertices) ? KC_TEAM : KC_BATCH;
     }
-    if (k == KC_LDS) {
-      if (wg_lds_bytes(np) > c->lds_limit) {
-        if (opt.force_kernel == 2) return fail(SBC_E_INVALID_ARG, "piece too large for the LDS kernel");
-        k = (np >= 64) ? KC_BATCH : KC_GLOBAL;
-      }
-    }
     piece_class[p] = k;
     int32_t nsrc = np;
     if (opt.sources) nsrc = (int32_t)opt.nsrc;
-    if (opt.debug_single) nsrc = 1;
     if (nsrc <= 0) continue;
-    int32_t chunk = 1;
-    if (k == KC_WAVE) chunk = (int32_t)std::min<int64_t>(64, pr.wave_sources_per_item);
-    if (k == KC_LDS) chunk = (int32_t)pr.lds_sources_per_item;
-    if (k == KC_BATCH || k == KC_TEAM) chunk = 64;
+    const int32_t chunk = k == KC_WAVE ? (int32_t)std::min<int64_t>(64, pr.wave_sources_per_item) : 64;
     const double per = 8.0 * arcs + (plain ? 48.0 : (reach || ident ? 56.0 : 48.0)) * np;
     for (int32_t s0 = 0; s0 < nsrc; s0 += chunk) {
       const int32_t s1 = std::min(nsrc, s0 + chunk);
@@ -370,8 +350,6 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   (void)hipMemGetInfo(&freeb, &totalb);
   size_t budget = pr.mem_budget_mb > 0 ? (size_t)pr.mem_budget_mb << 20 : (size_t)(freeb * 0.6);
   const int cus = c->cus;
-  block[KC_LDS] = (int)pr.lds_block;
-  block[KC_GLOBAL] = 256;
   block[KC_BATCH] = (int)pr.batch_wg_waves * 64;
   if (nitems[KC_WAVE]) {
     // The launch's LDS holds the largest piece's vertices and the most arcs
@@ -395,33 +373,6 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (pr.slots > 0) g = (int)pr.slots;
     grid[KC_WAVE] = std::max(1, std::min(g, nitems[KC_WAVE]));
   }
-  for (int k : {KC_LDS}) {
-    if (!nitems[k]) continue;
-    const int occ = occupancy_wg(block[k], true, wg_lds_bytes(max_np[k]));
-    int g = cus * occ;
-    if (pr.slots > 0) g = (int)pr.slots;
-    grid[k] = std::max(1, std::min(g, nitems[k]));
-  }
-  if (nitems[KC_GLOBAL]) {
-    const int64_t stride = max_np[KC_GLOBAL];
-    const int occ = occupancy_wg(block[KC_GLOBAL], false, 0);
-    int g = cus * occ;
-    if (pr.slots > 0) g = (int)pr.slots;
-    g = std::min<int64_t>(g, std::max<int64_t>(1, (int64_t)(budget / 2 / wg_slot_bytes(stride))));
-    g = std::max(1, std::min(g, nitems[KC_GLOBAL]));
-    grid[KC_GLOBAL] = g;
-    wg.stride = stride;
-    if ((e = wg_d.alloc((size_t)g * stride * 4)) != hipSuccess) return hip_fail(e, "alloc wg d");
-    if ((e = wg_sig.alloc((size_t)g * stride * 8)) != hipSuccess) return hip_fail(e, "alloc wg sig");
-    if ((e = wg_q.alloc((size_t)g * stride * 4)) != hipSuccess) return hip_fail(e, "alloc wg q");
-    if ((e = wg_lvl.alloc((size_t)g * (stride + 2) * 4)) != hipSuccess) return hip_fail(e, "alloc wg lvl");
-    wg.d = wg_d.as<int32_t>();
-    wg.sig = wg_sig.as<double>();
-    wg.q = wg_q.as<int32_t>();
-    wg.lvl = wg_lvl.as<int32_t>();
-    if ((e = launch_fill_i32(wg.d, -1, (int64_t)g * stride, own)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_fill_f64(wg.sig, 0.0, (int64_t)g * stride, own)) != hipSuccess) return hip_fail(e, "fill");
-  }
   if (nitems[KC_BATCH]) {
     const int64_t stride = max_np[KC_BATCH];
     int64_t max_arcs = 0;
@@ -431,7 +382,8 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
         max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
     }
     const int64_t part_cap = max_arcs / kMsSliceArcs + 2 * kMsHeavyMax;
-    const int occ = occupancy_ms((int)pr.batch_wg_waves, (int)pr.batch_waves_per_eu);
+    batch_eu = opt.dump ? 0 : (int)pr.batch_waves_per_eu;  // the dump variant: compiler default only
+    const int occ = occupancy_ms((int)pr.batch_wg_waves, batch_eu);
     int g = cus * occ;
     if (pr.slots > 0) g = (int)pr.slots;
     const size_t per = ms_slot_bytes(stride, part_cap);
@@ -483,7 +435,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       max_slices = std::max(max_slices, slices);
     }
     team_waves = (int)pr.batch_wg_waves;
-    team_eu = pr.team_waves_per_eu > 0 ? 8 : 0;
+    team_eu = (pr.team_waves_per_eu > 0 && !opt.dump) ? 8 : 0;
     block[KC_TEAM] = team_waves * 64;
     int coop = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess) {
@@ -491,7 +443,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       coop = 0;
     }
     if (!coop) return fail(SBC_E_DEVICE, "the device does not support cooperative launches (team kernel)");
-    const int occ = occupancy_team(team_waves, team_eu);
+    const int occ = occupancy_team(team_waves, team_eu, opt.dump);
     if (occ <= 0) return fail(SBC_E_INVALID_ARG, "team kernel configuration cannot be resident");
     const int nteams = (int)std::max<int64_t>(1, pr.team_count);
     int g = cus * occ;
@@ -537,13 +489,18 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     targs.split_arcs = (int32_t)pr.team_split_arcs;
     targs.spin_ticks = (int64_t)((double)pr.team_spin_ms * c->wall_khz);
   }
-  if (opt.debug_single) {
-    const int64_t np = V;
-    if ((e = dbg_dist.alloc(np * 4)) != hipSuccess) return hip_fail(e, "alloc dbg");
-    if ((e = dbg_sigma.alloc(np * 8)) != hipSuccess) return hip_fail(e, "alloc dbg");
-    if ((e = dbg_delta.alloc(np * 8)) != hipSuccess) return hip_fail(e, "alloc dbg");
-    dbg = {dbg_dist.as<int32_t>(), dbg_sigma.as<double>(), dbg_delta.as<double>()};
-    if ((e = launch_fill_f64(dbg.delta, 0.0, np, own)) != hipSuccess) return hip_fail(e, "fill dbg");
+  if (opt.dump) {
+    // One row of V values per listed source; rows start unreached (-1) and
+    // with no dependency (0), which the traversal leaves at the source.
+    dump_rows = opt.sources ? opt.nsrc : V;
+    const size_t cells = (size_t)std::max<int64_t>(1, dump_rows) * (size_t)std::max<int64_t>(1, V);
+    if ((e = dump_dist.alloc(cells * 4)) != hipSuccess) return hip_fail(e, "alloc dump");
+    if ((e = dump_sigma.alloc(cells * 8)) != hipSuccess) return hip_fail(e, "alloc dump");
+    if ((e = dump_delta.alloc(cells * 8)) != hipSuccess) return hip_fail(e, "alloc dump");
+    dump = {dump_dist.as<int32_t>(), dump_sigma.as<double>(), dump_delta.as<double>(), (int32_t)V, 0};
+    if ((e = launch_fill_i32(dump.dist, -1, (int64_t)cells, own)) != hipSuccess) return hip_fail(e, "fill dump");
+    if ((e = launch_fill_f64(dump.sigma, 0.0, (int64_t)cells, own)) != hipSuccess) return hip_fail(e, "fill dump");
+    if ((e = launch_fill_f64(dump.delta, 0.0, (int64_t)cells, own)) != hipSuccess) return hip_fail(e, "fill dump");
   }
   if ((e = hipStreamSynchronize(own)) != hipSuccess) return hip_fail(e, "plan setup");
   return SBC_OK;
@@ -571,7 +528,8 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
   // Largest classes first so the long multi-source items start early.  The
   // team kernel occupies the whole device, so the other classes follow it.
-  const int order[KC_COUNT] = {KC_TEAM, KC_BATCH, KC_GLOBAL, KC_LDS, KC_WAVE};
+  const DumpOut* dp_dump = dump.dist ? &dump : nullptr;
+  const int order[3] = {KC_TEAM, KC_BATCH, KC_WAVE};
   for (int k : order) {
     if (!nitems[k]) continue;
     hipStream_t ks = side[k];
@@ -580,14 +538,11 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
     if (!use_graph && (e = hipEventRecord(ev_kc_start[k], ks)) != hipSuccess) return hip_fail(e, "event");
     QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], kArgMagic, heads + k, flags, done + k};
     if (k == KC_TEAM) {
-      e = launch_team(dp, qa, reach, ident, team_waves, team_eu, grid[k], tm, targs, ks);
+      e = launch_team(dp, qa, reach, ident, team_waves, team_eu, grid[k], tm, targs, dp_dump, ks);
     } else if (k == KC_BATCH) {
-      e = launch_ms(dp, qa, reach, ident, block[k] / 64, (int)ctx->params.batch_waves_per_eu, grid[k], ms, ks);
-    } else if (k == KC_WAVE) {
-      e = launch_wave(dp, qa, reach, ident, wave_waves, grid[k], wave_np, wave_arcs, ks);
+      e = launch_ms(dp, qa, reach, ident, block[k] / 64, (int)batch_eu, grid[k], ms, dp_dump, ks);
     } else {
-      const bool lds = k == KC_LDS;
-      e = launch_wg(dp, qa, reach, ident, lds, block[k], grid[k], max_np[k], wg, dbg.dist ? &dbg : nullptr, ks);
+      e = launch_wave(dp, qa, reach, ident, wave_waves, grid[k], wave_np, wave_arcs, dp_dump, ks);
     }
     if (e != hipSuccess) return hip_fail(e, "launch traversal");
     if ((e = hipEventRecord(ev_kc_end[k], ks)) != hipSuccess) return hip_fail(e, "event");
@@ -701,8 +656,8 @@ sbc_status Plan::sync(sbc_run_stats* st) {
     st->algo_bytes = algo_bytes;
     st->items = total_items;
     st->batched_sources = sources_in[KC_BATCH] + sources_in[KC_TEAM];
-    st->lds_sources = sources_in[KC_LDS] + sources_in[KC_WAVE];
-    st->global_sources = sources_in[KC_GLOBAL];
+    st->lds_sources = sources_in[KC_WAVE];
+    st->global_sources = 0;
     st->overflow = flags;
     for (int k = 0; k < KC_COUNT; ++k) {
       st->ms_class[k] = class_ms[k];

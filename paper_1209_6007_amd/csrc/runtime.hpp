@@ -37,16 +37,11 @@ struct DevBuf {
 struct Params {
   int64_t wave_max_vertices = 256;    // pieces up to this size: small-piece kernel (0: never)
   int64_t wave_wg_waves = 4;          // wavefronts per small-piece workgroup (4 or 8)
-  int64_t lds_max_vertices = 4096;    // pieces up to this size: one source per workgroup, LDS state
-  int64_t batch_min_vertices = 4097;  // pieces from this size: 64-source batches
   int64_t batch_wg_waves = 8;         // wavefronts per multi-source workgroup
   int64_t batch_waves_per_eu = 8;     // occupancy target of the batch kernel (0, 6 or 8 waves per SIMD)
-  int64_t lds_block = 256;            // threads per LDS workgroup
-  int64_t lds_sources_per_item = 32;  // sources per LDS work item
   int64_t wave_sources_per_item = 64; // sources per small-piece work item (at most 64)
   int64_t slots = 0;                  // resident workgroups per kernel (0: from occupancy)
   int64_t cluster_sources = 2;        // batch source order: 0 as is, 1 balls, 2 common-hub groups then balls
-  int64_t plain_kernel = 0;           // plain mode: 0 automatic, 1 one source per workgroup (global)
   int64_t mem_budget_mb = 0;          // traversal state budget (0: 60% of free memory)
   int64_t profile_phases = 0;         // 1: per-phase timers in the batch kernel
   int64_t order_plain = 0;            // 1: plain problems renumbered breadth-first
@@ -85,29 +80,16 @@ struct sbc_graph_s {
 namespace sbc {
 
 // KC_WAVE: small-piece kernel (one source per wavefront, the piece in LDS).
-// KC_LDS, KC_GLOBAL: one source per workgroup, state in LDS / global memory.
 // KC_BATCH: 64-source batches, one workgroup per batch.  KC_TEAM: 64-source
-// batches, one team of workgroups per batch.
-enum KernelClass { KC_WAVE = 0, KC_LDS = 1, KC_BATCH = 2, KC_GLOBAL = 3, KC_TEAM = 4, KC_COUNT = 5 };
-
-// The one-source-per-workgroup kernels (LDS and global-memory state) are
-// switched off: their first runs on the GPU ended in a memory fault whose
-// cause has not been found.  Every piece then runs on the 64-source batch
-// kernel, and the entry points that force a per-source kernel report
-// SBC_E_INVALID_ARG.
-// (The CPU-emulated test build re-enables them to keep checking their logic.)
-#ifdef SBC_ENABLE_PER_SOURCE_KERNELS
-constexpr bool kPerSourceKernelsEnabled = true;
-#else
-constexpr bool kPerSourceKernelsEnabled = false;
-#endif
+// batches, one team of workgroups per batch.  Classes 1 and 3 are not used
+// (their slots in sbc_run_stats stay zero).
+enum KernelClass { KC_WAVE = 0, KC_BATCH = 2, KC_TEAM = 4, KC_COUNT = 5 };
 
 struct PlanOptions {
-  int force_kernel = 0;                 // 0 automatic, 1 global, 2 LDS, 3 batch, 4 team, 5 small-piece
-  const int32_t* sources = nullptr;     // plain-mode source subset (host), or null
+  int force_kernel = 0;                 // 0 automatic, 3 batch, 4 team, 5 small-piece
+  const int32_t* sources = nullptr;     // one-piece problems: source subset (host), or null for all
   int64_t nsrc = 0;
-  bool debug_single = false;            // one source, keep per-vertex outputs
-  int32_t debug_source = 0;
+  bool dump = false;                    // keep every listed source's levels, path counts and dependencies
 };
 
 struct Plan {
@@ -127,7 +109,7 @@ struct Plan {
   int32_t nitems[KC_COUNT] = {0, 0, 0, 0, 0};
   int32_t max_np[KC_COUNT] = {0, 0, 0, 0, 0};
   int grid[KC_COUNT] = {0, 0, 0, 0, 0};
-  int block[KC_COUNT] = {64, 256, 1024, 256, 512};
+  int block[KC_COUNT] = {256, 0, 512, 0, 512};
   int64_t sources_in[KC_COUNT] = {0, 0, 0, 0, 0};
   // slot state
   DevBuf ms_sg, ms_q, ms_qm, ms_vis, ms_fa, ms_fb, ms_ba, ms_bb, ms_lvl, ms_part, ms_prof;
@@ -140,12 +122,12 @@ struct Plan {
   MsState tm{};
   TeamArgs targs{};
   int team_waves = 8, team_eu = 8;
+  int batch_eu = 8;                         // occupancy target of the batch kernel's launch
   int wave_waves = 4;                       // small-piece kernel: waves per workgroup
   int32_t wave_np = 0, wave_arcs = 0;       // its LDS is sized for these
-  DevBuf wg_d, wg_sig, wg_q, wg_lvl;
-  WgState wg{};
-  DebugOut dbg{nullptr, nullptr, nullptr};
-  DevBuf dbg_dist, dbg_sigma, dbg_delta;
+  DumpOut dump{};                           // verification dump (dump.dist null when off)
+  DevBuf dump_dist, dump_sigma, dump_delta;
+  int64_t dump_rows = 0;
   // streams and timing
   hipStream_t own = nullptr;
   hipStream_t side[KC_COUNT] = {nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -1,6 +1,9 @@
 // C consumer of the library's device-memory entry points: the result goes to
-// a hipMalloc'ed buffer on the caller's stream and must equal the host-result
-// entry point's output.  Exit status 0 and "device path ok" on success.
+// a hipMalloc'ed buffer on the caller's stream.  Both it and the host-result
+// entry point's output must equal the oracle's values for the same graph
+// (tests/golden/device_path_bc.txt, written by the script beside it from the
+// oracle alone) within 1e-9 relative, and exactly 0 where those are 0.
+// Run from the repository root.  Exit status 0 and "device path ok" on success.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -8,6 +11,47 @@
 #include <vector>
 
 #include "shatterbc.h"
+
+// Reads the golden file: a comment line, the vertex count, one value per line.
+static bool read_golden(const char* path, std::vector<double>* out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  if (!std::fgets(line, sizeof line, f)) {
+    std::fclose(f);
+    return false;
+  }
+  int n = 0;
+  if (std::fscanf(f, "%d", &n) != 1 || n <= 0) {
+    std::fclose(f);
+    return false;
+  }
+  out->resize(n);
+  for (int i = 0; i < n; ++i)
+    if (std::fscanf(f, "%lf", &(*out)[i]) != 1) {
+      std::fclose(f);
+      return false;
+    }
+  std::fclose(f);
+  return true;
+}
+
+// Largest relative difference from the golden values; -1 on a nonzero value
+// where the golden value is 0.
+static double worst_rel(const std::vector<double>& got, const std::vector<double>& want, const char* what) {
+  double worst = 0;
+  for (size_t v = 0; v < want.size(); ++v) {
+    if (want[v] == 0) {
+      if (got[v] != 0) {
+        std::printf("%s: vertex %zu is %g, oracle 0\n", what, v, got[v]);
+        return -1;
+      }
+      continue;
+    }
+    worst = std::fmax(worst, std::fabs(got[v] - want[v]) / std::fabs(want[v]));
+  }
+  return worst;
+}
 
 int main() {
   // a 60-cycle with chords every 7 vertices and three pendants
@@ -47,26 +91,21 @@ int main() {
     return 1;
   }
   if (hipMemcpy(dev_copy.data(), d, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess) return 1;
-  double worst = 0;
-  for (int v = 0; v < n; ++v) {
-    const double ref = host[v];
-    if (ref == 0) {
-      if (dev_copy[v] != 0) {
-        std::printf("vertex %d: %g, want 0\n", v, dev_copy[v]);
-        return 1;
-      }
-      continue;
-    }
-    worst = std::fmax(worst, std::fabs(dev_copy[v] - ref) / ref);
+  std::vector<double> want;
+  if (!read_golden("tests/golden/device_path_bc.txt", &want) || (int)want.size() != n) {
+    std::printf("cannot read tests/golden/device_path_bc.txt (run from the repository root)\n");
+    return 1;
   }
+  const double wh = worst_rel(host, want, "host output");
+  const double wd = worst_rel(dev_copy, want, "device output");
   (void)hipFree(d);
   (void)hipStreamDestroy(s);
   sbc_graph_destroy(g);
   sbc_context_destroy(ctx);
-  if (worst > 1e-12) {
-    std::printf("max relative difference %g\n", worst);
+  if (wh < 0 || wd < 0 || wh > 1e-9 || wd > 1e-9) {
+    std::printf("max relative difference from the oracle: host %g, device %g\n", wh, wd);
     return 1;
   }
-  std::printf("device path ok (max rel diff %g)\n", worst);
+  std::printf("device path ok (max rel diff from the oracle: host %g, device %g)\n", wh, wd);
   return 0;
 }

@@ -127,3 +127,22 @@ def assert_bc_close(got, want, rtol=1e-9, what=""):
     assert bad.size == 0, (f"{what}: {bad.size} vertices off; worst rel "
                            f"{np.max(err[~zero] / np.abs(want[~zero])) if (~zero).any() else 0:.3e} at "
                            f"{bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}")
+
+
+def piece_csr(ex, p):
+    """Local CSR (row_ptr, col), reach and ident of exported piece p."""
+    vb, ve = int(ex["vtx_off"][p]), int(ex["vtx_off"][p + 1])
+    rp = (ex["row"][vb:ve + 1] - ex["row"][vb]).astype(np.int32)
+    cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int32)
+    return rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve]
+
+
+def map_back(ex, bcp):
+    """Eq. (5): bc[v] = bcx[v] + sum over the piece vertices x standing for v
+    of (bc'[x] + corr[x]), for an exported preprocessing and per-piece bc'."""
+    n = len(ex["map_off"]) - 1
+    out = np.array(ex["bcx"][:n], dtype=np.float64, copy=True)
+    owner = np.repeat(np.arange(n), np.diff(ex["map_off"]))
+    idx = ex["map_idx"][:len(owner)]
+    np.add.at(out, owner, np.asarray(bcp)[idx] + ex["corr"][idx])
+    return out

@@ -1,15 +1,19 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
-configuration bench.py times (default context), on outputs the oracle can
-compute: sampled sources (Algorithm 1 restricted to them), single pieces of
-the full shattered graph (Algorithm 2 with ident weights on the piece), and
-properties that hold at any size (compressed equals plain)."""
+configuration bench.py times (default context, "odai" preprocessing, one
+plan executed once): the whole compressed result element by element against
+the oracle -- Algorithm 1 on the original graph where it finishes in minutes
+(R-MAT scale 17, grid512), and Algorithm 2 with ident weights on every
+exported piece, mapped back with Eq. (5), for the 20,000-piece block tree --
+plus sampled sources and properties that hold at any size."""
+import time
+
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
 import paper_1209_6007_amd as sbc
-from tests.helpers import assert_bc_close
+from tests.helpers import assert_bc_close, map_back, piece_csr
 
 pytestmark = pytest.mark.gpu
 RTOL = 1e-9
@@ -21,6 +25,50 @@ def ctx():
     c = sbc.Context(0)
     yield c
     c.close()
+
+
+def oracle_in_chunks(g, label, chunks=8):
+    """Algorithm 1 over all sources, in source chunks with a progress line each."""
+    out = np.zeros(g.n)
+    bounds = np.linspace(0, g.n, chunks + 1).astype(np.int64)
+    for c in range(chunks):
+        t0 = time.perf_counter()
+        src = np.arange(bounds[c], bounds[c + 1], dtype=np.int32)
+        out += oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src)
+        print(f"{label}: oracle chunk {c + 1}/{chunks} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    return out
+
+
+def bench_run(ctx, g, ops="odai"):
+    """The compressed result of the launch configuration bench.py times."""
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess(ops)
+    plan = sbc.sbc_plan_create(ctx.h, G.h, sbc.SBC_COMPRESSED)
+    try:
+        sbc.sbc_plan_execute(plan)
+        st = sbc.sbc_plan_sync(plan)
+        bc = sbc.sbc_plan_result(plan, g.n)
+    finally:
+        sbc.sbc_plan_destroy(plan)
+    return G, bc, st
+
+
+def test_rmat17_compressed_vs_oracle(ctx):
+    """R-MAT scale 17 (the headline workload): the whole compressed result
+    against Algorithm 1 on the original graph, every vertex."""
+    g = gg.rmat_decorated()
+    _, got, st = bench_run(ctx, g)
+    print(f"rmat17 n={g.n} m={g.m} compressed run {st['ms_device']:.1f} ms", flush=True)
+    assert_bc_close(got, oracle_in_chunks(g, "rmat17"), RTOL, "rmat17 compressed vs oracle")
+
+
+def test_grid512_compressed_vs_oracle(ctx):
+    """512x512 grid with 12% of edges deleted (about 800 levels): the whole
+    compressed result against Algorithm 1 on the original graph."""
+    g = gg.grid_deleted()
+    _, got, st = bench_run(ctx, g)
+    print(f"grid512 n={g.n} m={g.m} compressed run {st['ms_device']:.1f} ms", flush=True)
+    assert_bc_close(got, oracle_in_chunks(g, "grid512"), RTOL, "grid512 compressed vs oracle")
 
 
 def sampled_sources(ctx, g, k, seed):
@@ -66,31 +114,24 @@ def test_grid_compressed_equals_plain(ctx):
     assert_bc_close(plain, oracle.bc(g), RTOL, "grid128 plain vs oracle")
 
 
-def test_block_tree_full_run_and_sampled_pieces(ctx):
-    """The 20,000-piece block tree in one persistent launch per kernel class;
-    a sample of its pieces (as shattered, with reach) checked one by one
-    against Algorithm 2 with ident weights on the oracle."""
+def test_block_tree_one_launch_vs_oracle_pieces(ctx):
+    """The 20,000-piece block tree (about 13.1M vertices) in one persistent
+    launch per kernel class: every vertex of the result against the oracle's
+    Algorithm 2 with ident weights on every exported piece, mapped back with
+    Eq. (5).  (Algorithm 1 on the whole graph would take days; the host
+    preprocessing itself is checked against Algorithm 1 on smaller block
+    trees in test_block_tree_200_pieces_vs_oracle and the CPU tests.)"""
     g = gg.block_tree()
-    G = sbc.Graph(g.n, g.row_ptr, g.col)
-    st = G.preprocess("odai")
-    print(f"block tree n={g.n} m={g.m} pieces={st['pieces']} piece_vertices={st['piece_vertices']}", flush=True)
-    bc = sbc.sbc_betweenness(ctx.h, G.h, sbc.SBC_COMPRESSED)
-    assert np.all(np.isfinite(bc)) and np.all(bc >= 0)
-    deg = np.diff(g.row_ptr)
-    assert np.all(bc[deg == 1] == 0)
+    G, got, st = bench_run(ctx, g)
+    print(f"block tree n={g.n} m={g.m} items={st['items_class']} run {st['ms_device']:.1f} ms", flush=True)
     ex = sbc.sbc_graph_export(G.h)
-    vo = ex["vtx_off"]
-    sizes = np.diff(vo)
-    r = gg.rng(13)
-    picks = list(r.choice(len(sizes), size=6, replace=False)) + [int(np.argmax(sizes))]
-    for p in picks:
-        vb, ve = int(vo[p]), int(vo[p + 1])
-        rp = (ex["row"][vb:ve + 1] - ex["row"][vb]).astype(np.int32)
-        cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int32)
-        reach, ident = ex["reach"][vb:ve], ex["ident"][vb:ve]
-        got = sbc.sbc_piece_bc(ctx.h, ve - vb, rp, cl, reach, ident)
-        want = oracle.bc_weighted(ve - vb, rp, cl, reach, ident)
-        assert_bc_close(got, want, RTOL, f"block tree piece {p} (n={ve - vb})")
+    t0 = time.perf_counter()
+    bcp = oracle.bc_pieces(ex["vtx_off"], ex["row"], ex["col"], ex["reach"], ex["ident"])
+    print(f"block tree: oracle over {len(ex['vtx_off']) - 1} pieces ({time.perf_counter() - t0:.1f} s)", flush=True)
+    want = map_back(ex, bcp)
+    assert_bc_close(got, want, RTOL, "block tree one launch vs oracle pieces")
+    deg = np.diff(g.row_ptr)
+    assert np.all(got[deg == 1] == 0)
 
 
 def test_block_tree_200_pieces_vs_oracle(ctx):
@@ -131,9 +172,7 @@ def test_small_piece_block_tree_full_run(ctx):
     picks = list(r.choice(len(sizes), size=8, replace=False)) + [int(np.argmax(sizes))]
     for p in picks:
         vb, ve = int(vo[p]), int(vo[p + 1])
-        rp = (ex["row"][vb:ve + 1] - ex["row"][vb]).astype(np.int32)
-        cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int32)
-        reach, ident = ex["reach"][vb:ve], ex["ident"][vb:ve]
+        rp, cl, reach, ident = piece_csr(ex, p)
         got = sbc.sbc_piece_bc(ctx.h, ve - vb, rp, cl, reach, ident, kernel=5)
         want = oracle.bc_weighted(ve - vb, rp, cl, reach, ident)
         assert_bc_close(got, want, RTOL, f"small-piece block tree piece {p} (n={ve - vb})")

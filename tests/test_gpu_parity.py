@@ -67,6 +67,43 @@ def test_single_source_state(ctx, seed):
             np.testing.assert_allclose(dl[m], odl[m], rtol=RTOL, atol=0)
 
 
+STATE_CASES = {
+    # (graph, sources): ragged source counts, more than one 64-source item
+    "decorated": (lambda: gg.decorated_random(70, 0.06, 14, 6, 3, 2101), 70),
+    "disconnected": (lambda: gg.csr_from_edges(40, np.arange(0, 38), np.arange(1, 39)), 5),
+    "grid15": (lambda: gg.grid_deleted(side=15, seed=41), 130),
+    "rmat10": (lambda: gg.rmat_decorated(scale=10, seed=43), 65),
+    "K3,60": (lambda: gg.complete_bipartite(3, 60), 63),
+}
+
+
+@pytest.mark.parametrize("kernel", [3, 4, 5])
+@pytest.mark.parametrize("case", list(STATE_CASES))
+def test_sources_state_bit_exact(ctx, kernel, case):
+    """Per-source levels and path counts written by each traversal kernel's
+    dump variant equal the oracle's bit for bit (path counts here stay below
+    2^53, so they are exact integers on both sides); dependencies within
+    1e-9 relative, and exactly 0 at the source and where unreachable.
+    Unweighted and with random reach / ident."""
+    make, k = STATE_CASES[case]
+    g = make()
+    if kernel == 5 and g.n > 256:
+        pytest.skip("beyond the small-piece kernel's LDS (its refusal is tested in test_piece_kernels_weighted)")
+    src = gg.rng(g.n + kernel).choice(g.n, size=min(k, g.n), replace=False).astype(np.int32)
+    reach, ident = gg.random_attributes(g.n, 77 + g.n, rmax=4, kmax=3)
+    print(f"state case={case} n={g.n} m={g.m} kernel={kernel} sources={len(src)}", flush=True)
+    for rr, kk in ((None, None), (reach, ident)):
+        d, sg, dl = sbc.sbc_sources_state(ctx.h, g.n, g.row_ptr, g.col, src, kernel, rr, kk)
+        for row, s in enumerate(src):
+            od, osg, odl = oracle.single_source(g.n, g.row_ptr, g.col, int(s), rr, kk)
+            assert osg.max() < 2.0 ** 53
+            np.testing.assert_array_equal(d[row], od, err_msg=f"levels, source {s}")
+            np.testing.assert_array_equal(sg[row], osg, err_msg=f"path counts, source {s}")
+            live = od > 0
+            np.testing.assert_allclose(dl[row][live], odl[live], rtol=RTOL, atol=0, err_msg=f"delta, source {s}")
+            assert np.all(dl[row][~live] == 0)
+
+
 PIECE_SIZES = [3, 5, 63, 64, 65, 130, 257, 700, 2100]
 
 
@@ -177,7 +214,8 @@ def test_plan_reexecute_and_graph_replay(ctx, name):
 
 def test_device_memory_entry_point():
     """sbc_betweenness_device from a C++ program: output in a hipMalloc'ed
-    buffer on the caller's stream, equal to the host-output entry point."""
+    buffer on the caller's stream; it and the host-output entry point both
+    equal the oracle's values stored in tests/golden/device_path_bc.txt."""
     import os
     import subprocess
 

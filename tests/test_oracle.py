@@ -226,3 +226,47 @@ def test_source_subset_is_additive():
     a = oracle.bc_plain(g.n, g.row_ptr, g.col, sources=np.arange(0, 30))
     b = oracle.bc_plain(g.n, g.row_ptr, g.col, sources=np.arange(30, 60))
     np.testing.assert_allclose(a + b, full, rtol=1e-12, atol=1e-12)
+
+
+def test_bc_pieces_is_bc_weighted_per_piece():
+    """oracle.bc_pieces on a packed set of ragged attributed pieces (one of a
+    single vertex, one disconnected) equals oracle.bc_weighted run on each
+    piece alone, for one thread and for more threads than pieces."""
+    r = gg.rng(71)
+    pieces = [gg.erdos_renyi(n, min(0.9, 5.0 / n), 300 + n) for n in (1, 2, 9, 40, 3, 77, 12)]
+    pieces.append(gg.csr_from_edges(6, np.array([0, 1, 3]), np.array([1, 2, 4])))
+    vtx_off, row, col, reach, ident, want = [0], [0], [], [], [], []
+    for g in pieces:
+        rc, kc = gg.random_attributes(g.n, int(r.integers(1 << 30)), rmax=4, kmax=3)
+        want.append(oracle.bc_weighted(g.n, g.row_ptr, g.col, rc, kc, threads=1))
+        base = row[-1]
+        row.extend(int(base + x) for x in g.row_ptr[1:])
+        col.extend(int(c) for c in g.col)
+        reach.extend(rc)
+        ident.extend(kc)
+        vtx_off.append(vtx_off[-1] + g.n)
+    want = np.concatenate(want)
+    for threads in (1, 3, 40):
+        got = oracle.bc_pieces(np.array(vtx_off), np.array(row), np.array(col), np.array(reach), np.array(ident),
+                               threads=threads)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+
+
+def test_device_path_golden_file_is_the_oracle():
+    """tests/golden/device_path_bc.txt (read by the C consumer test) holds what
+    its script computes with the oracle, and the script's graph has the shape
+    the C program describes (63 vertices, 60 + 9 + 3 edges)."""
+    import importlib.util
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(here, "make_device_path_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    n, rp, col = mk.graph()
+    assert n == 63 and rp[-1] == 2 * (60 + 9 + 3)
+    with open(os.path.join(here, "device_path_bc.txt")) as f:
+        lines = [l for l in f.read().split("\n") if l and not l.startswith("#")]
+    assert int(lines[0]) == n
+    stored = np.array([float(x) for x in lines[1:]])
+    np.testing.assert_array_equal(stored, oracle.bc_plain(n, rp, col, threads=1))
+    assert stored[60] == stored[61] == stored[62] == 0

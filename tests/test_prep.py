@@ -15,7 +15,7 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_1209_6007_amd as sbc
-from tests.helpers import assert_bc_close
+from tests.helpers import assert_bc_close, map_back
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OPS = ["", "d", "a", "i", "da", "di", "ai", "dai", "o", "odai"]
@@ -190,6 +190,22 @@ def test_workload_shapes_small(name):
     for ops in ("d", "da", "dai", "ai", "odai"):
         got, st = compressed_via_oracle(g, ops)
         assert_bc_close(got, want, 1e-9, f"{name} ops={ops}")
+
+
+@pytest.mark.parametrize("name", ["blocks", "rmat"])
+def test_bc_pieces_mapped_back_is_the_oracle(name):
+    """The check the full-size block tree uses on the GPU machine: the oracle's
+    bc' of every exported piece (oracle.bc_pieces), mapped back with Eq. (5),
+    equals Algorithm 1 on the original graph (Theorem 1)."""
+    g = gg.block_tree(n_pieces=80, max_size=300, seed=15) if name == "blocks" else gg.rmat_decorated(scale=9, seed=8)
+    h = sbc.sbc_graph_create(g.n, g.row_ptr, g.col)
+    try:
+        sbc.sbc_graph_preprocess(h, "odai")
+        ex = sbc.sbc_graph_export(h)
+    finally:
+        sbc.sbc_graph_destroy(h)
+    bcp = oracle.bc_pieces(ex["vtx_off"], ex["row"], ex["col"], ex["reach"], ex["ident"], threads=4)
+    assert_bc_close(map_back(ex, bcp), oracle.bc(g), 1e-9, name)
 
 
 def test_block_tree_shatters_into_its_blocks():
