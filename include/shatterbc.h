@@ -297,6 +297,37 @@ sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr,
                              const int32_t* reach, const int32_t* ident, int32_t s, int32_t* dist,
                              double* sigma, double* delta);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the result
+ * of sbc_piece_bc (bc' of one attributed piece, all sources, ordered pairs)
+ * from inputs already in device memory, with no device allocation.
+ *   n              piece vertices, 1..SBC_NOALLOC_MAX_VERTICES
+ *   arcs           entries of col_dev (2 x edges)
+ *   row_ptr_dev    device, n+1 int32 arc offsets (row_ptr_dev[0] = 0)
+ *   col_dev        device, arcs int32 local neighbour ids (symmetric, loop-free)
+ *   reach_dev, ident_dev  device, n int32 each (>= 1), or NULL for all ones
+ *   bc_dev         device, n doubles: receives bc'
+ *   flags_dev      device, one int32 (or NULL): the run's device check flags,
+ *                  0 when every check passed and every work item finished
+ *   stream         hipStream_t (NULL = the null stream)
+ * Asynchronous: only kernel launches are enqueued on `stream`; the output and
+ * flags are valid once the stream reaches this point.  The 64-source batch
+ * kernel's traversal state, work items and control words live in one static
+ * device array of SBC_NOALLOC_SCRATCH_MB MiB per GPU, which the library holds
+ * from the first call on a GPU until the process ends; every call on that GPU
+ * shares it, so calls that overlap on one GPU (concurrent streams or threads)
+ * race and give wrong results.  The CSR is read as given (row offsets within
+ * [0, arcs], neighbour ids within [0, n) are checked on the device and
+ * reported in flags_dev).
+ * Errors: SBC_E_INVALID_ARG (NULL argument, n < 1, arcs < 0), SBC_E_TOO_LARGE
+ * (n > SBC_NOALLOC_MAX_VERTICES, or the piece's state does not fit the
+ * array), SBC_E_DEVICE (a launch failed). */
+#define SBC_NOALLOC_MAX_VERTICES 65536
+#define SBC_NOALLOC_SCRATCH_MB 256
+sbc_status sbc_piece_bc_noalloc(sbc_context ctx, int32_t n, int32_t arcs, const int32_t* row_ptr_dev,
+                                const int32_t* col_dev, const int32_t* reach_dev, const int32_t* ident_dev,
+                                double* bc_dev, int32_t* flags_dev, void* stream);
+
 /* Streaming copy of `bytes` (rounded down to 16) between two device buffers
  * the library allocates, `reps` times after one warm-up: *gbps = (read +
  * write bytes) / time.  It measures the bandwidth a plain streaming kernel

@@ -125,6 +125,8 @@ _SIGS = {
                           ctypes.c_int32),
     "sbc_sources_state": ([_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int,
                            _i32p, _f64p, _f64p], ctypes.c_int32),
+    "sbc_piece_bc_noalloc": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+                             ctypes.c_int32),
     "sbc_copy_bandwidth": ([_vp, ctypes.c_size_t, ctypes.c_int, _f64p], ctypes.c_int32),
     "sbc_server_create": ([_vp, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int32),
     "sbc_server_destroy": ([_vp], ctypes.c_int32),
@@ -367,6 +369,15 @@ def sbc_sources_state(ctx, n, row_ptr, col, sources, kernel: int = 0, reach=None
     _check(lib().sbc_sources_state(ctx, int(n), rpp, clp, rep, idp, k, svp, int(kernel),
                                    dist.ctypes.data_as(_i32p), sig.ctypes.data_as(_f64p), dl.ctypes.data_as(_f64p)))
     return dist, sig, dl
+
+
+def sbc_piece_bc_noalloc(ctx, n: int, arcs: int, row_ptr_dev: int, col_dev: int, reach_dev, ident_dev,
+                         bc_dev: int, flags_dev=None, stream=None):
+    """Device-pointer arguments (integers); see include/shatterbc.h."""
+    _check(lib().sbc_piece_bc_noalloc(ctx, int(n), int(arcs), _vp(row_ptr_dev), _vp(col_dev),
+                                      _vp(reach_dev) if reach_dev else None, _vp(ident_dev) if ident_dev else None,
+                                      _vp(bc_dev), _vp(flags_dev) if flags_dev else None,
+                                      _vp(stream) if stream else None))
 
 
 def sbc_copy_bandwidth(ctx, nbytes: int = 1 << 30, reps: int = 10) -> float:

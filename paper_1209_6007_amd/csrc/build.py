@@ -20,7 +20,7 @@ OUT = os.path.join(PKG, "libshatterbc.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 
 HOST_SOURCES = ["prep.cpp"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "server.hip"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "server.hip", "noalloc.hip"]
 
 ARCH = "gfx950"
 HIP_FLAGS = [
@@ -75,7 +75,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     return OUT
 
 
-C_TESTS = [("tests/c_api/device_path.cpp", "tests/c_api/device_path")]
+C_TESTS = [("tests/c_api/device_path.cpp", "tests/c_api/device_path"), ("tests/c_api/noalloc.cpp", "tests/c_api/noalloc")]
 
 
 def build_c_tests(hipcc: str) -> None:

@@ -12,13 +12,13 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1209_6007_amd", "csrc")
 OUT_DIR = os.path.join(ROOT, "_build", "emu")
 OUT = os.path.join(OUT_DIR, "libshatterbc_emu.so")
-SOURCES = ["prep.cpp", "kernels.hip", "runtime.hip", "api.hip", "server.hip"]
+SOURCES = ["prep.cpp", "kernels.hip", "runtime.hip", "api.hip", "server.hip", "noalloc.hip"]
 
 
 def build(asan: bool = True) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     flags = ["-std=c++17", "-O1", "-g", "-fPIC", "-pthread", "-fno-omit-frame-pointer", "-Wno-unused-function",
-             "-DSBC_ENABLE_PER_SOURCE_KERNELS=1", "-DSBC_EMU_FEW_VARIANTS=1", f"-I{HERE}",
+             "-DSBC_EMU_FEW_VARIANTS=1", f"-I{HERE}",
              f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
     if asan:
         flags.append("-fsanitize=address")

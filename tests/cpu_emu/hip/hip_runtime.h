@@ -291,6 +291,7 @@ enum {
   hipSuccess = 0,
   hipErrorInvalidValue = 1,
   hipErrorOutOfMemory = 2,
+  hipErrorInvalidSymbol = 13,
   hipErrorNotSupported = 801,
 };
 typedef struct emu_stream* hipStream_t;
@@ -420,6 +421,14 @@ inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* nb, const void*, int, size_t) {
   *nb = 2;
+  return hipSuccess;
+}
+
+// A file-scope device variable is an ordinary host object here; its "device
+// address" is its host address.
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  *p = const_cast<void*>(sym);
   return hipSuccess;
 }
 

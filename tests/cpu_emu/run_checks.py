@@ -272,6 +272,33 @@ def main(which):
                 print(f"   routed {name} ok", flush=True)
             wctx.close()
         check("small-piece kernel", wave)
+    if "noalloc" in which:
+        def noalloc():
+            # the entry point without device allocation: "device" buffers are
+            # host memory in the emulation; two calls in a row, the second
+            # smaller, each equal to sbc_piece_bc; then a refused size
+            for n, seed in ((300, 21), (70, 22)):
+                r = gg.rng(seed)
+                g = gg.erdos_renyi(n, 6.0 / n, seed)
+                reach, ident = gg.random_attributes(n, int(r.integers(1 << 30)), rmax=4, kmax=3)
+                want = sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, reach, ident, kernel=3)
+                rp, cl = np.ascontiguousarray(g.row_ptr, np.int32), np.ascontiguousarray(g.col, np.int32)
+                rc, kc = np.ascontiguousarray(reach, np.int32), np.ascontiguousarray(ident, np.int32)
+                out = np.full(n, 7.0)
+                flags = np.full(1, -1, np.int32)
+                sbc.sbc_piece_bc_noalloc(ctx.h, n, len(cl), rp.ctypes.data, cl.ctypes.data, rc.ctypes.data,
+                                         kc.ctypes.data, out.ctypes.data, flags.ctypes.data)
+                assert flags[0] == 0, flags
+                assert_bc_close(out, want, 1e-9, f"noalloc n={n}")
+                print(f"   n={n} ok", flush=True)
+            try:
+                sbc.sbc_piece_bc_noalloc(ctx.h, 65537, 0, rp.ctypes.data, cl.ctypes.data, None, None,
+                                         out.ctypes.data)
+            except sbc.SbcError as e:
+                assert e.status == -6, e
+            else:
+                raise AssertionError("an oversized piece was accepted")
+        check("no-allocation entry point", noalloc)
     if "server" in which:
         def server():
             gs = [gg.rmat_decorated(scale=7, seed=s) for s in range(3)] + [gg.grid_deleted(side=10, seed=4)]
@@ -288,4 +315,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "wave", "server"])
+    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "wave", "noalloc", "server"])
