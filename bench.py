@@ -28,9 +28,9 @@ import graphgen as gg  # noqa: E402
 
 METRIC = "exact-BC GTEPS (sources×edges/s) + HBM roofline %, compressed-batched vs plain"
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = ["small_lds", "unused1", "batch64", "unused3", "team64"]
-KERNEL_SYMBOLS = {0: "wave_kernel<WAVES,*,*>", 1: "", 2: "ms_kernel<WAVES,EU,*,*>", 3: "",
-                  4: "ms_team_kernel<WAVES,EU,*,*>"}
+CLASS_NAMES = ["small_lds", "unused1", "batch64", "deep64", "team64"]
+KERNEL_SYMBOLS = {0: "wave_kernel<WAVES,*,*>", 1: "", 2: "ms_kernel<WAVES,EU,*,*>",
+                  3: "ms_kernel<WAVES,EU,*,*> (deep pieces)", 4: "ms_team_kernel<WAVES,EU,*,*>"}
 
 WORKLOADS = {
     "rmat17": ("R-MAT scale 17 (131,072 labels), edge factor 8, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "

@@ -91,8 +91,9 @@ typedef struct {
   int64_t global_sources;    /* always 0 (no other traversal kernel) */
   int32_t overflow;          /* device flags of the run (nonzero: a check failed or a path count overflowed) */
   /* Per traversal kernel class: 0 small pieces, one source per wavefront (LDS),
-   * 2 64-source batches (one workgroup per batch), 4 64-source batches run by
-   * teams of workgroups (one team per XCD); 1 and 3 are not used and stay 0.
+   * 2 64-source batches (one workgroup per batch), 3 the same for deep pieces
+   * (a launch of its own), 4 64-source batches run by teams of workgroups (one
+   * team per XCD); 1 is not used and stays 0.
    * Device time of the class's persistent launch, its streaming-model bytes,
    * and its sources x edges. */
   double ms_class[5];
@@ -129,6 +130,15 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "cluster_sources"    batch source order: 0 piece order, 1 breadth-first balls,
  *                        2 (default) vertices grouped by a common neighbour of
  *                        degree >= 32 first, then balls
+ *   "batch_pairs"        the batch kernel pulls entries with at most 32 arcs and
+ *                        at most this many of the batch's sources as (entry,
+ *                        source) pairs, one per lane (default 16, 0..64; 0: one
+ *                        wave per entry always)
+ *   "deep_min_levels"    pieces whose breadth-first depth from their highest-degree
+ *                        vertex exceeds this (default 64; 0: never) run on the
+ *                        batch kernel in a launch of their own (class 3)
+ *   "deep_wg_waves"      wavefronts per workgroup of that launch (4, 8, 16; default 16)
+ *   "deep_waves_per_eu"  its occupancy target: 0 (default), 6 or 8
  *   "mem_budget_mb"      traversal-state budget of a plan (0: 60% of free memory)
  *   "profile_phases"     1: plans keep per-phase timers of the batch and team kernels
  *   "order_plain"        1: plain plans run on the graph renumbered breadth-first
@@ -149,8 +159,10 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "server_order"       serving: 1 (default) least estimated work first, 0 oldest first
  *   "server_max_wait_ms" serving: a job waiting longer is taken first (default 30000)
  *   "sample_items"       tuning only (0: off): plans run an evenly spaced sample of
- *                        at most this many work items per kernel class, so the
- *                        result covers only those items' sources
+ *                        the work items -- at most this many of the kernel class
+ *                        with the most items, and the same fraction of every
+ *                        other class (at least one) -- so the result covers
+ *                        only those items' sources
  *   "team_spin_ms"       bound of one team barrier wait; a longer wait aborts
  *                        the launch with SBC_E_DEVICE instead of hanging
  *                        (0: no waiting at all, which aborts any team of more

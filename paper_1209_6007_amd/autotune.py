@@ -14,13 +14,16 @@ keeps the fastest:
 * then, with that choice fixed, whether small pieces run on the small-piece
   kernel (one source per wavefront, the piece in LDS) and its workgroup
   shape (``wave_max_vertices``, ``wave_wg_waves``), when the workload has
-  pieces small enough for it.
+  pieces small enough for it;
+* and, when its largest piece is deep (more levels than ``deep_min_levels``),
+  the workgroup shape of the deep pieces' own launch (``deep_wg_waves``,
+  ``deep_waves_per_eu``).
 
-Runs are sampled (``sample_items``: an evenly spaced subset of each kernel
-class's work items) yet keep the device fully loaded: eight rounds of the
-resident workgroups for one workgroup per batch, four items per team for the
-team kernel.  The sampled time is scaled by the number of items to estimate a
-full run.  Results are cached in a JSON file
+Runs are sampled (``sample_items``: an evenly spaced subset of the work
+items, the same fraction of every kernel class) yet keep the device fully
+loaded: eight rounds of the resident workgroups for one workgroup per batch,
+four items per team for the team kernel.  The sampled time is scaled by the
+number of items to estimate a full run.  Results are cached in a JSON file
 per device (``$SBC_AUTOTUNE_CACHE`` or ``~/.cache/shatterbc/autotune.json``),
 keyed by device name and bucket.
 
@@ -47,7 +50,7 @@ TEAM_ROUNDS = 4           # items per team in a team-kernel run
 # Candidate configurations of the large pieces' kernels.  Every one sets
 # every tuned key, so that the choice does not depend on the context it is
 # applied to; the small-piece keys are at their defaults here.
-_WAVE_DEFAULT = {"wave_max_vertices": 256, "wave_wg_waves": 4}
+_WAVE_DEFAULT = {"wave_max_vertices": 256, "wave_wg_waves": 4, "deep_wg_waves": 16, "deep_waves_per_eu": 0}
 CANDIDATES = [dict(c, **_WAVE_DEFAULT) for c in (
     {"team_min_vertices": 0, "batch_wg_waves": 8, "batch_waves_per_eu": 8, "team_count": 64, "team_max_levels": 0},
     {"team_min_vertices": 0, "batch_wg_waves": 16, "batch_waves_per_eu": 8, "team_count": 64, "team_max_levels": 0},
@@ -64,6 +67,15 @@ SMALL_CANDIDATES = [
     {"wave_max_vertices": 256, "wave_wg_waves": 4},
     {"wave_max_vertices": 256, "wave_wg_waves": 8},
     {"wave_max_vertices": 128, "wave_wg_waves": 8},
+]
+# Third stage, for workloads whose largest piece is deeper than the deep
+# class's threshold: the deep launch's workgroup shape.
+DEEP_MIN_LEVELS = 64  # the library's default deep_min_levels
+DEEP_CANDIDATES = [
+    {"deep_wg_waves": 16, "deep_waves_per_eu": 0},
+    {"deep_wg_waves": 16, "deep_waves_per_eu": 8},
+    {"deep_wg_waves": 8, "deep_waves_per_eu": 0},
+    {"deep_wg_waves": 8, "deep_waves_per_eu": 8},
 ]
 
 
@@ -131,7 +143,8 @@ def total_items(graph: Graph, mode: int, n: int) -> int:
 
 
 def sample_for(params: dict, cus: int = 256) -> int:
-    """Items per kernel class of a sampled run: several rounds of the resident
+    """Items of the largest kernel class in a sampled run (the other classes
+    keep the same fraction of theirs): several rounds of the resident
     workgroups (a run of one or two rounds measures its slowest item, not the
     throughput), or TEAM_ROUNDS items per team."""
     if params.get("team_min_vertices", 0) > 0:
@@ -209,9 +222,20 @@ def tune(graph: Graph, mode: int = SBC_COMPRESSED, device: int = 0, row_ptr=None
             if log:
                 log(f"autotune {key}: small pieces {opt} -> {m:.1f} ms estimated ({time.perf_counter() - t0:.1f} s)")
         ms, best = min(small, key=lambda r: r[0])
+    deep = []
+    if depth > DEEP_MIN_LEVELS:
+        for opt in DEEP_CANDIDATES:
+            cand = dict(best, **opt)
+            t0 = time.perf_counter()
+            m = _time_candidate(cand, graph, mode, device, full, cus)
+            deep.append((m, cand))
+            if log:
+                log(f"autotune {key}: deep pieces {opt} -> {m:.1f} ms estimated ({time.perf_counter() - t0:.1f} s)")
+        ms, best = min(deep, key=lambda r: r[0])
     cache[key] = {"params": best, "estimated_ms": ms, "piece_vertices": int(np_max), "depth": int(depth),
                   "items": full, "candidates": [{"params": c, "estimated_ms": m} for m, c in results],
-                  "small_candidates": [{"params": c, "estimated_ms": m} for m, c in small]}
+                  "small_candidates": [{"params": c, "estimated_ms": m} for m, c in small],
+                  "deep_candidates": [{"params": c, "estimated_ms": m} for m, c in deep]}
     save_cache(cache, path)
     return dict(best)
 

@@ -96,6 +96,10 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "wave_wg_waves") return &p.wave_wg_waves;
   if (k == "slots") return &p.slots;
   if (k == "cluster_sources") return &p.cluster_sources;
+  if (k == "batch_pairs") return &p.batch_pairs;
+  if (k == "deep_min_levels") return &p.deep_min_levels;
+  if (k == "deep_wg_waves") return &p.deep_wg_waves;
+  if (k == "deep_waves_per_eu") return &p.deep_waves_per_eu;
   if (k == "mem_budget_mb") return &p.mem_budget_mb;
   if (k == "profile_phases") return &p.profile_phases;
   if (k == "order_plain") return &p.order_plain;
@@ -121,9 +125,12 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   bool ok = value >= 0;
   if (k == "batch_wg_waves") ok = value == 4 || value == 8 || value == 16;
   if (k == "batch_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
+  if (k == "deep_wg_waves") ok = value == 4 || value == 8 || value == 16;
+  if (k == "deep_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
   if (k == "team_waves_per_eu") ok = value == 0 || value == 8;
   if (k == "team_count") ok = value >= 1 && value <= 1024;
   if (k == "cluster_sources") ok = value >= 0 && value <= 2;
+  if (k == "batch_pairs") ok = value >= 0 && value <= 64;
   if (k == "team_spin_ms") ok = value <= 600000;
   if (k == "team_local_fences") ok = value == 0 || value == 1;
   if (k == "server_order") ok = value == 0 || value == 1;

@@ -80,6 +80,8 @@ struct MsState {
   uint64_t* prof;  // [slots][kProfCounters] phase timers, or null
   int64_t stride;
   int32_t part_cap;
+  int32_t pairs;   // batch kernel: entries with short rows and at most this many lanes are pulled as
+                   // (entry, lane) pairs (0: never)
 };
 
 // Per-slot phase timers of the batch kernel (wall-clock ticks, or counts).

@@ -366,13 +366,69 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 
 // One wave's LDS slots for pull_list: vertex, row bounds and lanes of up to
-// 64 entries.
+// 64 entries, and for the pair path each entry's first pair and its per-entry
+// sum.
 struct EntrySlots {
   int32_t* v;
   int32_t* e0;
   int32_t* e1;
   uint64_t* need;
+  int32_t* poff;
+  double* pacc;
 };
+
+// Pair path of pull_list: an entry whose row has at most kPairMaxDeg arcs and
+// whose lanes number at most `pairs` is pulled as (entry, lane) pairs,
+// one pair per lane, instead of by a whole wave of which only the entry's few
+// lanes would load anything.  On deep, sparse pieces the sources of a batch
+// reach a vertex at many different levels, so most entries carry a handful of
+// lanes: pairs keep every lane of the wave busy and issue the loads of many
+// entries at once.
+constexpr int kPairMaxDeg = 32;
+__device__ __forceinline__ bool pair_entry(int32_t e0, int32_t e1, uint64_t need, int max_lanes) {
+  return e1 - e0 <= kPairMaxDeg && __builtin_popcountll(need) <= max_lanes;
+}
+
+// One lane's sum over the arcs [e0, e1) of sg[u*64 + j] for the neighbours u
+// whose mask mk[u] holds lane j (scaled by ident[u] when `scale`), added in
+// arc order.  With U > 1 the arcs go U at a time (their neighbour ids, then
+// masks, then values loaded together); on MI355X U = 1 measured as fast on a
+// deep grid and faster on the block tree (fewer registers).
+template <int U>
+__device__ __forceinline__ double pair_sum(const int32_t* __restrict__ col, int32_t e0, int32_t e1, int32_t np,
+                                           uint64_t* __restrict__ mk, const double* __restrict__ sg,
+                                           const int32_t* __restrict__ idn, bool scale, int j, int32_t* flags) {
+  double acc = 0.0;
+  for (int32_t e = e0; e < e1; e += U) {
+    int32_t u[U];
+    uint64_t m[U];
+    double x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      u[k] = -1;
+      if (e + k < e1) {
+        u[k] = col_load(&col[e + k]);
+        if (u[k] < 0 || u[k] >= np) {
+          raise_flag(flags, kFlagBadArc);
+          u[k] = -1;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) m[k] = u[k] >= 0 ? group_load(&mk[u[k]]) : 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      x[k] = 0.0;
+      if ((m[k] >> j) & 1) {
+        x[k] = row_load(&sg[(size_t)u[k] * 64 + j]);
+        if (scale) x[k] *= (double)idn[u[k]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc += x[k];
+  }
+  return acc;
+}
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
@@ -389,14 +445,20 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 // costs three dependent rounds (queue slot, then row bounds, then lanes).
 // The entries are then pulled one after another; a bad vertex or row is
 // flagged and skipped.
-template <typename NeedOf, typename Defer, typename Early, typename Finish>
+//
+// With `pairs` > 0, entries that pass pair_entry are instead done first, as
+// pairs: the wave's pairs are numbered entry by entry (a scan of the entries'
+// lane counts), lane t takes pairs t, t+64, ..., finds its entry by binary
+// search and its lane j as the entry's r-th lane, and calls pair(k, i, v, e0,
+// e1, j).  Then lane k calls pair_done(k, i, v, need) for each such entry k.
+template <typename NeedOf, typename Defer, typename Early, typename Finish, typename Pair, typename PairDone>
 __device__ __forceinline__ void pull_list(const int first, const int step, const int n, const EntrySlots& sl,
                                           const int32_t* __restrict__ q, const int32_t* __restrict__ rowp,
                                           const int32_t np, const int32_t narcs, const int32_t* __restrict__ col,
                                           uint64_t* __restrict__ mk, const double* __restrict__ sg,
                                           const int32_t* __restrict__ idn, const bool scale, const int lane,
                                           int32_t* flags, NeedOf need_of, Defer defer, Early early,
-                                          Finish finish) {
+                                          Finish finish, const int pairs, Pair pair, PairDone pair_done) {
   if (lane < n) {
     const int i = first + lane * step;
     int32_t v = q[i], e0 = 0, e1 = 0;
@@ -419,7 +481,36 @@ __device__ __forceinline__ void pull_list(const int first, const int step, const
     sl.e1[lane] = e1;
     sl.need[lane] = need;
   }
-  wave_sync();
+  if (pairs > 0) {  // wave-uniform
+    int cnt = 0;
+    bool mine = false;
+    if (lane < n) {
+      const int32_t v = sl.v[lane];
+      const uint64_t need = sl.need[lane];
+      mine = v >= 0 && pair_entry(sl.e0[lane], sl.e1[lane], need, pairs);
+      if (mine) cnt = __builtin_popcountll(need);
+    }
+    const int incl = wave_incl_scan(cnt, lane);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    sl.poff[lane] = incl - cnt;
+    sl.pacc[lane] = 0.0;
+    wave_sync();
+    for (int t = lane; t < total; t += 64) {
+      int lo = 0, hi = n - 1;  // the last entry whose first pair is at most t
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sl.poff[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      uint64_t m = sl.need[lo];
+      for (int r = t - sl.poff[lo]; r > 0; --r) m &= m - 1;
+      pair(lo, first + lo * step, sl.v[lo], sl.e0[lo], sl.e1[lo], __builtin_ctzll(m));
+    }
+    wave_sync();
+    if (mine) pair_done(lane, first + lane * step, sl.v[lane], sl.need[lane]);
+  } else {
+    wave_sync();
+  }
   for (int k = 0; k < n; ++k) {
     const int32_t v = __builtin_amdgcn_readfirstlane(sl.v[k]);
     if (v < 0) continue;
@@ -427,6 +518,7 @@ __device__ __forceinline__ void pull_list(const int first, const int step, const
     const int32_t e0 = __builtin_amdgcn_readfirstlane(sl.e0[k]);
     const int32_t e1 = __builtin_amdgcn_readfirstlane(sl.e1[k]);
     const uint64_t need = uniform64(sl.need[k]);
+    if (pairs > 0 && pair_entry(e0, e1, need, pairs)) continue;  // done as pairs
     if (defer(i, v, e0, e1, need)) continue;
     const auto pre = early(i, v, need);
     double acc;
@@ -502,13 +594,18 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
   __shared__ int s_e0[BLOCK];
   __shared__ int s_e1[BLOCK];
   __shared__ uint64_t s_f[BLOCK];
+  __shared__ int s_poff[BLOCK];
+  __shared__ double s_pacc[BLOCK];
+  __shared__ double s_wsrc[64];  // ident[s]*reach[s] of lane s's source (pair path)
   __shared__ int s_nheavy, s_nslices;
   __shared__ int s_heavy[kHeavyMax];
   __shared__ int s_hoff[kHeavyMax];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // The pull phases gather entries in the phase-A scratch arrays (free then).
-  const EntrySlots slots{s_scan + wave * 64, s_e0 + wave * 64, s_e1 + wave * 64, s_f + wave * 64};
+  const EntrySlots slots{s_scan + wave * 64, s_e0 + wave * 64, s_e1 + wave * 64,
+                         s_f + wave * 64,    s_poff + wave * 64, s_pacc + wave * 64};
+  const int pairs = st.pairs;
   const size_t slot = blockIdx.x;
   double* sg = st.sg + slot * (size_t)st.stride * 64;
   int32_t* q = st.q + slot * (size_t)st.stride * 64;
@@ -580,6 +677,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         sg[(size_t)s * 64 + lane] = 1.0;
       }
     }
+    if (wave == 0) s_wsrc[lane] = wsrc;
     if (tid == 0) {
       lvl[0] = 0;
       lvl[1] = nsrc;
@@ -681,9 +779,15 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
         if (lane == 0) qm[i] = need;
       };
+      // Pair (w, lane j): sigma of w for source j from the neighbours on level L.
+      auto pair_f = [&](int, int, int32_t w, int32_t e0, int32_t e1, int j) {
+        const double acc = pair_sum<1>(col, e0, e1, np, fcur, sg, idn, scale, j, Q.flags);
+        sg[(size_t)w * 64 + j] = acc;
+      };
+      auto pair_done_f = [&](int, int i, int32_t, uint64_t need) { qm[i] = need; };
       for (int first = qe + wave; first < nt; first += WAVES * 64)
         pull_list(first, WAVES, min(64, (nt - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, fcur, sg,
-                  idn, scale, lane, Q.flags, need_f, defer_long, early_f, finish_f);
+                  idn, scale, lane, Q.flags, need_f, defer_long, early_f, finish_f, pairs, pair_f, pair_done_f);
       __syncthreads();
       mark(kProfPhaseB);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -806,9 +910,28 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, const BackEarly& pre) {
         back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
       };
+      // Pair (v, lane j): the dependency of v for source j from the
+      // coefficients of its neighbours on level l+1 (Eq. (3) in pull form),
+      // the coefficient that replaces sigma, and the weighted contribution
+      // to bc'[v], summed per entry in LDS.
+      auto pair_b = [&](int k, int, int32_t v, int32_t e0, int32_t e1, int j) {
+        const double sv = sg[(size_t)v * 64 + j];
+        const double rm1 = REACH ? (double)(rch[v] - 1) : 0.0;
+        const double id = IDENT ? (double)idn[v] : 1.0;
+        const double acc = pair_sum<1>(col, e0, e1, np, br, sg, idn, false, j, Q.flags);
+        const double dv = rm1 + sv * acc;
+        sg[(size_t)v * 64 + j] = id * (1.0 + dv) / sv;
+        atomicAdd(&s_pacc[wave * 64 + k], s_wsrc[j] * dv);  // LDS (the array, not the slot pointer)
+        if constexpr (DUMP) dump.delta[(size_t)(W.s0 + j) * dump.np + v] = dv;
+        if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
+      };
+      auto pair_done_b = [&](int k, int, int32_t v, uint64_t amask) {
+        atomicAdd(&bcp[v], s_pacc[wave * 64 + k]);
+        bw[v] = amask;
+      };
       for (int first = b + wave; first < e; first += WAVES * 64)
         pull_list(first, WAVES, min(64, (e - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, br, sg, idn,
-                  false, lane, Q.flags, need_b, defer_long_b, early_b, finish_b);
+                  false, lane, Q.flags, need_b, defer_long_b, early_b, finish_b, pairs, pair_b, pair_done_b);
       __syncthreads();
       mark(kProfBackward);
       const int nh = min(s_nheavy, kHeavyMax);

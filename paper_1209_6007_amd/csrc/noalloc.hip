@@ -132,6 +132,7 @@ extern "C" sbc_status sbc_piece_bc_noalloc(sbc_context ctx, int32_t n, int32_t a
   ms.lvl = reinterpret_cast<int32_t*>(take(align256((size_t)(stride + 3) * 4) * g));
   ms.part = reinterpret_cast<double*>(take(align256((size_t)part_cap * 64 * 8) * g));
   ms.prof = nullptr;
+  ms.pairs = (int32_t)ctx->params.batch_pairs;
   if (off > kScratchBytes) return fail(SBC_E_TOO_LARGE, "piece state does not fit the no-allocation scratch");
   // The slot arrays of one kind are contiguous per slot: slot b uses
   // [b*stride*64, (b+1)*stride*64) of sg, q, qm and [b*stride, ...) of the

@@ -95,11 +95,13 @@ Plan::~Plan() {
 size_t Plan::device_bytes() const {
   size_t t = 0;
   for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
-                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &ms_sg, &ms_q, &ms_qm, &ms_vis, &ms_fa, &ms_fb,
-                          &ms_ba, &ms_bb, &ms_lvl, &ms_part, &ms_prof, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
+                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
                           &tm_fc, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof, &tm_ctl, &tm_heavy, &dump_dist,
                           &dump_sigma, &dump_delta})
     t += b->bytes;
+  for (const BatchState& b : bst)
+    for (const DevBuf* d : {&b.sg, &b.q, &b.qm, &b.vis, &b.fa, &b.fb, &b.ba, &b.bb, &b.lvl, &b.part, &b.prof})
+      t += d->bytes;
   for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes;
   return t;
 }
@@ -271,6 +273,12 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (k == KC_TEAM && opt.force_kernel != 4 && pr.team_max_levels > 0 &&
         bfs_depth(prob, p) > pr.team_max_levels)
       k = KC_BATCH;
+    // Pieces deeper than deep_min_levels run on the batch kernel in their own
+    // launch and shape: most of their entries carry a few lanes, and more
+    // waves per workgroup keep more of them in flight.
+    if ((k == KC_BATCH || k == KC_TEAM) && opt.force_kernel == 0 && pr.deep_min_levels > 0 &&
+        np > pr.deep_min_levels && bfs_depth(prob, p) > pr.deep_min_levels)
+      k = KC_DEEP;
     // A small piece must fit LDS with the class's largest vertex count: then
     // any mix of the class's pieces fits one launch.
     if (k == KC_WAVE &&
@@ -294,12 +302,19 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     }
     max_np[k] = std::max(max_np[k], np);
   }
-  // Tuning runs may keep an evenly spaced sample of each class's items (the
-  // result then covers only their sources).
+  // Tuning runs may keep an evenly spaced sample of the items (the result
+  // then covers only their sources): the class with the most items keeps at
+  // most sample_items of them, and every other class the same fraction of
+  // its own (at least one), so that one factor scales the whole run.
   total_items = 0;
+  size_t most = 0;
+  for (int k = 0; k < KC_COUNT; ++k) most = std::max(most, items[k].size());
+  const double keep_frac = (pr.sample_items > 0 && most > (size_t)pr.sample_items)
+                               ? (double)pr.sample_items / (double)most : 1.0;
   for (int k = 0; k < KC_COUNT; ++k) {
-    if (pr.sample_items > 0 && (int64_t)items[k].size() > pr.sample_items) {
-      const size_t total = items[k].size(), keep = (size_t)pr.sample_items;
+    if (keep_frac < 1.0 && !items[k].empty()) {
+      const size_t total = items[k].size();
+      const size_t keep = std::min(total, std::max<size_t>(1, (size_t)std::llround(keep_frac * (double)total)));
       std::vector<WorkItem> kept;
       std::vector<double> kt, kb;
       for (size_t j = 0; j < keep; ++j) {
@@ -350,7 +365,6 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   (void)hipMemGetInfo(&freeb, &totalb);
   size_t budget = pr.mem_budget_mb > 0 ? (size_t)pr.mem_budget_mb << 20 : (size_t)(freeb * 0.6);
   const int cus = c->cus;
-  block[KC_BATCH] = (int)pr.batch_wg_waves * 64;
   if (nitems[KC_WAVE]) {
     // The launch's LDS holds the largest piece's vertices and the most arcs
     // of any piece of the class; each fits, and both together must too.
@@ -373,50 +387,53 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (pr.slots > 0) g = (int)pr.slots;
     grid[KC_WAVE] = std::max(1, std::min(g, nitems[KC_WAVE]));
   }
-  if (nitems[KC_BATCH]) {
-    const int64_t stride = max_np[KC_BATCH];
+  for (int k : {KC_BATCH, KC_DEEP}) {
+    if (!nitems[k]) continue;
+    BatchState& B = batch_of(k);
+    const int64_t stride = max_np[k];
     int64_t max_arcs = 0;
     for (int32_t p = 0; p < P; ++p) {
       const int32_t vb = prob.vtx_off[p], np = prob.vtx_off[p + 1] - vb;
-      if (piece_class[p] == KC_BATCH)
-        max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
+      if (piece_class[p] == k) max_arcs = std::max<int64_t>(max_arcs, (int64_t)prob.row[vb + np] - prob.row[vb]);
     }
     const int64_t part_cap = max_arcs / kMsSliceArcs + 2 * kMsHeavyMax;
-    batch_eu = opt.dump ? 0 : (int)pr.batch_waves_per_eu;  // the dump variant: compiler default only
-    const int occ = occupancy_ms((int)pr.batch_wg_waves, batch_eu);
+    B.waves = (int)(k == KC_DEEP ? pr.deep_wg_waves : pr.batch_wg_waves);
+    // the dump variant is built at the compiler's default occupancy only
+    B.eu = opt.dump ? 0 : (int)(k == KC_DEEP ? pr.deep_waves_per_eu : pr.batch_waves_per_eu);
+    block[k] = B.waves * 64;
+    const int occ = occupancy_ms(B.waves, B.eu);
     int g = cus * occ;
     if (pr.slots > 0) g = (int)pr.slots;
     const size_t per = ms_slot_bytes(stride, part_cap);
     g = std::min<int64_t>(g, std::max<int64_t>(1, (int64_t)(budget / per)));
-    g = std::max(1, std::min(g, nitems[KC_BATCH]));
-    grid[KC_BATCH] = g;
+    g = std::max(1, std::min(g, nitems[k]));
+    grid[k] = g;
+    MsState& ms = B.ms;
     ms.stride = stride;
     ms.part_cap = (int32_t)part_cap;
+    ms.pairs = (int32_t)pr.batch_pairs;
     const size_t G = g;
-    if ((e = ms_sg.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms sg");
-    if ((e = ms_q.alloc(G * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc ms q");
-    if ((e = ms_qm.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms qm");
-    if ((e = ms_vis.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms vis");
-    if ((e = ms_fa.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms fa");
-    if ((e = ms_fb.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms fb");
-    if ((e = ms_ba.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms ba");
-    if ((e = ms_bb.alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms bb");
-    if ((e = ms_lvl.alloc(G * (stride + 3) * 4)) != hipSuccess) return hip_fail(e, "alloc ms lvl");
-    if ((e = ms_part.alloc(G * part_cap * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms part");
-    ms.sg = ms_sg.as<double>();
-    ms.q = ms_q.as<int32_t>();
-    ms.qm = ms_qm.as<uint64_t>();
-    ms.vis = ms_vis.as<uint64_t>();
-    ms.fa = ms_fa.as<uint64_t>();
-    ms.fb = ms_fb.as<uint64_t>();
-    ms.ba = ms_ba.as<uint64_t>();
-    ms.bb = ms_bb.as<uint64_t>();
-    ms.lvl = ms_lvl.as<int32_t>();
-    ms.part = ms_part.as<double>();
+    if ((e = B.sg.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms sg");
+    if ((e = B.q.alloc(G * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc ms q");
+    if ((e = B.qm.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms qm");
+    for (DevBuf* d : {&B.vis, &B.fa, &B.fb, &B.ba, &B.bb})
+      if ((e = d->alloc(G * stride * 8)) != hipSuccess) return hip_fail(e, "alloc ms masks");
+    if ((e = B.lvl.alloc(G * (stride + 3) * 4)) != hipSuccess) return hip_fail(e, "alloc ms lvl");
+    if ((e = B.part.alloc(G * part_cap * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms part");
+    ms.sg = B.sg.as<double>();
+    ms.q = B.q.as<int32_t>();
+    ms.qm = B.qm.as<uint64_t>();
+    ms.vis = B.vis.as<uint64_t>();
+    ms.fa = B.fa.as<uint64_t>();
+    ms.fb = B.fb.as<uint64_t>();
+    ms.ba = B.ba.as<uint64_t>();
+    ms.bb = B.bb.as<uint64_t>();
+    ms.lvl = B.lvl.as<int32_t>();
+    ms.part = B.part.as<double>();
     ms.prof = nullptr;
     if (pr.profile_phases) {
-      if ((e = ms_prof.alloc(G * kProfCounters * 8)) != hipSuccess) return hip_fail(e, "alloc ms prof");
-      ms.prof = ms_prof.as<uint64_t>();
+      if ((e = B.prof.alloc(G * kProfCounters * 8)) != hipSuccess) return hip_fail(e, "alloc ms prof");
+      ms.prof = B.prof.as<uint64_t>();
     }
     for (uint64_t* p : {ms.vis, ms.fa, ms.fb, ms.ba, ms.bb})
       if ((e = launch_fill_u64(p, 0, (int64_t)G * stride, own)) != hipSuccess) return hip_fail(e, "fill ms");
@@ -514,8 +531,11 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
   int32_t* flags = ctl + kCtlFlags;
   if ((e = launch_fill_f64(d_bcp.as<double>(), 0.0, V, s)) != hipSuccess) return hip_fail(e, "fill bcp");
   if ((e = launch_fill_i32(ctl, 0, kCtlInts, s)) != hipSuccess) return hip_fail(e, "fill ctl");
-  if (ms.prof && (e = launch_fill_u64(ms.prof, 0, (int64_t)grid[KC_BATCH] * kProfCounters, s)) != hipSuccess)
-    return hip_fail(e, "fill prof");
+  for (int k : {KC_BATCH, KC_DEEP}) {
+    const MsState& ms = batch_of(k).ms;
+    if (nitems[k] && ms.prof && (e = launch_fill_u64(ms.prof, 0, (int64_t)grid[k] * kProfCounters, s)) != hipSuccess)
+      return hip_fail(e, "fill prof");
+  }
   if (nitems[KC_TEAM]) {
     if ((e = launch_fill_i32((int32_t*)targs.ctl, 0, (int64_t)targs.nteams * (int64_t)(sizeof(TeamCtl) / 4), s)) !=
         hipSuccess)
@@ -529,7 +549,7 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
   // Largest classes first so the long multi-source items start early.  The
   // team kernel occupies the whole device, so the other classes follow it.
   const DumpOut* dp_dump = dump.dist ? &dump : nullptr;
-  const int order[3] = {KC_TEAM, KC_BATCH, KC_WAVE};
+  const int order[4] = {KC_TEAM, KC_DEEP, KC_BATCH, KC_WAVE};
   for (int k : order) {
     if (!nitems[k]) continue;
     hipStream_t ks = side[k];
@@ -539,8 +559,9 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
     QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], kArgMagic, heads + k, flags, done + k};
     if (k == KC_TEAM) {
       e = launch_team(dp, qa, reach, ident, team_waves, team_eu, grid[k], tm, targs, dp_dump, ks);
-    } else if (k == KC_BATCH) {
-      e = launch_ms(dp, qa, reach, ident, block[k] / 64, (int)batch_eu, grid[k], ms, dp_dump, ks);
+    } else if (k == KC_BATCH || k == KC_DEEP) {
+      const BatchState& B = batch_of(k);
+      e = launch_ms(dp, qa, reach, ident, B.waves, B.eu, grid[k], B.ms, dp_dump, ks);
     } else {
       e = launch_wave(dp, qa, reach, ident, wave_waves, grid[k], wave_np, wave_arcs, dp_dump, ks);
     }
@@ -633,11 +654,11 @@ sbc_status Plan::sync(sbc_run_stats* st) {
     ms_tr = ms_all;
   }
   const int32_t flags = h_ctl[kCtlFlags];
-  if (ms.prof || tm.prof) {
+  if (bst[0].ms.prof || bst[1].ms.prof || tm.prof) {
     h_prof.assign(kProfCounters, 0);
     prof_slots = 0;
-    for (int k : {KC_BATCH, KC_TEAM}) {
-      uint64_t* src = (k == KC_BATCH) ? ms.prof : tm.prof;
+    for (int k : {KC_BATCH, KC_DEEP, KC_TEAM}) {
+      uint64_t* src = (k == KC_TEAM) ? tm.prof : batch_of(k).ms.prof;
       if (!src || !nitems[k]) continue;
       std::vector<uint64_t> raw((size_t)grid[k] * kProfCounters);
       if ((e = hipMemcpy(raw.data(), src, raw.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
@@ -655,7 +676,7 @@ sbc_status Plan::sync(sbc_run_stats* st) {
     st->teps = teps;
     st->algo_bytes = algo_bytes;
     st->items = total_items;
-    st->batched_sources = sources_in[KC_BATCH] + sources_in[KC_TEAM];
+    st->batched_sources = sources_in[KC_BATCH] + sources_in[KC_DEEP] + sources_in[KC_TEAM];
     st->lds_sources = sources_in[KC_WAVE];
     st->global_sources = 0;
     st->overflow = flags;

@@ -42,6 +42,10 @@ struct Params {
   int64_t wave_sources_per_item = 64; // sources per small-piece work item (at most 64)
   int64_t slots = 0;                  // resident workgroups per kernel (0: from occupancy)
   int64_t cluster_sources = 2;        // batch source order: 0 as is, 1 balls, 2 common-hub groups then balls
+  int64_t batch_pairs = 16;           // batch kernel: rows of <= 32 arcs with at most this many lanes pulled as pairs
+  int64_t deep_min_levels = 64;       // pieces deeper than this (BFS from the highest-degree vertex): deep class
+  int64_t deep_wg_waves = 16;         // wavefronts per workgroup of the deep class's batch kernel
+  int64_t deep_waves_per_eu = 0;      // occupancy target of the deep class's batch kernel
   int64_t mem_budget_mb = 0;          // traversal state budget (0: 60% of free memory)
   int64_t profile_phases = 0;         // 1: per-phase timers in the batch kernel
   int64_t order_plain = 0;            // 1: plain problems renumbered breadth-first
@@ -80,10 +84,18 @@ struct sbc_graph_s {
 namespace sbc {
 
 // KC_WAVE: small-piece kernel (one source per wavefront, the piece in LDS).
-// KC_BATCH: 64-source batches, one workgroup per batch.  KC_TEAM: 64-source
-// batches, one team of workgroups per batch.  Classes 1 and 3 are not used
-// (their slots in sbc_run_stats stay zero).
-enum KernelClass { KC_WAVE = 0, KC_BATCH = 2, KC_TEAM = 4, KC_COUNT = 5 };
+// KC_BATCH: 64-source batches, one workgroup per batch.  KC_DEEP: the same
+// kernel for deep pieces (many levels), launched separately in its own
+// workgroup shape.  KC_TEAM: 64-source batches, one team of workgroups per
+// batch.  Class 1 is not used (its slots in sbc_run_stats stay zero).
+enum KernelClass { KC_WAVE = 0, KC_BATCH = 2, KC_DEEP = 3, KC_TEAM = 4, KC_COUNT = 5 };
+
+// Per-slot state of one launch of the 64-source batch kernel.
+struct BatchState {
+  DevBuf sg, q, qm, vis, fa, fb, ba, bb, lvl, part, prof;
+  MsState ms{};
+  int waves = 8, eu = 8;  // workgroup shape of the launch
+};
 
 struct PlanOptions {
   int force_kernel = 0;                 // 0 automatic, 3 batch, 4 team, 5 small-piece
@@ -111,18 +123,16 @@ struct Plan {
   int grid[KC_COUNT] = {0, 0, 0, 0, 0};
   int block[KC_COUNT] = {256, 0, 512, 0, 512};
   int64_t sources_in[KC_COUNT] = {0, 0, 0, 0, 0};
-  // slot state
-  DevBuf ms_sg, ms_q, ms_qm, ms_vis, ms_fa, ms_fb, ms_ba, ms_bb, ms_lvl, ms_part, ms_prof;
+  // slot state: the batch kernel's launches (batch and deep classes)
+  BatchState bst[2];
   std::vector<uint64_t> h_prof;  // last execution's phase timers, summed over slots
   int64_t prof_slots = 0;        // workgroups whose timers h_prof sums
-  MsState ms{};
   // team kernel state: one slot per team, plus control blocks and split-row lists
   DevBuf tm_sg, tm_q, tm_qm, tm_vis, tm_fa, tm_fb, tm_fc, tm_ba, tm_bb, tm_bc, tm_lvl, tm_part, tm_prof, tm_ctl,
       tm_heavy;
   MsState tm{};
   TeamArgs targs{};
   int team_waves = 8, team_eu = 8;
-  int batch_eu = 8;                         // occupancy target of the batch kernel's launch
   int wave_waves = 4;                       // small-piece kernel: waves per workgroup
   int32_t wave_np = 0, wave_arcs = 0;       // its LDS is sized for these
   DumpOut dump{};                           // verification dump (dump.dist null when off)
@@ -147,6 +157,8 @@ struct Plan {
   double last_host_ms = 0;
 
   ~Plan();
+  // BatchState of a batch-kernel class (KC_BATCH or KC_DEEP)
+  BatchState& batch_of(int k) { return bst[k == KC_DEEP ? 1 : 0]; }
   sbc_status build(sbc_context c, const Prepared& prob, uint32_t mode, const PlanOptions& opt);
   sbc_status build_impl(sbc_context c, const Prepared& prob, uint32_t mode, const PlanOptions& opt);
   // Wait for everything this plan enqueued; called before any buffer is freed.

@@ -95,13 +95,21 @@ def main(which):
                 assert_bc_close(sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ops="odai", ctx=ctx), want,
                                 1e-9, f"{name}/odai")
                 sbc.sbc_context_set_param(ctx.h, "order_plain", 0)
-                # default routing, then every piece on the batch kernel
-                for wave_max in (256, 0):
+                # default routing, then every piece on the batch kernel, with
+                # and without the pair path
+                # (deep_min_levels 2 sends every piece deeper than two levels
+                # to the deep class's own launch, in 4-wave workgroups)
+                for wave_max, pairs, deep in ((256, 16, 64), (0, 64, 64), (0, 0, 64), (0, 16, 2)):
                     sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", wave_max)
+                    sbc.sbc_context_set_param(ctx.h, "batch_pairs", pairs)
+                    sbc.sbc_context_set_param(ctx.h, "deep_min_levels", deep)
+                    sbc.sbc_context_set_param(ctx.h, "deep_wg_waves", 4)
                     for mode in ("plain", "compressed"):
                         got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=ctx)
-                        assert_bc_close(got, want, 1e-9, f"{name}/{mode}/wave_max={wave_max}")
+                        assert_bc_close(got, want, 1e-9, f"{name}/{mode}/wave_max={wave_max}/pairs={pairs}/deep={deep}")
                 sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", 256)
+                sbc.sbc_context_set_param(ctx.h, "batch_pairs", 16)
+                sbc.sbc_context_set_param(ctx.h, "deep_min_levels", 64)
                 print(f"   {name} n={g.n} ok", flush=True)
         check("whole graphs", whole)
 

@@ -50,6 +50,13 @@ def test_small_stage_keys_are_tuned_keys():
     assert any(c["wave_max_vertices"] == 0 for c in at.SMALL_CANDIDATES)  # the kernel off is a choice
 
 
+def test_deep_stage_keys_are_tuned_keys():
+    for c in at.DEEP_CANDIDATES:
+        assert set(c) <= set(at.TUNED_KEYS)
+    # the first stage runs the library's default deep shape
+    assert all(c["deep_wg_waves"] == 16 and c["deep_waves_per_eu"] == 0 for c in at.CANDIDATES)
+
+
 def test_smallest_piece():
     g = gg.block_tree(n_pieces=30, max_size=200, seed=5)
     G = sbc.Graph(g.n, g.row_ptr, g.col)

@@ -53,6 +53,40 @@ def test_autotune_small_piece_stage(tmp_path):
     ctx.close()
 
 
+def test_sampled_estimate_of_a_two_class_plan():
+    """A block tree with small pieces (small-piece kernel) and larger ones
+    (batch kernel): a sampled plan keeps the same fraction of both classes'
+    items, and its scaled time estimates the full run's within 35%."""
+    g = gg.block_tree(n_pieces=4000, max_size=2048, seed=47)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+
+    def run(params, reps):
+        ctx = sbc.Context(0, params)
+        plan = sbc.sbc_plan_create(ctx.h, G.h, sbc.SBC_COMPRESSED)
+        try:
+            ts = []
+            for _ in range(reps):
+                sbc.sbc_plan_execute(plan)
+                st = sbc.sbc_plan_sync(plan)
+                ts.append(st["ms_traverse"])
+        finally:
+            sbc.sbc_plan_destroy(plan)
+            ctx.close()
+        return st, float(np.median(ts))
+
+    full, t_full = run({}, 3)
+    assert full["items_class"][0] > 0 and full["items_class"][2] > 0, full["items_class"]
+    keep = full["items_class"][2] // 4
+    samp, t_samp = run({"sample_items": keep}, 3)
+    for k in (0, 2):
+        frac = samp["items_class"][k] / full["items_class"][k]
+        assert abs(frac - 0.25) <= 1.0 / full["items_class"][k] + 0.01, (k, samp["items_class"], full["items_class"])
+    est = t_samp * full["items"] / samp["items"]
+    print(f"full {t_full:.2f} ms, sampled {t_samp:.2f} ms, estimate {est:.2f} ms", flush=True)
+    assert 0.65 * t_full <= est <= 1.35 * t_full
+
+
 @pytest.mark.parametrize("team", [0, 3])
 def test_sampled_plan_runs_the_sample(team):
     """sample_items keeps an evenly spaced subset of each class's items (here 3
