@@ -53,6 +53,17 @@ typedef int32_t sbc_status;
 #define SBC_PLAIN 0u         /* Algorithm 1 on the whole graph, no preprocessing */
 #define SBC_COMPRESSED 1u    /* preprocess (default "odai" unless the graph was preprocessed) */
 #define SBC_UNORDERED 2u     /* report unordered-pair scores (Eq. (1) halved) */
+/* Bit-reproducible result: every work item (a piece and up to 64 of its
+ * sources) accumulates its dependencies (Eq. (3), Algorithm 2's accumulation
+ * step) into an area of its own, and the areas of a piece are summed in the
+ * order of its sources afterwards, so no sum depends on the order in which
+ * the device schedules items.  The same graph, mode and context parameters
+ * then give the same bits on every run, alone or served beside other jobs.
+ * Costs one double per (item, piece vertex) of device memory, and small
+ * pieces run on the 64-source batch kernel instead of the small-piece kernel
+ * (whose waves add into shared sums in no fixed order), with every entry
+ * pulled by a whole wave. */
+#define SBC_DETERMINISTIC 4u
 
 typedef struct sbc_context_s* sbc_context;
 typedef struct sbc_graph_s* sbc_graph;

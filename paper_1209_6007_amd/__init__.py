@@ -36,6 +36,7 @@ SBC_SANITIZE = 1
 SBC_PLAIN = 0
 SBC_COMPRESSED = 1
 SBC_UNORDERED = 2
+SBC_DETERMINISTIC = 4
 
 STATUS = {
     0: "SBC_OK", -1: "SBC_E_INVALID_ARG", -2: "SBC_E_NOT_SYMMETRIC", -3: "SBC_E_SELF_LOOP",
@@ -173,6 +174,8 @@ def _mode(mode) -> int:
     m = {"plain": SBC_PLAIN, "compressed": SBC_COMPRESSED}[mode.split("+")[0]]
     if "unordered" in mode:
         m |= SBC_UNORDERED
+    if "deterministic" in mode:
+        m |= SBC_DETERMINISTIC
     return m
 
 

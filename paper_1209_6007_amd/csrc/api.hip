@@ -277,7 +277,7 @@ static sbc_status ensure_problem(sbc_context ctx, sbc_graph g, uint32_t mode, Pr
 
 sbc_status sbc_plan_create(sbc_context ctx, sbc_graph g, uint32_t mode, sbc_plan* out) {
   if (!ctx || !g || !out) return fail(SBC_E_INVALID_ARG, "NULL argument");
-  if (mode & ~(SBC_COMPRESSED | SBC_UNORDERED)) return fail(SBC_E_INVALID_ARG, "unknown mode bit");
+  if (mode & ~(SBC_COMPRESSED | SBC_UNORDERED | SBC_DETERMINISTIC)) return fail(SBC_E_INVALID_ARG, "unknown mode bit");
   *out = nullptr;
   SBC_TRY({
     Prepared plain;

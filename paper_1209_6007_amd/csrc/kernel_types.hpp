@@ -189,6 +189,11 @@ struct QueueArgs {
   int32_t* head;      // next item to take (device counter, zero before launch)
   int32_t* flags;     // kFlag* bits
   int32_t* done;      // items finished (device counter)
+  // Deterministic runs: item i accumulates its bc' into its own area
+  // item_out[item_base[i] .. + piece vertices) instead of the shared bc'
+  // (null otherwise); a later reduction sums the areas in a fixed order.
+  const int64_t* item_base;
+  double* item_out;
 };
 
 }  // namespace sbc

@@ -274,6 +274,15 @@ hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t
   return hipGetLastError();
 }
 
+hipError_t launch_det_reduce(int32_t nverts, int32_t npieces, const int32_t* vtx_off, const int64_t* area_base,
+                             const int32_t* piece_items, const double* item_out, double* bcp, hipStream_t stream) {
+  if (nverts <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(det_reduce_kernel, dim3((nverts + 255) / 256), dim3(256), 0, stream, nverts, npieces, vtx_off,
+                     area_base, piece_items, item_out, bcp);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, int grid, hipStream_t stream) {
   const int64_t n = bytes / 16;
   if (n <= 0) return hipSuccess;

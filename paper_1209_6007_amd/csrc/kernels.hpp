@@ -25,6 +25,10 @@ hipError_t launch_wave(const DevPieces& P, const QueueArgs& Q, bool reach, bool 
 hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
                           const double* bcp, const double* corr, const double* bcx, double scale, double* out,
                           hipStream_t stream);
+// Deterministic runs: bcp[x] = sum over x's piece's items, in item order, of
+// the item areas (see QueueArgs::item_base).
+hipError_t launch_det_reduce(int32_t nverts, int32_t npieces, const int32_t* vtx_off, const int64_t* area_base,
+                             const int32_t* piece_items, const double* item_out, double* bcp, hipStream_t stream);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, int grid, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t stream);

@@ -651,7 +651,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
     const int32_t* col = P.col;
     const int32_t* rch = REACH ? P.reach + vb : nullptr;
     const int32_t* idn = IDENT ? P.ident + vb : nullptr;
-    double* bcp = P.bcp + vb;
+    double* bcp = Q.item_base ? Q.item_out + Q.item_base[it] : P.bcp + vb;  // the item's own area when deterministic
     const int nsrc = W.s1 - W.s0;  // 1..64
 
     // Lane j runs source src_order[vb + s0 + j].
@@ -1183,7 +1183,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
     const int32_t* col = P.col;
     const int32_t* rch = REACH ? P.reach + vb : nullptr;
     const int32_t* idn = IDENT ? P.ident + vb : nullptr;
-    double* bcp = P.bcp + vb;
+    double* bcp = Q.item_base ? Q.item_out + Q.item_base[it] : P.bcp + vb;  // the item's own area when deterministic
     const int nsrc = W.s1 - W.s0;
 
     // Lane j runs source src_order[vb + s0 + j].
@@ -1821,7 +1821,7 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
     __syncthreads();
     for (int v = tid; v < np; v += BLOCK) {
       const double x = s_bc[v];
-      if (x != 0.0) atomicAdd(&P.bcp[vb + v], x);
+      if (x != 0.0) atomicAdd(Q.item_base ? &Q.item_out[Q.item_base[it] + v] : &P.bcp[vb + v], x);
     }
     if (tid == 0) atomicAdd(Q.done, 1);
     __syncthreads();  // LDS is refilled by the next item
@@ -1842,6 +1842,28 @@ __global__ void mapback_kernel(int32_t n, int32_t nverts, int32_t nmap, const in
     acc += bcp[x] + (corr ? corr[x] : 0.0);
   }
   out[v] = acc * scale;
+}
+
+// Deterministic runs: bc'[x] of packed piece vertex x is the sum, in item
+// order (the order of the sources), of x's value in the areas of its piece's
+// items; piece p's c_p items own consecutive areas of n_p values from
+// area_base[p].
+__global__ void det_reduce_kernel(int32_t nverts, int32_t npieces, const int32_t* __restrict__ vtx_off,
+                                  const int64_t* __restrict__ area_base, const int32_t* __restrict__ piece_items,
+                                  const double* __restrict__ item_out, double* __restrict__ bcp) {
+  const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nverts) return;
+  int32_t lo = 0, hi = npieces - 1;  // the piece holding x
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (vtx_off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  const int32_t np = vtx_off[lo + 1] - vtx_off[lo];
+  const double* a = item_out + area_base[lo] + (x - vtx_off[lo]);
+  double acc = 0.0;
+  for (int32_t j = 0; j < piece_items[lo]; ++j) acc += a[(size_t)j * np];
+  bcp[x] = acc;
 }
 
 // Streaming copy of 16-byte words: a kernel of known traffic (read n*16

@@ -4,6 +4,7 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstring>
 #include <numeric>
@@ -95,14 +96,14 @@ Plan::~Plan() {
 size_t Plan::device_bytes() const {
   size_t t = 0;
   for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
-                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
+                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &d_area_base, &d_piece_items, &d_item_out, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
                           &tm_fc, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof, &tm_ctl, &tm_heavy, &dump_dist,
                           &dump_sigma, &dump_delta})
     t += b->bytes;
   for (const BatchState& b : bst)
     for (const DevBuf* d : {&b.sg, &b.q, &b.qm, &b.vis, &b.fa, &b.fb, &b.ba, &b.bb, &b.lvl, &b.part, &b.prof})
       t += d->bytes;
-  for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes;
+  for (int c = 0; c < KC_COUNT; ++c) t += d_items[c].bytes + d_item_base[c].bytes;
   return t;
 }
 
@@ -228,6 +229,12 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if ((e = hipEventCreate(&ev_kc_end[k])) != hipSuccess) return hip_fail(e, "event");
   }
   const bool plain = !(mode & SBC_COMPRESSED);
+  // Deterministic runs: every item sums into its own area, reduced in a fixed
+  // order afterwards.  Small pieces go to the batch kernel (the small-piece
+  // kernel's waves add into shared LDS sums in no fixed order), and the batch
+  // kernel pulls every entry with a whole wave (the pair path's per-entry LDS
+  // sums have no fixed order either).
+  det = (mode & SBC_DETERMINISTIC) != 0;
   const Prepared* probp = &prob_in;
   Prepared local;
   if (opt.sources || (pr.cluster_sources && prob_in.pieces() > 0)) {
@@ -260,6 +267,10 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
 
   // Work items by kernel class.
   std::vector<WorkItem> items[KC_COUNT];
+  std::vector<int64_t> item_base[KC_COUNT];
+  std::vector<int64_t> area_base(P, 0);
+  std::vector<int32_t> piece_items(P, 0);
+  det_values = 0;
   std::vector<double> item_teps[KC_COUNT], item_bytes[KC_COUNT];
   std::vector<int> piece_class(P, -1);
   teps = 0;
@@ -288,6 +299,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       if (opt.force_kernel == 5) return fail(SBC_E_INVALID_ARG, "piece too large for the small-piece kernel");
       k = (pr.team_min_vertices > 0 && np >= pr.team_min_vertices) ? KC_TEAM : KC_BATCH;
     }
+    if (det && k == KC_WAVE) k = (pr.team_min_vertices > 0 && np >= pr.team_min_vertices) ? KC_TEAM : KC_BATCH;
     piece_class[p] = k;
     int32_t nsrc = np;
     if (opt.sources) nsrc = (int32_t)opt.nsrc;
@@ -297,9 +309,13 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     for (int32_t s0 = 0; s0 < nsrc; s0 += chunk) {
       const int32_t s1 = std::min(nsrc, s0 + chunk);
       items[k].push_back({p, s0, s1, k});
+      item_base[k].push_back(det_values + (int64_t)piece_items[p] * np);
+      piece_items[p]++;
       item_teps[k].push_back((double)(s1 - s0) * (double)arcs * 0.5);
       item_bytes[k].push_back((double)(s1 - s0) * per);
     }
+    area_base[p] = det_values;
+    det_values += (int64_t)piece_items[p] * np;
     max_np[k] = std::max(max_np[k], np);
   }
   // Tuning runs may keep an evenly spaced sample of the items (the result
@@ -317,13 +333,16 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       const size_t keep = std::min(total, std::max<size_t>(1, (size_t)std::llround(keep_frac * (double)total)));
       std::vector<WorkItem> kept;
       std::vector<double> kt, kb;
+      std::vector<int64_t> kbase;
       for (size_t j = 0; j < keep; ++j) {
         const size_t idx = j * total / keep;
         kept.push_back(items[k][idx]);
         kt.push_back(item_teps[k][idx]);
         kb.push_back(item_bytes[k][idx]);
+        kbase.push_back(item_base[k][idx]);
       }
       items[k].swap(kept);
+      item_base[k].swap(kbase);
       item_teps[k].swap(kt);
       item_bytes[k].swap(kb);
     }
@@ -355,6 +374,14 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   if ((e = d_out.alloc(std::max<int32_t>(n, 1) * sizeof(double))) != hipSuccess) return hip_fail(e, "alloc out");
   for (int k = 0; k < KC_COUNT; ++k)
     if ((e = upload(d_items[k], items[k])) != hipSuccess) return hip_fail(e, "upload items");
+  if (det) {
+    for (int k = 0; k < KC_COUNT; ++k)
+      if ((e = upload(d_item_base[k], item_base[k])) != hipSuccess) return hip_fail(e, "upload item areas");
+    if ((e = upload(d_area_base, area_base)) != hipSuccess) return hip_fail(e, "upload item areas");
+    if ((e = upload(d_piece_items, piece_items)) != hipSuccess) return hip_fail(e, "upload item areas");
+    if ((e = d_item_out.alloc((size_t)std::max<int64_t>(det_values, 1) * sizeof(double))) != hipSuccess)
+      return hip_fail(e, "alloc per-item areas of a deterministic run");
+  }
   if ((e = d_ctl.alloc(sizeof(int32_t) * kCtlInts)) != hipSuccess) return hip_fail(e, "alloc ctl");
   if ((e = hipHostMalloc((void**)&h_ctl, sizeof(int32_t) * kCtlInts, hipHostMallocDefault)) != hipSuccess)
     return hip_fail(e, "hipHostMalloc");
@@ -411,7 +438,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     MsState& ms = B.ms;
     ms.stride = stride;
     ms.part_cap = (int32_t)part_cap;
-    ms.pairs = (int32_t)pr.batch_pairs;
+    ms.pairs = det ? 0 : (int32_t)pr.batch_pairs;
     const size_t G = g;
     if ((e = B.sg.alloc(G * stride * 64 * 8)) != hipSuccess) return hip_fail(e, "alloc ms sg");
     if ((e = B.q.alloc(G * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc ms q");
@@ -530,6 +557,8 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
   int32_t* done = ctl + kCtlDone;
   int32_t* flags = ctl + kCtlFlags;
   if ((e = launch_fill_f64(d_bcp.as<double>(), 0.0, V, s)) != hipSuccess) return hip_fail(e, "fill bcp");
+  if (det && (e = launch_fill_f64(d_item_out.as<double>(), 0.0, det_values, s)) != hipSuccess)
+    return hip_fail(e, "fill item areas");
   if ((e = launch_fill_i32(ctl, 0, kCtlInts, s)) != hipSuccess) return hip_fail(e, "fill ctl");
   for (int k : {KC_BATCH, KC_DEEP}) {
     const MsState& ms = batch_of(k).ms;
@@ -556,7 +585,8 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
     hipEvent_t after = (k != KC_TEAM && nitems[KC_TEAM]) ? ev_kc_end[KC_TEAM] : ev_fork;
     if ((e = hipStreamWaitEvent(ks, after, 0)) != hipSuccess) return hip_fail(e, "wait");
     if (!use_graph && (e = hipEventRecord(ev_kc_start[k], ks)) != hipSuccess) return hip_fail(e, "event");
-    QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], kArgMagic, heads + k, flags, done + k};
+    QueueArgs qa{d_items[k].as<WorkItem>(), nitems[k], kArgMagic, heads + k, flags, done + k,
+                 det ? d_item_base[k].as<int64_t>() : nullptr, det ? d_item_out.as<double>() : nullptr};
     if (k == KC_TEAM) {
       e = launch_team(dp, qa, reach, ident, team_waves, team_eu, grid[k], tm, targs, dp_dump, ks);
     } else if (k == KC_BATCH || k == KC_DEEP) {
@@ -569,6 +599,10 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
     if ((e = hipEventRecord(ev_kc_end[k], ks)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipStreamWaitEvent(s, ev_kc_end[k], 0)) != hipSuccess) return hip_fail(e, "wait");
   }
+  if (det && (e = launch_det_reduce((int32_t)V, P, d_vtx_off.as<int32_t>(), d_area_base.as<int64_t>(),
+                                    d_piece_items.as<int32_t>(), d_item_out.as<double>(), d_bcp.as<double>(), s)) !=
+                 hipSuccess)
+    return hip_fail(e, "launch deterministic reduction");
   if (!use_graph && (e = hipEventRecord(ev_trav, s)) != hipSuccess) return hip_fail(e, "event");
   double* dst = out ? out : d_out.as<double>();
   if (has_map) {

@@ -116,6 +116,10 @@ struct Plan {
   // device problem
   DevBuf d_vtx_off, d_row, d_col, d_reach, d_ident, d_src, d_bcp, d_corr, d_bcx, d_map_off, d_map_idx, d_out;
   DevBuf d_items[KC_COUNT];
+  // deterministic runs: per-item bc' areas (see QueueArgs::item_base)
+  bool det = false;
+  int64_t det_values = 0;   // doubles in d_item_out
+  DevBuf d_item_base[KC_COUNT], d_area_base, d_piece_items, d_item_out;
   DevBuf d_ctl;             // int32: heads[KC_COUNT] at 0, done[KC_COUNT] at 8, flags at 16
   int32_t* h_ctl = nullptr; // pinned copy of the control block
   int32_t nitems[KC_COUNT] = {0, 0, 0, 0, 0};

@@ -221,7 +221,7 @@ sbc_status sbc_server_destroy(sbc_server s) {
 
 sbc_status sbc_server_submit(sbc_server s, sbc_graph g, uint32_t mode, sbc_job* out) {
   if (!s || !g || !out) return fail(SBC_E_INVALID_ARG, "NULL argument");
-  if (mode & ~(SBC_COMPRESSED | SBC_UNORDERED)) return fail(SBC_E_INVALID_ARG, "unknown mode bit");
+  if (mode & ~(SBC_COMPRESSED | SBC_UNORDERED | SBC_DETERMINISTIC)) return fail(SBC_E_INVALID_ARG, "unknown mode bit");
   sbc_job j = new (std::nothrow) sbc_job_s();
   if (!j) return fail(SBC_E_OOM, "host allocation failed");
   j->g = g;

@@ -110,6 +110,11 @@ def main(which):
                 sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", 256)
                 sbc.sbc_context_set_param(ctx.h, "batch_pairs", 16)
                 sbc.sbc_context_set_param(ctx.h, "deep_min_levels", 64)
+                # deterministic mode: per-item areas, the same bits twice
+                d1 = sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed+deterministic", ops="odai", ctx=ctx)
+                d2 = sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed+deterministic", ops="odai", ctx=ctx)
+                assert np.array_equal(d1, d2), name
+                assert_bc_close(d1, want, 1e-9, f"{name}/deterministic")
                 print(f"   {name} n={g.n} ok", flush=True)
         check("whole graphs", whole)
 

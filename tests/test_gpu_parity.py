@@ -157,6 +157,37 @@ def test_whole_graph(ctx, name, mode):
     assert_bc_close(got, want, RTOL, f"{name}/{mode}")
 
 
+@pytest.mark.parametrize("name", ["rmat12", "blocks", "grid100", "ba2100"])
+def test_deterministic_runs_are_bit_equal(ctx, name):
+    """SBC_DETERMINISTIC: three runs (two plans, one executed twice, one with
+    a different workgroup count) give the same bits, and match the oracle.
+    grid100 is deep enough for the deep-piece launch; rmat12 is one piece on
+    the team kernel when forced there below."""
+    g = {"rmat12": lambda: gg.rmat_decorated(scale=12, seed=61),
+         "blocks": lambda: gg.block_tree(n_pieces=150, max_size=700, seed=62),
+         "grid100": lambda: gg.grid_deleted(side=100, seed=63),
+         "ba2100": lambda: gg.ba_pendant_triangles()}[name]()
+    want = oracle.bc(g)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+    mode = sbc.SBC_COMPRESSED | sbc.SBC_DETERMINISTIC
+    runs = []
+    for params in ({}, {"slots": 37, "team_min_vertices": 0}, {"team_min_vertices": 64, "team_count": 16}):
+        c = sbc.Context(0, params)
+        plan = sbc.sbc_plan_create(c.h, G.h, mode)
+        try:
+            for _ in range(2 if not runs else 1):
+                sbc.sbc_plan_execute(plan)
+                sbc.sbc_plan_sync(plan)
+                runs.append(sbc.sbc_plan_result(plan, g.n))
+        finally:
+            sbc.sbc_plan_destroy(plan)
+            c.close()
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r, runs[0])
+    assert_bc_close(runs[0], want, RTOL, f"{name} deterministic")
+
+
 def test_unordered_halves(ctx):
     g = gg.ba_pendant_triangles()
     a = run(ctx, g, "compressed")

@@ -107,21 +107,27 @@ def test_sampled_plan_runs_the_sample(team):
     ctx.close()
 
 
-def test_server_mix_equals_alone():
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_server_mix_equals_alone(deterministic):
     """Jobs of different sizes and shapes served together give the results of
-    the same jobs run alone (and the oracle's)."""
+    the same jobs run alone (and the oracle's): bit for bit in deterministic
+    mode, to 1e-12 otherwise (device atomics add in another order)."""
     graphs = [gg.rmat_decorated(scale=s, seed=40 + s) for s in (9, 10, 11)] + \
-             [gg.grid_deleted(side=sd, seed=50 + sd) for sd in (20, 33, 47)] + [gg.ba_pendant_triangles()]
+             [gg.grid_deleted(side=sd, seed=50 + sd) for sd in (20, 33, 47, 90)] + [gg.ba_pendant_triangles()]
+    mode = "compressed+deterministic" if deterministic else "compressed"
     ctx = sbc.Context(0)
-    alone = [sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ctx=ctx) for g in graphs]
+    alone = [sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ops="odai", ctx=ctx) for g in graphs]
     Gs = [sbc.Graph(g.n, g.row_ptr, g.col) for g in graphs]
     srv = sbc.sbc_server_create(ctx.h, 3, 0)
-    jobs = [sbc.sbc_server_submit(srv, G.h, sbc.SBC_COMPRESSED) for G in Gs]
+    jobs = [sbc.sbc_server_submit(srv, G.h, sbc._mode(mode)) for G in Gs]
     for g, j, a in zip(graphs, jobs, alone):
         got, st = sbc.sbc_job_wait(j, g.n)
         sbc.sbc_job_release(j)
         assert st["latency_ms"] > 0
-        assert_bc_close(got, a, 1e-12, "mix vs alone")
+        if deterministic:
+            np.testing.assert_array_equal(got, a)
+        else:
+            assert_bc_close(got, a, 1e-12, "mix vs alone")
         assert_bc_close(got, oracle.bc(g), RTOL, "mix vs oracle")
     sbc.sbc_server_destroy(srv)
     ctx.close()
