@@ -9,6 +9,8 @@ It shares no code with ``paper_1209_6007_amd`` and never imports it.
                       identical-vertex weights of Section 3.3.3, in C, FP64.
 * ``single_source``   per-source levels / path counts / dependencies.
 * ``bc_pieces``       ``bc_weighted`` on every piece of a packed set of pieces.
+* ``bc_side``         Algorithm 3 (Bfs-Side, Section 3.3.2) for side vertices
+                      removed one after another.
 * ``brute.bc_bruteforce`` Eq. (1) evaluated pair by pair (tiny graphs).
 
 All scores are over ordered pairs, unnormalised (Eq. (1)).
@@ -54,6 +56,8 @@ def _load():
         lib.oracle_single_source.restype = ctypes.c_int
         lib.oracle_bc_pieces.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p, ctypes.c_int, f64p]
         lib.oracle_bc_pieces.restype = ctypes.c_int
+        lib.oracle_bc_side.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int64, i32p, ctypes.c_int, f64p]
+        lib.oracle_bc_side.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -138,6 +142,22 @@ def bc_pieces(vtx_off, row, col, reach=None, ident=None, threads: int | None = N
     if rc != 0:
         raise RuntimeError(f"oracle_bc_pieces failed: {rc}")
     return out[:V]
+
+
+def bc_side(n, row_ptr, col, reach, sides, threads: int | None = None) -> np.ndarray:
+    """Algorithm 3 for the side vertices `sides`, removed in that order from
+    the attributed graph (row_ptr, col, reach): bc' contributions per vertex."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    re, rep = _i32(reach if reach is not None else np.ones(n, np.int32))
+    sv, svp = _i32(sides)
+    out = np.zeros(max(n, 1), dtype=np.float64)
+    rc = lib.oracle_bc_side(int(n), rpp, clp, rep, len(sv), svp, threads or default_threads(),
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise RuntimeError(f"oracle_bc_side failed: {rc}")
+    return out[:n]
 
 
 def bc(g, sources=None, threads=None) -> np.ndarray:

@@ -22,6 +22,8 @@
  *   oracle_bc_pieces    -- oracle_bc_weighted on every piece of a packed set of
  *                          pieces (all sources of each piece), for checking a
  *                          whole shattered graph piece by piece.
+ *   oracle_bc_side      -- Algorithm 3 (Bfs-Side, Section 3.3.2) for a list of
+ *                          side vertices removed one after another.
  *
  * Threads split the source list into contiguous static blocks; each thread
  * keeps private arrays and the per-thread scores are added in thread order,
@@ -371,5 +373,131 @@ int oracle_bc_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row, cons
     }
     for (int t = 0; t < nthreads; ++t) free(jobs[t].acc);
     free(jobs); free(tid);
+    return rc;
+}
+
+/*
+ * Algorithm 3 (Bfs-Side, Section 3.3.2) for the side vertices sides[0..nside)
+ * of an attributed graph (reach, no ident), removed one after another in that
+ * order.  Side vertex sides[i] is removed from the graph left after removing
+ * sides[0..i-1], so its breadth-first search runs on that graph: the earlier
+ * ones are skipped as if deleted.  With delta from the search (initialised
+ * to reach-1 as in Algorithm 2), every vertex w != sides[i] of that graph gets
+ *   reach[s]*delta[w] + reach[s]*(delta[w] - (reach[w]-1))
+ * -- the dependencies of the sources s stands for, and those of the pairs
+ * whose target s stands for, which the smaller graph can no longer see.
+ * The searches of different i are independent given i, so threads take
+ * contiguous ranges of i.
+ */
+typedef struct {
+    const int32_t *row_ptr, *col, *reach, *sides, *rank;
+    int32_t n;
+    int64_t i0, i1;
+    double *acc;
+    int status;
+} side_job;
+
+static void *side_worker(void *arg) {
+    side_job *J = (side_job *)arg;
+    const int32_t n = J->n;
+    int32_t *Q = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *d = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    double *sigma = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *delta = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!Q || !d || !sigma || !delta) {
+        free(Q); free(d); free(sigma); free(delta);
+        J->status = -7;
+        return NULL;
+    }
+    for (int64_t i = J->i0; i < J->i1; ++i) {
+        const int32_t s = J->sides[i];
+        /* vertex v is still present iff it is not a side vertex removed before s */
+        for (int32_t v = 0; v < n; ++v) {
+            d[v] = -1;
+            sigma[v] = 0.0;
+        }
+        int32_t qh = 0, qt = 0;
+        Q[qt++] = s;
+        d[s] = 0;
+        sigma[s] = 1.0;
+        while (qh < qt) {
+            const int32_t v = Q[qh++];
+            for (int32_t e = J->row_ptr[v]; e < J->row_ptr[v + 1]; ++e) {
+                const int32_t x = J->col[e];
+                if (J->rank[x] < i) continue;                /* removed earlier */
+                if (d[x] < 0) {
+                    d[x] = d[v] + 1;
+                    Q[qt++] = x;
+                }
+                if (d[x] == d[v] + 1) sigma[x] += sigma[v];
+            }
+        }
+        /* back propagation in reverse BFS order: each vertex takes its
+           dependency from its successors */
+        for (int32_t k = qt - 1; k >= 0; --k) {
+            const int32_t v = Q[k];
+            double dv = (double)(J->reach[v] - 1);
+            for (int32_t e = J->row_ptr[v]; e < J->row_ptr[v + 1]; ++e) {
+                const int32_t x = J->col[e];
+                if (J->rank[x] < i) continue;
+                if (d[x] == d[v] + 1) dv += sigma[v] / sigma[x] * (1.0 + delta[x]);
+            }
+            delta[v] = dv;
+            if (v != s) {
+                const double rs = (double)J->reach[s];
+                J->acc[v] += rs * dv + rs * (dv - (double)(J->reach[v] - 1));
+            }
+        }
+    }
+    free(Q); free(d); free(sigma); free(delta);
+    J->status = 0;
+    return NULL;
+}
+
+int oracle_bc_side(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach, int64_t nside,
+                   const int32_t *sides, int nthreads, double *bc_out) {
+    if (n < 0 || !row_ptr || (n > 0 && !col) || !reach || !bc_out || nside < 0 || (nside > 0 && !sides)) return -1;
+    for (int32_t v = 0; v < n; ++v) bc_out[v] = 0.0;
+    if (nside == 0 || n == 0) return 0;
+    int32_t *rank = malloc((size_t)n * sizeof(int32_t));
+    if (!rank) return -7;
+    for (int32_t v = 0; v < n; ++v) rank[v] = INT32_MAX;
+    for (int64_t i = 0; i < nside; ++i) {
+        if (sides[i] < 0 || sides[i] >= n || rank[sides[i]] != INT32_MAX) {
+            free(rank);
+            return -1;
+        }
+        rank[sides[i]] = (int32_t)i;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > nside) nthreads = (int)nside;
+    side_job *jobs = calloc((size_t)nthreads, sizeof(side_job));
+    pthread_t *tid = calloc((size_t)nthreads, sizeof(pthread_t));
+    double *acc = calloc((size_t)nthreads * (size_t)n, sizeof(double));
+    if (!jobs || !tid || !acc) {
+        free(rank); free(jobs); free(tid); free(acc);
+        return -7;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        side_job *J = &jobs[t];
+        J->row_ptr = row_ptr; J->col = col; J->reach = reach; J->sides = sides; J->rank = rank; J->n = n;
+        J->i0 = nside * t / nthreads;
+        J->i1 = nside * (t + 1) / nthreads;
+        J->acc = acc + (size_t)t * (size_t)n;
+        J->status = -1;
+    }
+    for (int t = 1; t < nthreads; ++t)
+        if (pthread_create(&tid[t], NULL, side_worker, &jobs[t]) != 0) jobs[t].status = -99;
+    side_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t)
+        if (jobs[t].status != -99) pthread_join(tid[t], NULL);
+    int rc = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (jobs[t].status == -99) side_worker(&jobs[t]);
+        if (jobs[t].status != 0) rc = jobs[t].status;
+    }
+    for (int t = 0; t < nthreads; ++t)
+        for (int32_t v = 0; v < n; ++v) bc_out[v] += acc[(size_t)t * (size_t)n + v];
+    free(rank); free(jobs); free(tid); free(acc);
     return rc;
 }

@@ -270,3 +270,69 @@ def test_device_path_golden_file_is_the_oracle():
     stored = np.array([float(x) for x in lines[1:]])
     np.testing.assert_array_equal(stored, oracle.bc_plain(n, rp, col, threads=1))
     assert stored[60] == stored[61] == stored[62] == 0
+
+
+def side_vertices(g):
+    """Vertices of degree 1..4 whose neighbours are pairwise adjacent (side
+    vertices, Section 2), in id order -- detected here independently of the
+    library."""
+    adj = [set(int(x) for x in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]) for v in range(g.n)]
+    return [v for v in range(g.n)
+            if 1 <= len(adj[v]) <= 4 and all(b in adj[a] for a in adj[v] for b in adj[v] if a < b)]
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_bc_side_restores_removed_side_vertices(seed):
+    """Section 3.3.2: Algorithm 2 on a graph with reach equals Algorithm 2 on
+    the graph with its side vertices removed one by one (in id order), plus
+    oracle.bc_side's Algorithm 3 contributions, plus each removed vertex u's
+    own term (reach[u]-1) x (reach of its component left after removing u).
+    Random graphs with many triangles, pendant paths and cliques, random
+    reach; pins bc_side against the pinned bc_weighted."""
+    r = gg.rng(500 + seed)
+    n = int(r.integers(6, 40))
+    g0 = gg.erdos_renyi(n, float(r.uniform(0.05, 0.3)), 600 + seed)
+    # the edge list, then triangles and a small clique hung off random vertices
+    u0, v0 = g0.edges()
+    us, vs = [int(x) for x in u0], [int(x) for x in v0]
+    nxt = n
+    for _ in range(int(r.integers(1, 6))):
+        c = int(r.integers(0, n))
+        us += [c, c, nxt]
+        vs += [nxt, nxt + 1, nxt + 1]
+        nxt += 2
+    if seed % 3 == 0:  # a K4 hung on a vertex: every non-attachment vertex is a side vertex
+        c = int(r.integers(0, n))
+        k = [c, nxt, nxt + 1, nxt + 2]
+        for a in range(4):
+            for b in range(a + 1, 4):
+                us.append(k[a])
+                vs.append(k[b])
+        nxt += 3
+    g = gg.csr_from_edges(nxt, np.array(us, np.int64), np.array(vs, np.int64))
+    reach = r.integers(1, 5, size=g.n).astype(np.int32)
+    S = side_vertices(g)
+    assert S, "no side vertex"
+    want = oracle.bc_weighted(g.n, g.row_ptr, g.col, reach, None, threads=1)
+    keep = np.ones(g.n, bool)
+    keep[S] = False
+    sub, idx = gg.induced_subgraph(g, keep)
+    got = np.zeros(g.n)
+    if sub.n:
+        got[idx] = oracle.bc_weighted(sub.n, sub.row_ptr, sub.col, reach[idx], None, threads=1)
+    got += oracle.bc_side(g.n, g.row_ptr, g.col, reach, np.array(S, np.int32), threads=2)
+    comp = gg.components(g)
+    left = {c: int(reach[comp == c].sum()) for c in np.unique(comp)}
+    for u in S:
+        left[comp[u]] -= int(reach[u])
+        got[u] += (reach[u] - 1) * left[comp[u]]
+    assert_bc_close(got, want, 1e-12, f"seed {seed}")
+
+
+def test_bc_side_threads_agree():
+    g = gg.decorated_random(30, 0.15, 6, 4, 5, 77)
+    S = np.array(side_vertices(g), np.int32)
+    reach = gg.rng(3).integers(1, 4, size=g.n).astype(np.int32)
+    a = oracle.bc_side(g.n, g.row_ptr, g.col, reach, S, threads=1)
+    b = oracle.bc_side(g.n, g.row_ptr, g.col, reach, S, threads=5)
+    np.testing.assert_allclose(a, b, rtol=1e-14)
