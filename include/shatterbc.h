@@ -86,6 +86,8 @@ typedef struct {
   int64_t piece_arcs;       /* sum of piece arc counts (2 x edges) */
   double work_teps;         /* sum over pieces of vertices x edges */
   double ms_degree1, ms_shatter, ms_twins, ms_pack; /* host wall time per stage */
+  int64_t side_vertices;    /* side vertices removed (Section 3.3.2) */
+  int64_t side_pieces;      /* side pieces: blocks whose side vertices run Algorithm 3 */
 } sbc_prep_stats;
 
 /* Statistics of one execution. */
@@ -203,8 +205,11 @@ sbc_status sbc_graph_info(sbc_graph g, int32_t* n, int64_t* arcs);
  * highest-degree vertex (the ordering of Section 4.1, applied per piece after
  * the other steps), 'd' degree-1 vertices (Section 3.3.1), 'a' articulation
  * vertices via biconnected components, bridges included ('b' is accepted as
- * the same step; Sections 3.2.1, 3.2.2, 3.4), 'i' identical vertices
- * (Section 3.3.3).  "" keeps every connected component whole.  st may be NULL.
+ * the same step; Sections 3.2.1, 3.2.2, 3.4), 's' side vertices -- degree 1
+ * to 4, neighbours pairwise adjacent (Sections 3.3.2, 3.4) -- removed one
+ * after another from each piece, each leaving an Algorithm 3 search on the
+ * piece as it was (a side piece), 'i' identical vertices (Section 3.3.3).
+ * "" keeps every connected component whole.  st may be NULL.
  * Errors: SBC_E_INVALID_ARG for an unknown letter, SBC_E_TOO_LARGE. */
 sbc_status sbc_graph_preprocess(sbc_graph g, const char* ops, sbc_prep_stats* st);
 
@@ -222,6 +227,15 @@ sbc_status sbc_graph_export_sizes(sbc_graph g, int64_t* P, int64_t* V, int64_t* 
  * bc[v] = bcx[v] + sum over j in map of (bc'[map_idx[j]] + corr[map_idx[j]]). */
 sbc_status sbc_graph_export(sbc_graph g, int32_t* vtx_off, int32_t* row, int32_t* col, int32_t* reach,
                             int32_t* ident, double* corr, double* bcx, int32_t* map_off, int32_t* map_idx);
+/* nside[P] (host): 0 for a piece of Algorithm 2 (every vertex a source), or
+ * k > 0 for a side piece: a piece as it was before its side vertices were
+ * removed, those being its local ids 0..k-1 in removal order; its only
+ * sources are those k vertices, and source i runs Algorithm 3 (Section
+ * 3.3.2) on the piece without side vertices 0..i-1, adding
+ * reach[i]*delta[w] + reach[i]*(delta[w] - (reach[w]-1)) to every other
+ * vertex w still there.  Its bc' enters Eq. (5) like any piece's.
+ * Errors: SBC_E_INVALID_ARG (NULL, or not preprocessed). */
+sbc_status sbc_graph_export_side(sbc_graph g, int32_t* nside);
 
 /* ------------------------------------------------------------------- plan */
 

@@ -57,7 +57,8 @@ class PrepStats(ctypes.Structure):
         "n", "m", "components", "stripped", "blocks", "bridges", "twin_classes", "twins_merged",
         "tiny_pieces", "pieces", "piece_vertices", "piece_arcs")] + [
         ("work_teps", ctypes.c_double), ("ms_degree1", ctypes.c_double), ("ms_shatter", ctypes.c_double),
-        ("ms_twins", ctypes.c_double), ("ms_pack", ctypes.c_double)]
+        ("ms_twins", ctypes.c_double), ("ms_pack", ctypes.c_double), ("side_vertices", ctypes.c_int64),
+        ("side_pieces", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +110,7 @@ _SIGS = {
     "sbc_graph_preprocess": ([_vp, ctypes.c_char_p, ctypes.POINTER(PrepStats)], ctypes.c_int32),
     "sbc_graph_export_sizes": ([_vp, _i64p, _i64p, _i64p, _i64p], ctypes.c_int32),
     "sbc_graph_export": ([_vp, _i32p, _i32p, _i32p, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p], ctypes.c_int32),
+    "sbc_graph_export_side": ([_vp, _i32p], ctypes.c_int32),
     "sbc_plan_create": ([_vp, _vp, ctypes.c_uint32, ctypes.POINTER(_vp)], ctypes.c_int32),
     "sbc_plan_destroy": ([_vp], ctypes.c_int32),
     "sbc_plan_execute": ([_vp, _vp, _vp], ctypes.c_int32),
@@ -250,6 +252,9 @@ def sbc_graph_export(g) -> dict:
     p = {k: v.ctypes.data_as(_f64p if v.dtype == np.float64 else _i32p) for k, v in out.items()}
     _check(lib().sbc_graph_export(g, p["vtx_off"], p["row"], p["col"], p["reach"], p["ident"], p["corr"], p["bcx"],
                                   p["map_off"], p["map_idx"]))
+    nside = np.zeros(max(P.value, 1), np.int32)
+    _check(lib().sbc_graph_export_side(g, nside.ctypes.data_as(_i32p)))
+    out["nside"] = nside[:P.value]
     out["col"] = out["col"][:A.value]
     for k in ("reach", "ident", "corr"):
         out[k] = out[k][:V.value]

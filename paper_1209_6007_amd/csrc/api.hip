@@ -223,6 +223,8 @@ sbc_status sbc_graph_preprocess(sbc_graph g, const char* ops, sbc_prep_stats* st
     s.ms_shatter = ps.ms_shatter;
     s.ms_twins = ps.ms_twins;
     s.ms_pack = ps.ms_pack;
+    s.side_vertices = ps.side_vertices;
+    s.side_pieces = ps.side_pieces;
     g->stats = s;
     if (st) *st = s;
     return SBC_OK;
@@ -256,6 +258,14 @@ sbc_status sbc_graph_export(sbc_graph g, int32_t* vtx_off, int32_t* row, int32_t
   cp(bcx, p.bcx);
   cp(map_off, p.map_off);
   cp(map_idx, p.map_idx);
+  return SBC_OK;
+}
+
+sbc_status sbc_graph_export_side(sbc_graph g, int32_t* nside) {
+  if (!g || !nside) return fail(SBC_E_INVALID_ARG, "NULL argument");
+  if (!g->prepared) return fail(SBC_E_INVALID_ARG, "graph has not been preprocessed");
+  const Prepared& p = g->prep;
+  for (int32_t i = 0; i < p.pieces(); ++i) nside[i] = i < (int32_t)p.nside.size() ? p.nside[i] : 0;
   return SBC_OK;
 }
 

@@ -34,6 +34,10 @@ struct DevPieces {
   const int32_t* reach;      // may be null when no piece uses reach
   const int32_t* ident;      // may be null when no piece uses ident
   const int32_t* src_order;  // per piece, local source order
+  // per piece: 0, or k > 0 for a side piece (sources: its side vertices
+  // 0..k-1, each running Algorithm 3 without the side vertices before it);
+  // null when no piece is a side piece
+  const int32_t* nside;
   double* bcp;               // accumulated bc' per piece vertex
   int32_t npieces;           // P: entries of vtx_off are P+1
   int32_t nverts;            // V: entries of row are V+1

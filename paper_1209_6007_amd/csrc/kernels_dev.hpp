@@ -554,20 +554,36 @@ __device__ __forceinline__ BackEarly back_early(const double* __restrict__ sg, c
   return r;
 }
 
+// A lane's contribution of delta dv at vertex v to bc'.  In a side piece
+// (srank >= 0: the lane's source, a side vertex, whose id is its removal
+// rank) it is Algorithm 3's reach[s]*(delta + (delta - (reach[v]-1))), and a
+// side vertex removed before the source (v < srank) is absent from the
+// source's graph: it adds nothing and passes nothing back (coefficient 0).
+// It is never on a shortest path between other vertices, so the forward
+// sweep needs no change.
+__device__ __forceinline__ bool side_absent(int32_t v, int32_t srank) { return v < srank; }
+__device__ __forceinline__ double side_contrib(double wsrc, double dv, double rm1, int32_t srank) {
+  return srank >= 0 ? wsrc * (2.0 * dv - rm1) : wsrc * dv;
+}
+
 // Backward finish of entry (v, level) with lanes amask and pulled sum acc:
 // delta (Eq. (3) in pull form), the coefficient that replaces sigma, the
 // wave's contribution to bc'[v] (weighted by ident[s]*reach[s] in wsrc) and
 // the level's backward mask.  drow, when not null, is the lane's row of the
-// dependency dump.
+// dependency dump; srank is the lane's side rank (-1 outside side pieces).
 __device__ __forceinline__ void back_finish(double* __restrict__ sg, double* __restrict__ bcp,
                                             uint64_t* __restrict__ bw, int32_t v, uint64_t amask, double acc,
                                             const BackEarly& pre, double wsrc, int lane, int32_t* flags,
-                                            double* drow) {
+                                            double* drow, int32_t srank) {
   double contrib = 0.0;
   if ((amask >> lane) & 1) {
     const double dv = pre.rm1 + pre.sv * acc;
-    sg[(size_t)v * 64 + lane] = pre.id * (1.0 + dv) / pre.sv;
-    contrib = wsrc * dv;
+    if (side_absent(v, srank)) {
+      sg[(size_t)v * 64 + lane] = 0.0;
+    } else {
+      sg[(size_t)v * 64 + lane] = pre.id * (1.0 + dv) / pre.sv;
+      contrib = side_contrib(wsrc, dv, pre.rm1, srank);
+    }
     if (drow) drow[v] = dv;
     if (!(pre.sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, kFlagSigmaOverflow);
   }
@@ -597,6 +613,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
   __shared__ int s_poff[BLOCK];
   __shared__ double s_pacc[BLOCK];
   __shared__ double s_wsrc[64];  // ident[s]*reach[s] of lane s's source (pair path)
+  __shared__ int32_t s_srank[64];  // side rank of lane s's source, -1 outside side pieces (pair path)
   __shared__ int s_nheavy, s_nslices;
   __shared__ int s_heavy[kHeavyMax];
   __shared__ int s_hoff[kHeavyMax];
@@ -665,6 +682,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       continue;
     }
     double wsrc = 0.0;
+    const bool side_item = P.nside && P.nside[W.piece] > 0;
+    const int32_t srank = (side_item && lane < nsrc) ? s : -1;  // Algorithm 3 items: the source's removal rank
     if (lane < nsrc) {
       wsrc = 1.0;
       if (REACH) wsrc *= (double)rch[s];
@@ -677,7 +696,10 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         sg[(size_t)s * 64 + lane] = 1.0;
       }
     }
-    if (wave == 0) s_wsrc[lane] = wsrc;
+    if (wave == 0) {
+      s_wsrc[lane] = wsrc;
+      s_srank[lane] = srank;
+    }
     if (tid == 0) {
       lvl[0] = 0;
       lvl[1] = nsrc;
@@ -908,7 +930,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         return back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
       };
       auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, const BackEarly& pre) {
-        back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
+        back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
       };
       // Pair (v, lane j): the dependency of v for source j from the
       // coefficients of its neighbours on level l+1 (Eq. (3) in pull form),
@@ -920,8 +942,13 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         const double id = IDENT ? (double)idn[v] : 1.0;
         const double acc = pair_sum<1>(col, e0, e1, np, br, sg, idn, false, j, Q.flags);
         const double dv = rm1 + sv * acc;
-        sg[(size_t)v * 64 + j] = id * (1.0 + dv) / sv;
-        atomicAdd(&s_pacc[wave * 64 + k], s_wsrc[j] * dv);  // LDS (the array, not the slot pointer)
+        const int32_t sr = s_srank[j];
+        if (side_absent(v, sr)) {
+          sg[(size_t)v * 64 + j] = 0.0;
+        } else {
+          sg[(size_t)v * 64 + j] = id * (1.0 + dv) / sv;
+          atomicAdd(&s_pacc[wave * 64 + k], side_contrib(s_wsrc[j], dv, rm1, sr));  // LDS (the array itself)
+        }
         if constexpr (DUMP) dump.delta[(size_t)(W.s0 + j) * dump.np + v] = dv;
         if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
       };
@@ -963,7 +990,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
-          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
+          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
         }
         __syncthreads();
         mark(kProfBackHeavy);
@@ -1197,6 +1224,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       continue;
     }
     double wsrc = 0.0;
+    const int32_t srank = (P.nside && P.nside[W.piece] > 0 && lane < nsrc) ? s : -1;  // Algorithm 3 items
     if (lane < nsrc) {
       wsrc = 1.0;
       if (REACH) wsrc *= (double)rch[s];
@@ -1516,7 +1544,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       auto early_b = [](int, int32_t, uint64_t) { return 0; };
       auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, int) {
         back_finish(sg, bcp, bw, v, amask, acc, back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane), wsrc, lane,
-                    Q.flags, drow);
+                    Q.flags, drow, srank);
       };
       grabbed(hs, b, e, [&](int i0, int i1) {
         pull_entries<kGroup>(i0, i1, q, rowp, np, narcs, col, br, sg, idn, false, lane, Q.flags, need_b, defer_b,
@@ -1558,7 +1586,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
           const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(hv_off[h] + sl) * 64 + lane];
-          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow);
+          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
         }
         if (!team_sync(kProfBackHeavy)) {
           alive = false;
@@ -1712,6 +1740,7 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
         continue;
       }
       const double wsrc = (REACH ? (double)s_rch[s] : 1.0) * (IDENT ? (double)s_idn[s] : 1.0);
+      const int32_t srank = (P.nside && P.nside[W.piece] > 0) ? s : -1;  // Algorithm 3 items
       if (lane == 0) {
         d[s] = 0;
         sig[s] = 1.0;
@@ -1802,9 +1831,14 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
             if (d[w] == l + 1) acc += sig[w];
           }
           const double sv = sig[v];
-          const double dv = (REACH ? (double)(s_rch[v] - 1) : 0.0) + sv * acc;
-          sig[v] = (IDENT ? (double)s_idn[v] : 1.0) * (1.0 + dv) / sv;
-          atomicAdd(&s_bc[v], wsrc * dv);
+          const double rm1 = REACH ? (double)(s_rch[v] - 1) : 0.0;
+          const double dv = rm1 + sv * acc;
+          if (side_absent(v, srank)) {
+            sig[v] = 0.0;
+          } else {
+            sig[v] = (IDENT ? (double)s_idn[v] : 1.0) * (1.0 + dv) / sv;
+            atomicAdd(&s_bc[v], side_contrib(wsrc, dv, rm1, srank));
+          }
           if constexpr (DUMP) drow[v] = dv;
           if (!(sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(Q.flags, kFlagSigmaOverflow);
         }

@@ -149,7 +149,7 @@ extern "C" sbc_status sbc_piece_bc_noalloc(sbc_context ctx, int32_t n, int32_t a
   for (uint64_t* p : {ms.vis, ms.fa, ms.fb, ms.ba, ms.bb})
     if ((e = launch_fill_u64(p, 0, (int64_t)g * stride, s)) != hipSuccess) return hip_fail(e, "fill masks");
   if ((e = launch_fill_f64(bc_dev, 0.0, n, s)) != hipSuccess) return hip_fail(e, "fill output");
-  DevPieces dp{vtx_off, row_ptr_dev, col_dev, reach_dev, ident_dev, src_order, bc_dev, 1, n, arcs, 0};
+  DevPieces dp{vtx_off, row_ptr_dev, col_dev, reach_dev, ident_dev, src_order, nullptr, bc_dev, 1, n, arcs, 0};
   QueueArgs qa{items, nitems, kArgMagic, &ctl->head, &ctl->flags, &ctl->done};
   e = launch_ms(dp, qa, reach_dev != nullptr, ident_dev != nullptr, waves, eu, (int)g, ms, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "launch traversal");

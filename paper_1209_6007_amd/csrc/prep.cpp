@@ -123,6 +123,7 @@ void plain_problem(const HostGraph& g, Prepared* P) {
   std::iota(P->map_idx.begin(), P->map_idx.end(), 0);
   P->src_order.resize(g.n);
   std::iota(P->src_order.begin(), P->src_order.end(), 0);
+  P->nside.assign(1, 0);
 }
 
 namespace {
@@ -142,19 +143,100 @@ struct OutPiece {
   std::vector<double> corr;
   std::vector<int32_t> member_orig;  // original id of each member
   std::vector<int32_t> member_cls;   // quotient vertex of each member
+  int32_t nside = 0;                 // side piece: its side vertices are local 0..nside-1
 };
 
 struct Builder {
   const HostGraph& g;
-  bool opi;
+  bool opi, op_side;
   std::vector<double>& bcx;
   PrepStats* st;
   std::vector<OutPiece> out;
   std::vector<int32_t> loc;  // scratch: original id -> local id, -1 otherwise
   double ms_twins = 0;
 
-  Builder(const HostGraph& g_, bool opi_, std::vector<double>& bcx_, PrepStats* st_)
-      : g(g_), opi(opi_), bcx(bcx_), st(st_), loc(g_.n, -1) {}
+  Builder(const HostGraph& g_, bool opi_, bool side_, std::vector<double>& bcx_, PrepStats* st_)
+      : g(g_), opi(opi_), op_side(side_), bcx(bcx_), st(st_), loc(g_.n, -1) {}
+
+  // Side vertices (Section 3.3.2): vertices of degree 1..4 whose neighbours
+  // are pairwise adjacent, so that no shortest path between two other
+  // vertices passes through them.  They are removed one after another in
+  // local id order (each stays a side vertex when earlier ones go, since a
+  // clique minus a vertex is a clique), and at least one vertex stays.  The
+  // block as it was goes out as a side piece with the side vertices first,
+  // in removal order; each removed vertex u gets its own dependency term
+  // (reach[u]-1) x (the reach left in the component after removing it) on
+  // the host; the piece continues without them.
+  void strip_side_vertices(RawPiece& p) {
+    const int32_t np = (int32_t)p.verts.size();
+    if (np < 3) return;
+    auto adjacent = [&](int32_t a, int32_t b) {
+      return std::binary_search(p.cl.begin() + p.rp[a], p.cl.begin() + p.rp[a + 1], b);
+    };
+    std::vector<int32_t> side;
+    for (int32_t v = 0; v < np; ++v) {
+      const int32_t k = p.rp[v + 1] - p.rp[v];
+      if (k < 1 || k > 4) continue;
+      bool clique = true;
+      for (int32_t i = p.rp[v]; i < p.rp[v + 1] && clique; ++i)
+        for (int32_t j = i + 1; j < p.rp[v + 1] && clique; ++j) clique = adjacent(p.cl[i], p.cl[j]);
+      if (clique) side.push_back(v);
+    }
+    if ((int32_t)side.size() == np) side.pop_back();
+    if (side.empty()) return;
+    const int32_t ns = (int32_t)side.size();
+    // the side piece: side vertices first, then the rest in local order
+    std::vector<int32_t> nid(np, -1), old_of(np);
+    for (int32_t i = 0; i < ns; ++i) nid[side[i]] = i;
+    int32_t nxt = ns;
+    for (int32_t v = 0; v < np; ++v)
+      if (nid[v] < 0) nid[v] = nxt++;
+    for (int32_t v = 0; v < np; ++v) old_of[nid[v]] = v;
+    OutPiece q;
+    q.rp.assign(np + 1, 0);
+    for (int32_t i = 0; i < np; ++i) {
+      const int32_t v = old_of[i];
+      for (int32_t e = p.rp[v]; e < p.rp[v + 1]; ++e) q.cl.push_back(nid[p.cl[e]]);
+      std::sort(q.cl.begin() + q.rp[i], q.cl.end());
+      q.rp[i + 1] = (int32_t)q.cl.size();
+      q.reach.push_back((int32_t)p.reach[v]);
+      q.member_orig.push_back(p.verts[v]);
+    }
+    q.ident.assign(np, 1);
+    q.corr.assign(np, 0.0);
+    q.member_cls.resize(np);
+    std::iota(q.member_cls.begin(), q.member_cls.end(), 0);
+    q.nside = ns;
+    // each removed vertex's own term, with the reach left after removing it
+    int64_t left = 0;
+    for (int32_t v = 0; v < np; ++v) left += p.reach[v];
+    for (int32_t u : side) {
+      left -= p.reach[u];
+      bcx[p.verts[u]] += (double)(p.reach[u] - 1) * (double)left;
+    }
+    out.push_back(std::move(q));
+    st->side_vertices += ns;
+    st->side_pieces++;
+    // the block without its side vertices
+    std::vector<uint8_t> gone(np, 0);
+    for (int32_t u : side) gone[u] = 1;
+    RawPiece r;
+    std::vector<int32_t> rid(np, -1);
+    for (int32_t v = 0; v < np; ++v)
+      if (!gone[v]) {
+        rid[v] = (int32_t)r.verts.size();
+        r.verts.push_back(p.verts[v]);
+        r.reach.push_back(p.reach[v]);
+      }
+    r.rp.assign(r.verts.size() + 1, 0);
+    for (int32_t v = 0; v < np; ++v) {
+      if (gone[v]) continue;
+      for (int32_t e = p.rp[v]; e < p.rp[v + 1]; ++e)
+        if (!gone[p.cl[e]]) r.cl.push_back(rid[p.cl[e]]);  // rows stay sorted: rid keeps the order
+      r.rp[rid[v] + 1] = (int32_t)r.cl.size();
+    }
+    p = std::move(r);
+  }
 
   // Local CSR of the piece from an edge list of original ids.
   void build_local(RawPiece& p, const std::vector<int32_t>& eu, const std::vector<int32_t>& ev) {
@@ -186,6 +268,7 @@ struct Builder {
   //       paths evenly over the D members of its neighbour classes.
   // Only members with equal reach are merged.
   void finish_piece(RawPiece& p) {
+    if (op_side) strip_side_vertices(p);
     const int32_t np = (int32_t)p.verts.size();
     std::vector<int32_t> cls(np);
     std::vector<int8_t> ctype;  // per class: 0 singleton, 1 open, 2 closed neighbourhood
@@ -355,14 +438,15 @@ struct Builder {
 }  // namespace
 
 int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStats* st, std::string* why) {
-  bool opd = false, opa = false, opi = false, opo = false;
+  bool opd = false, opa = false, opi = false, opo = false, op_side = false;
   for (char c : ops) {
     if (c == 'o') opo = true;
     else if (c == 'd') opd = true;
     else if (c == 'a' || c == 'b') opa = true;
     else if (c == 'i') opi = true;
+    else if (c == 's') op_side = true;
     else {
-      *why = std::string("unknown preprocessing letter '") + c + "' (known: o, d, a, b, i)";
+      *why = std::string("unknown preprocessing letter '") + c + "' (known: o, d, a, b, s, i)";
       return SBC_E_INVALID_ARG;
     }
   }
@@ -438,7 +522,7 @@ int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStat
   double t1 = now_ms();
   st->ms_degree1 = t1 - t0;
 
-  Builder B(g, opi, bcx, st);
+  Builder B(g, opi, op_side, bcx, st);
   std::vector<int32_t> eu, ev;
 
   if (opa) {
@@ -610,10 +694,11 @@ int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStat
     for (size_t i = 0; i < q.member_orig.size(); ++i)
       Q.map_idx[fill[q.member_orig[i]]++] = base + q.member_cls[i];
     Q.vtx_off.push_back(base + C);
+    Q.nside.push_back(q.nside);
     st->pieces++;
     st->piece_vertices += C;
     st->piece_arcs += (int64_t)q.cl.size();
-    st->work_teps += (double)C * (double)q.cl.size() * 0.5;
+    st->work_teps += (double)(q.nside > 0 ? q.nside : C) * (double)q.cl.size() * 0.5;
     for (int32_t c = 0; c < C; ++c) {
       if (q.reach[c] > 1) Q.weighted = true;
       if (q.ident[c] > 1) Q.has_ident = true;
@@ -641,6 +726,11 @@ void order_pieces(Prepared* P) {
     const int32_t vb = P->vtx_off[p], np = P->vtx_off[p + 1] - vb;
     order.clear();
     seen.assign(np, 0);
+    if (!P->nside.empty() && P->nside[p] > 0) {
+      // a side piece keeps its ids: its side vertices are 0..nside-1 in removal order
+      for (int32_t v = 0; v < np; ++v) order.push_back(v);
+      std::fill(seen.begin(), seen.end(), 1);
+    }
     int32_t start = 0;
     for (int32_t v = 1; v < np; ++v)
       if (P->row[vb + v + 1] - P->row[vb + v] > P->row[vb + start + 1] - P->row[vb + start]) start = v;
@@ -701,6 +791,10 @@ void cluster_sources(Prepared* P, int group, int mode) {
   std::vector<int32_t> mark;
   for (int32_t p = 0; p < np_total; ++p) {
     const int32_t vb = P->vtx_off[p], np = P->vtx_off[p + 1] - vb;
+    if (!P->nside.empty() && P->nside[p] > 0) {  // side piece: its sources are 0..nside-1
+      for (int32_t v = 0; v < np; ++v) P->src_order[vb + v] = v;
+      continue;
+    }
     used.assign(np, 0);
     mark.assign(np, -1);
     int32_t out = 0;

@@ -33,6 +33,8 @@ struct PrepStats {
   int64_t twin_classes = 0;    // classes with >= 2 members
   int64_t twins_merged = 0;    // vertices removed by merging (sum of k-1)
   int64_t tiny_pieces = 0;     // pieces of <= 2 vertices after merging, closed in form
+  int64_t side_vertices = 0;   // side vertices removed (Section 3.3.2)
+  int64_t side_pieces = 0;     // pieces that carry Algorithm 3 searches
   int64_t pieces = 0;          // pieces left for the device
   int64_t piece_vertices = 0;  // sum of n_p over device pieces
   int64_t piece_arcs = 0;      // sum of arcs over device pieces
@@ -57,14 +59,20 @@ struct Prepared {
   std::vector<int32_t> map_off;  // n+1: original v maps to piece vertices map_idx[map_off[v]..]
   std::vector<int32_t> map_idx;  // global piece vertex ids
   std::vector<int32_t> src_order;  // V: per piece, local source order (clustered for batching)
+  // Per piece: 0 for a piece of Algorithm 2, or k > 0 for a side piece -- a
+  // block as it was before its k side vertices were removed, those vertices
+  // being local ids 0..k-1 in removal order; its only sources are those k
+  // vertices, each running Algorithm 3 with the vertices removed before it
+  // left out (Section 3.3.2).
+  std::vector<int32_t> nside;
   int32_t pieces() const { return vtx_off.empty() ? 0 : (int32_t)vtx_off.size() - 1; }
   int64_t V() const { return vtx_off.empty() ? 0 : vtx_off.back(); }
   int64_t A() const { return col.size(); }
 };
 
 // ops: any of 'd' (degree-1), 'a' (articulation / biconnected shattering),
-// 'i' (identical vertices), applied in that order.  "" keeps each connected
-// component whole.
+// 's' (side vertices), 'i' (identical vertices), applied in that order.  ""
+// keeps each connected component whole.
 int preprocess(const HostGraph& g, const std::string& ops, Prepared* out, PrepStats* st, std::string* why);
 
 // The plain problem: the whole graph as one piece, no attributes.

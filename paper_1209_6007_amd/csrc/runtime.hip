@@ -96,7 +96,8 @@ Plan::~Plan() {
 size_t Plan::device_bytes() const {
   size_t t = 0;
   for (const DevBuf* b : {&d_vtx_off, &d_row, &d_col, &d_reach, &d_ident, &d_src, &d_bcp, &d_corr, &d_bcx,
-                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &d_area_base, &d_piece_items, &d_item_out, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
+                          &d_map_off, &d_map_idx, &d_out, &d_ctl, &d_area_base, &d_piece_items, &d_item_out,
+                          &d_nside, &tm_sg, &tm_q, &tm_qm, &tm_vis, &tm_fa, &tm_fb,
                           &tm_fc, &tm_ba, &tm_bb, &tm_bc, &tm_lvl, &tm_part, &tm_prof, &tm_ctl, &tm_heavy, &dump_dist,
                           &dump_sigma, &dump_delta})
     t += b->bytes;
@@ -303,6 +304,8 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     piece_class[p] = k;
     int32_t nsrc = np;
     if (opt.sources) nsrc = (int32_t)opt.nsrc;
+    const bool side_piece = p < (int32_t)prob.nside.size() && prob.nside[p] > 0;
+    if (side_piece) nsrc = prob.nside[p];  // Algorithm 3: only the side vertices are sources
     if (nsrc <= 0) continue;
     const int32_t chunk = k == KC_WAVE ? (int32_t)std::min<int64_t>(64, pr.wave_sources_per_item) : 64;
     const double per = 8.0 * arcs + (plain ? 48.0 : (reach || ident ? 56.0 : 48.0)) * np;
@@ -364,6 +367,9 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   if (reach && (e = upload(d_reach, prob.reach)) != hipSuccess) return hip_fail(e, "upload reach");
   if (ident && (e = upload(d_ident, prob.ident)) != hipSuccess) return hip_fail(e, "upload ident");
   if ((e = upload(d_src, prob.src_order)) != hipSuccess) return hip_fail(e, "upload src_order");
+  has_side = false;
+  for (int32_t x : prob.nside) has_side = has_side || x > 0;
+  if (has_side && (e = upload(d_nside, prob.nside)) != hipSuccess) return hip_fail(e, "upload nside");
   if ((e = d_bcp.alloc(std::max<int64_t>(V, 1) * sizeof(double))) != hipSuccess) return hip_fail(e, "alloc bcp");
   has_map = !plain;
   nmap = (int32_t)prob.map_idx.size();
@@ -573,7 +579,8 @@ sbc_status Plan::enqueue(double* out, hipStream_t s) {
       return hip_fail(e, "fill prof");
   }
   DevPieces dp{d_vtx_off.as<int32_t>(), d_row.as<int32_t>(), d_col.as<int32_t>(), d_reach.as<int32_t>(),
-               d_ident.as<int32_t>(), d_src.as<int32_t>(), d_bcp.as<double>(), P, (int32_t)V, (int32_t)A, 0};
+               d_ident.as<int32_t>(), d_src.as<int32_t>(), has_side ? d_nside.as<int32_t>() : nullptr,
+               d_bcp.as<double>(), P, (int32_t)V, (int32_t)A, 0};
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
   // Largest classes first so the long multi-source items start early.  The
   // team kernel occupies the whole device, so the other classes follow it.

@@ -115,6 +115,8 @@ struct Plan {
   int32_t nmap = 0;         // entries of map_idx
   // device problem
   DevBuf d_vtx_off, d_row, d_col, d_reach, d_ident, d_src, d_bcp, d_corr, d_bcx, d_map_off, d_map_idx, d_out;
+  DevBuf d_nside;           // per piece: side vertices of a side piece (Algorithm 3), when any piece has them
+  bool has_side = false;
   DevBuf d_items[KC_COUNT];
   // deterministic runs: per-item bc' areas (see QueueArgs::item_base)
   bool det = false;

@@ -110,6 +110,13 @@ def main(which):
                 sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", 256)
                 sbc.sbc_context_set_param(ctx.h, "batch_pairs", 16)
                 sbc.sbc_context_set_param(ctx.h, "deep_min_levels", 64)
+                # side vertices (Algorithm 3 items) on every kernel class
+                for ops in ("odasi", "dasi"):
+                    for wave_max in (256, 0):
+                        sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", wave_max)
+                        assert_bc_close(sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ops=ops, ctx=ctx),
+                                        want, 1e-9, f"{name}/{ops}/wave_max={wave_max}")
+                sbc.sbc_context_set_param(ctx.h, "wave_max_vertices", 256)
                 # deterministic mode: per-item areas, the same bits twice
                 d1 = sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed+deterministic", ops="odai", ctx=ctx)
                 d2 = sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed+deterministic", ops="odai", ctx=ctx)
@@ -176,6 +183,8 @@ def main(which):
                         for mode in ("plain", "compressed"):
                             got = sbc.betweenness(g.n, g.row_ptr, g.col, mode=mode, ctx=tctx)
                             assert_bc_close(got, want, 1e-9, f"team {name}/{mode} teams={tc}")
+                        got = sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ops="odasi", ctx=tctx)
+                        assert_bc_close(got, want, 1e-9, f"team {name}/odasi teams={tc}")
                 print(f"   teams={tc} slots={slots} ok", flush=True)
                 tctx.close()
         check("team kernel", team)

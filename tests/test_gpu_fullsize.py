@@ -27,8 +27,14 @@ def ctx():
     c.close()
 
 
+_ORACLE = {}
+
+
 def oracle_in_chunks(g, label, chunks=8):
-    """Algorithm 1 over all sources, in source chunks with a progress line each."""
+    """Algorithm 1 over all sources, in source chunks with a progress line
+    each (kept per label for the other tests of the module)."""
+    if label in _ORACLE:
+        return _ORACLE[label]
     out = np.zeros(g.n)
     bounds = np.linspace(0, g.n, chunks + 1).astype(np.int64)
     for c in range(chunks):
@@ -36,6 +42,7 @@ def oracle_in_chunks(g, label, chunks=8):
         src = np.arange(bounds[c], bounds[c + 1], dtype=np.int32)
         out += oracle.bc_plain(g.n, g.row_ptr, g.col, sources=src)
         print(f"{label}: oracle chunk {c + 1}/{chunks} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    _ORACLE[label] = out
     return out
 
 
@@ -60,6 +67,18 @@ def test_rmat17_compressed_vs_oracle(ctx):
     _, got, st = bench_run(ctx, g)
     print(f"rmat17 n={g.n} m={g.m} compressed run {st['ms_device']:.1f} ms", flush=True)
     assert_bc_close(got, oracle_in_chunks(g, "rmat17"), RTOL, "rmat17 compressed vs oracle")
+
+
+def test_rmat17_side_vertices_vs_oracle(ctx):
+    """The same with side vertices removed ("odasi": Algorithm 3 items on the
+    side pieces beside Algorithm 2 on the rest), and in deterministic mode."""
+    g = gg.rmat_decorated()
+    want = oracle_in_chunks(g, "rmat17")
+    G, got, st = bench_run(ctx, g, "odasi")
+    print(f"rmat17 odasi run {st['ms_device']:.1f} ms, items {st['items_class']}", flush=True)
+    assert_bc_close(got, want, RTOL, "rmat17 odasi vs oracle")
+    det = sbc.sbc_betweenness(ctx.h, G.h, sbc.SBC_COMPRESSED | sbc.SBC_DETERMINISTIC)
+    assert_bc_close(det, want, RTOL, "rmat17 odasi deterministic vs oracle")
 
 
 def test_grid512_compressed_vs_oracle(ctx):

@@ -23,11 +23,11 @@ def ctx():
     c.close()
 
 
-def run(ctx, g, mode):
+def run(ctx, g, mode, ops="dai"):
     h = sbc.sbc_graph_create(g.n, g.row_ptr, g.col)
     try:
         if mode.startswith("compressed"):
-            sbc.sbc_graph_preprocess(h, "dai")
+            sbc.sbc_graph_preprocess(h, ops)
         return sbc.sbc_betweenness(ctx.h, h, sbc._mode(mode))
     finally:
         sbc.sbc_graph_destroy(h)
@@ -65,6 +65,25 @@ def test_single_source_state(ctx, seed):
             np.testing.assert_array_equal(sg, osg)
             m = (od > 0)
             np.testing.assert_allclose(dl[m], odl[m], rtol=RTOL, atol=0)
+
+
+def test_side_pieces_on_every_kernel(ctx):
+    """Algorithm 3 items (side pieces) forced onto each kernel class: the
+    small-piece kernel, the batch kernel (with and without pairs), the deep
+    launch and the team kernel."""
+    graphs = [gg.rmat_decorated(scale=10, seed=71), gg.decorated_random(120, 0.05, 20, 10, 25, 72),
+              gg.decorated_random(400, 0.006, 30, 10, 40, 74)]
+    for g in graphs:
+        want = oracle.bc(g)
+        G = sbc.Graph(g.n, g.row_ptr, g.col)
+        st = G.preprocess("odasi")
+        assert st["side_pieces"] > 0, st
+        for params in ({}, {"wave_max_vertices": 0}, {"wave_max_vertices": 0, "batch_pairs": 0},
+                       {"wave_max_vertices": 0, "deep_min_levels": 2}, {"team_min_vertices": 3, "team_count": 16}):
+            c = sbc.Context(0, params)
+            got = sbc.sbc_betweenness(c.h, G.h, sbc.SBC_COMPRESSED)
+            c.close()
+            assert_bc_close(got, want, RTOL, f"n={g.n} {params}")
 
 
 STATE_CASES = {
@@ -148,12 +167,14 @@ SMALL = {
 
 
 @pytest.mark.parametrize("name", list(SMALL))
-@pytest.mark.parametrize("mode", ["plain", "compressed"])
+@pytest.mark.parametrize("mode", ["plain", "compressed", "compressed-side"])
 def test_whole_graph(ctx, name, mode):
+    """Plain, compressed ("dai") and compressed with side vertices ("odasi":
+    Algorithm 3 items beside Algorithm 2 items) against the oracle."""
     g = SMALL[name]()
     print(f"graph {name} n={g.n} m={g.m} mode={mode}", flush=True)
     want = oracle.bc(g)
-    got = run(ctx, g, mode)
+    got = run(ctx, g, "compressed", "odasi") if mode == "compressed-side" else run(ctx, g, mode)
     assert_bc_close(got, want, RTOL, f"{name}/{mode}")
 
 
@@ -205,6 +226,8 @@ def test_decorated_random(ctx, seed):
     want = oracle.bc(g)
     for mode in ("plain", "compressed"):
         assert_bc_close(run(ctx, g, mode), want, RTOL, f"seed={seed}/{mode}")
+    assert_bc_close(run(ctx, g, "compressed", "odasi"), want, RTOL, f"seed={seed}/odasi")
+    assert_bc_close(run(ctx, g, "compressed+deterministic", "odasi"), want, RTOL, f"seed={seed}/odasi deterministic")
 
 
 def test_source_subset(ctx):

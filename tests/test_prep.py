@@ -18,7 +18,7 @@ import paper_1209_6007_amd as sbc
 from tests.helpers import assert_bc_close, map_back
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-OPS = ["", "d", "a", "i", "da", "di", "ai", "dai", "o", "odai"]
+OPS = ["", "d", "a", "i", "da", "di", "ai", "dai", "o", "odai", "s", "ds", "as", "si", "dasi", "odasi"]
 
 
 def setup_module(_m):
@@ -115,13 +115,18 @@ def compressed_via_oracle(g, ops, check_invariants=True):
         cl = ex["col"][ex["row"][vb]:ex["row"][ve]]
         assert np_ >= 3
         assert cl.min() >= 0 and cl.max() < np_
-        bcp[vb:ve] = oracle.bc_weighted(np_, rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve], threads=2)
+        k = int(ex["nside"][p])
+        if k > 0:  # a side piece: Algorithm 3 for its side vertices 0..k-1, in that order
+            assert "s" in ops and np.all(ex["ident"][vb:ve] == 1)
+            bcp[vb:ve] = oracle.bc_side(np_, rp, cl, ex["reach"][vb:ve], np.arange(k, dtype=np.int32), threads=2)
+        else:
+            bcp[vb:ve] = oracle.bc_weighted(np_, rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve], threads=2)
     out = ex["bcx"].copy()
     for v in range(g.n):
         for j in range(ex["map_off"][v], ex["map_off"][v + 1]):
             x = ex["map_idx"][j]
             out[v] += bcp[x] + ex["corr"][x]
-    if check_invariants and len(ex["vtx_off"]) > 1:
+    if check_invariants and len(ex["vtx_off"]) > 1 and "s" not in ops:
         # every piece represents its whole component: sum of reach*ident = component size
         owner = {}
         for v in range(g.n):
@@ -139,7 +144,7 @@ def compressed_via_oracle(g, ops, check_invariants=True):
 def test_exhaustive_six_vertex_graphs_every_ops(ops):
     """Every labelled graph on 6 vertices (sampled 1 in 4 for the full sweep)."""
     pairs = [(i, j) for i in range(6) for j in range(i + 1, 6)]
-    step = 1 if ops == "dai" else 4
+    step = 1 if ops in ("dai", "dasi") else 4
     for mask in range(0, 1 << 15, step):
         es = [pairs[b] for b in range(15) if (mask >> b) & 1]
         u = np.array([e[0] for e in es], dtype=np.int64)
@@ -174,6 +179,21 @@ def test_worked_examples_twins_with_reach():
     assert st["pieces"] == 0                    # the triangle collapses to one class
 
 
+def test_side_vertices_removed_with_algorithm3():
+    """Side vertices (Section 3.3.2): a block with triangles and a K4 hung on
+    it; 's' removes the side vertices, exports one side piece per block that
+    had them (its side vertices first), and the result is exact."""
+    # a 6-cycle 0..5 with chords 0-2 and 3-5 (vertices 1 and 4 become side
+    # vertices of degree 2), a triangle 0-6-7 and a K4 {3, 8, 9, 10}
+    u = [0, 1, 2, 3, 4, 5, 0, 3, 0, 0, 6, 3, 3, 3, 8, 8, 9]
+    v = [1, 2, 3, 4, 5, 0, 2, 5, 6, 7, 7, 8, 9, 10, 9, 10, 10]
+    g = gg.csr_from_edges(11, np.array(u), np.array(v))
+    for ops in ("s", "as", "das", "dasi", "odasi"):
+        got, st = compressed_via_oracle(g, ops)
+        assert st["side_vertices"] > 0 and st["side_pieces"] > 0, (ops, st)
+        assert_bc_close(got, oracle.bc(g), 1e-12, ops)
+
+
 @pytest.mark.parametrize("name", ["ba", "blocks", "grid", "rmat", "trees"])
 def test_workload_shapes_small(name):
     if name == "ba":
@@ -187,7 +207,7 @@ def test_workload_shapes_small(name):
     else:
         g = gg.random_tree(300, 8)
     want = oracle.bc(g)
-    for ops in ("d", "da", "dai", "ai", "odai"):
+    for ops in ("d", "da", "dai", "ai", "odai", "odasi", "s"):
         got, st = compressed_via_oracle(g, ops)
         assert_bc_close(got, want, 1e-9, f"{name} ops={ops}")
 
