@@ -149,9 +149,9 @@ def serving(args, sbc):
     with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         graphs = list(ex.map(gg.request_graph, reqs, chunksize=4))
     # Jobs share the device, so none takes the team kernel (a cooperative
-    # launch holds every CU); the deep grid jobs carry most of the work, and
-    # 16-wave batch workgroups are the tuned shape for deep pieces.
-    params = {"team_min_vertices": 0, "batch_wg_waves": 16}
+    # launch holds every CU); deep pieces (the grid jobs, which carry most of
+    # the work) get their own launch shape from the library's deep class.
+    params = {"team_min_vertices": 0}
     for kv in args.param:
         k, v = kv.split("=")
         params[k] = int(v)
@@ -172,6 +172,7 @@ def serving(args, sbc):
     th = threading.Thread(target=submit_all)
     th.start()
     lat, work = [], 0.0
+    by_kind = {"rmat": [], "grid": []}
     last_done = t0
     for i in range(len(reqs)):
         while jobs[i] is None:
@@ -179,6 +180,7 @@ def serving(args, sbc):
         bc, st = sbc.sbc_job_wait(jobs[i], graphs[i].n)
         sbc.sbc_job_release(jobs[i])
         lat.append(st["latency_ms"])
+        by_kind[reqs[i].kind].append(st["latency_ms"])
         work += float(graphs[i].n) * float(graphs[i].m)
         last_done = max(last_done, time.perf_counter())
         if i % 50 == 49:
@@ -193,6 +195,8 @@ def serving(args, sbc):
            "value": work / makespan / 1e9, "unit": "GTEPS", "n_gpus": 1, "higher_is_better": True,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "max_ms": float(np.max(lat)), "mean_ms": float(np.mean(lat)), "requests": len(reqs),
+           "by_kind": {k: {"jobs": len(v), "p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99))}
+                       for k, v in by_kind.items() if v},
            "rate_per_s": args.rate, "makespan_s": makespan, "offered_gteps": offered,
            "config": {"workload": f"Poisson stream at {args.rate}/s of {len(reqs)} jobs: R-MAT scale 10..15 "
                                   "(decorated) or deleted-edge grid side 32..256, fair coin", "slots": args.slots,

@@ -379,7 +379,12 @@ sbc_status sbc_copy_bandwidth(sbc_context ctx, size_t bytes, int reps, double* g
  * their device footprint fits in hbm_budget_bytes (0 = 80% of free memory)
  * and a slot is free; admitted jobs run concurrently on `slots` streams, so a
  * job that arrives while others run starts as soon as a slot and memory free
- * up.  Graph data and scores stay resident until the job is released.
+ * up.  The budget is allocated at creation, divided among the slots as
+ * device arenas (plus 64 MiB of pinned staging memory per slot): a job's
+ * device buffers come from its slot's arena and its copies run
+ * asynchronously on the slot's stream, so no job allocates or frees device
+ * memory (a job whose state does not fit its slot's arena fails with
+ * SBC_E_OOM).
  * A free slot takes the waiting job with the least estimated work
  * (n x arcs x (1 + breadth-first depth / 16)), or the oldest job once it has
  * waited server_max_wait_ms; context parameter server_order = 0 takes the

@@ -22,15 +22,73 @@ double wall_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+thread_local SlotResources* t_borrow = nullptr;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// A device copy of v.  With borrowed slot resources, the bytes go through
+// the slot's pinned staging memory with an asynchronous copy on its stream
+// (the plan waits for that stream before it runs); otherwise, or when the
+// staging memory is full, a synchronous copy.
 template <typename T>
 hipError_t upload(DevBuf& b, const std::vector<T>& v) {
   size_t bytes = std::max<size_t>(v.size() * sizeof(T), sizeof(T));
   hipError_t e = b.alloc(bytes);
-  if (e != hipSuccess) return e;
-  if (!v.empty()) e = hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-  return e;
+  if (e != hipSuccess || v.empty()) return e;
+  const size_t n = v.size() * sizeof(T);
+  SlotResources* r = t_borrow;
+  if (r && r->staging && r->staging_used + align256(n) <= r->staging_bytes) {
+    char* h = r->staging + r->staging_used;
+    r->staging_used += align256(n);
+    std::memcpy(h, v.data(), n);
+    return hipMemcpyAsync(b.p, h, n, hipMemcpyHostToDevice, r->own);
+  }
+  return hipMemcpy(b.p, v.data(), n, hipMemcpyHostToDevice);
 }
 }  // namespace
+
+SlotResources* borrowed_resources() { return t_borrow; }
+BorrowScope::BorrowScope(SlotResources* r) : prev(t_borrow) { t_borrow = r; }
+BorrowScope::~BorrowScope() { t_borrow = prev; }
+
+hipError_t SlotResources::create(size_t arena_b, size_t staging_b) {
+  hipError_t e;
+  arena_bytes = arena_b;
+  staging_bytes = staging_b;
+  if ((e = hipMalloc((void**)&arena, arena_b)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&staging, staging_b, hipHostMallocDefault)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&h_ctl, 256, hipHostMallocDefault)) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking)) != hipSuccess) return e;
+  for (auto& st : side)
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
+  for (hipEvent_t* ev : {&ev_start, &ev_trav, &ev_end})
+    if ((e = hipEventCreate(ev)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+  for (int k = 0; k < 5; ++k) {
+    if ((e = hipEventCreate(&ev_kc_start[k])) != hipSuccess) return e;
+    if ((e = hipEventCreate(&ev_kc_end[k])) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void SlotResources::destroy() {
+  if (own) (void)hipStreamSynchronize(own);
+  for (auto st : side)
+    if (st) (void)hipStreamSynchronize(st);
+  for (auto ev : {ev_start, ev_trav, ev_end, ev_fork})
+    if (ev) (void)hipEventDestroy(ev);
+  for (int k = 0; k < 5; ++k) {
+    if (ev_kc_start[k]) (void)hipEventDestroy(ev_kc_start[k]);
+    if (ev_kc_end[k]) (void)hipEventDestroy(ev_kc_end[k]);
+  }
+  for (auto st : side)
+    if (st) (void)hipStreamDestroy(st);
+  if (own) (void)hipStreamDestroy(own);
+  if (h_ctl) (void)hipHostFree(h_ctl);
+  if (staging) (void)hipHostFree(staging);
+  if (arena) (void)hipFree(arena);
+  *this = SlotResources();
+}
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 const std::string& last_error() { return g_last_error; }
@@ -48,6 +106,14 @@ sbc_status hip_fail(hipError_t e, const char* what) {
 hipError_t DevBuf::alloc(size_t b) {
   release();
   if (b == 0) b = 8;
+  if (SlotResources* r = t_borrow) {  // from the slot's arena: no device allocation
+    if (r->arena_used + align256(b) > r->arena_bytes) return hipErrorOutOfMemory;
+    p = r->arena + r->arena_used;
+    r->arena_used += align256(b);
+    bytes = b;
+    owned = false;
+    return hipSuccess;
+  }
   hipError_t e = hipMalloc(&p, b);
   if (e != hipSuccess) {
     p = nullptr;
@@ -55,13 +121,15 @@ hipError_t DevBuf::alloc(size_t b) {
     return e;
   }
   bytes = b;
+  owned = true;
   return hipSuccess;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && owned) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+  owned = false;
 }
 
 void Plan::quiesce() {
@@ -82,6 +150,7 @@ Plan::~Plan() {
   }
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
+  if (borrowed) return;  // the streams, events and control-block copy are the slot's
   for (auto e : {ev_start, ev_trav, ev_end, ev_fork})
     if (e) (void)hipEventDestroy(e);
   for (int c = 0; c < KC_COUNT; ++c) {
@@ -218,16 +287,31 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   // Streams and events first: every set-up kernel runs on `own`, so any
-  // return path can wait for it before buffers are released.
-  if ((e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-  for (int k = 0; k < KC_COUNT; ++k)
-    if ((e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-  for (hipEvent_t* ev : {&ev_start, &ev_trav, &ev_end})
-    if ((e = hipEventCreate(ev)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-  for (int k = 0; k < KC_COUNT; ++k) {
-    if ((e = hipEventCreate(&ev_kc_start[k])) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipEventCreate(&ev_kc_end[k])) != hipSuccess) return hip_fail(e, "event");
+  // return path can wait for it before buffers are released.  A serving
+  // slot lends its own.
+  if (SlotResources* r = borrowed_resources()) {
+    borrowed = true;
+    own = r->own;
+    for (int k = 0; k < KC_COUNT; ++k) {
+      side[k] = r->side[k];
+      ev_kc_start[k] = r->ev_kc_start[k];
+      ev_kc_end[k] = r->ev_kc_end[k];
+    }
+    ev_start = r->ev_start;
+    ev_trav = r->ev_trav;
+    ev_end = r->ev_end;
+    ev_fork = r->ev_fork;
+  } else {
+    if ((e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    for (int k = 0; k < KC_COUNT; ++k)
+      if ((e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    for (hipEvent_t* ev : {&ev_start, &ev_trav, &ev_end})
+      if ((e = hipEventCreate(ev)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    for (int k = 0; k < KC_COUNT; ++k) {
+      if ((e = hipEventCreate(&ev_kc_start[k])) != hipSuccess) return hip_fail(e, "event");
+      if ((e = hipEventCreate(&ev_kc_end[k])) != hipSuccess) return hip_fail(e, "event");
+    }
   }
   const bool plain = !(mode & SBC_COMPRESSED);
   // Deterministic runs: every item sums into its own area, reduced in a fixed
@@ -389,14 +473,24 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       return hip_fail(e, "alloc per-item areas of a deterministic run");
   }
   if ((e = d_ctl.alloc(sizeof(int32_t) * kCtlInts)) != hipSuccess) return hip_fail(e, "alloc ctl");
-  if ((e = hipHostMalloc((void**)&h_ctl, sizeof(int32_t) * kCtlInts, hipHostMallocDefault)) != hipSuccess)
+  if (borrowed) {
+    h_ctl = borrowed_resources()->h_ctl;
+  } else if ((e = hipHostMalloc((void**)&h_ctl, sizeof(int32_t) * kCtlInts, hipHostMallocDefault)) != hipSuccess) {
     return hip_fail(e, "hipHostMalloc");
+  }
   std::memset(h_ctl, 0, sizeof(int32_t) * kCtlInts);
 
-  // Traversal state, sized by occupancy and the memory budget.
+  // Traversal state, sized by occupancy and the memory budget (a serving
+  // slot: what is left of its arena).
   size_t freeb = 0, totalb = 0;
-  (void)hipMemGetInfo(&freeb, &totalb);
-  size_t budget = pr.mem_budget_mb > 0 ? (size_t)pr.mem_budget_mb << 20 : (size_t)(freeb * 0.6);
+  size_t budget;
+  if (borrowed) {
+    const SlotResources* r = borrowed_resources();
+    budget = (size_t)((r->arena_bytes - r->arena_used) * 0.9);
+  } else {
+    (void)hipMemGetInfo(&freeb, &totalb);
+    budget = pr.mem_budget_mb > 0 ? (size_t)pr.mem_budget_mb << 20 : (size_t)(freeb * 0.6);
+  }
   const int cus = c->cus;
   if (nitems[KC_WAVE]) {
     // The launch's LDS holds the largest piece's vertices and the most arcs

@@ -20,10 +20,42 @@ void set_error(const std::string& msg);
 sbc_status fail(sbc_status code, const std::string& msg);
 sbc_status hip_fail(hipError_t e, const char* what);
 
-// Device buffer owned by one object.
+// Device memory, pinned host staging, streams and events a plan borrows
+// instead of creating its own: the serving loop keeps one set per slot, so
+// a job neither allocates nor frees device memory (whose release waits for
+// the whole device) nor creates streams.  Device buffers are bump-allocated
+// from `arena`, uploads go through `staging` with asynchronous copies on
+// `own`; reset() makes both empty again once the slot's job is done.
+struct SlotResources {
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  char* staging = nullptr;  // pinned host memory
+  size_t staging_bytes = 0, staging_used = 0;
+  int32_t* h_ctl = nullptr;  // pinned copy of a plan's control block
+  hipStream_t own = nullptr;
+  hipStream_t side[5] = {};
+  hipEvent_t ev_start = nullptr, ev_trav = nullptr, ev_end = nullptr, ev_fork = nullptr;
+  hipEvent_t ev_kc_start[5] = {}, ev_kc_end[5] = {};
+  void reset() { arena_used = staging_used = 0; }
+  hipError_t create(size_t arena_b, size_t staging_b);
+  void destroy();
+};
+
+// While a BorrowScope lives, device buffers of this thread come from the
+// given slot's arena and uploads go through its staging memory.
+struct BorrowScope {
+  explicit BorrowScope(SlotResources* r);
+  ~BorrowScope();
+  SlotResources* prev;
+};
+SlotResources* borrowed_resources();
+
+// Device buffer owned by one object (or borrowed from a slot's arena, then
+// returned with the arena).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -150,6 +182,7 @@ struct Plan {
   hipEvent_t ev_start = nullptr, ev_trav = nullptr, ev_end = nullptr;
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_kc_start[KC_COUNT] = {}, ev_kc_end[KC_COUNT] = {};
+  bool borrowed = false;  // streams, events and control-block copy belong to a serving slot
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool use_graph = false;

@@ -3,8 +3,16 @@
 // `slots` worker threads each take a waiting job, preprocess it on the host,
 // then wait until its device footprint fits in the memory budget (a job that
 // arrives while others run is admitted the moment a slot and enough memory
-// are free).  Admitted jobs upload, run and copy back on their own streams,
-// so the device overlaps the work of every admitted job.
+// are free).  Admitted jobs upload, run and copy back on their slot's
+// streams, so the device overlaps the work of every admitted job.
+//
+// Each slot owns, from sbc_server_create on, a device arena (the budget
+// divided among the slots), pinned staging memory and its streams and
+// events.  A job's plan takes its device buffers from the arena and its
+// copies go through the staging memory asynchronously on the slot's stream,
+// so a job neither allocates nor frees device memory -- a release would wait
+// for every other job's kernels -- and a finished small job is not held up
+// by the long jobs beside it.
 //
 // Which waiting job a free worker takes (context parameter server_order):
 // the oldest, or the one with the least estimated work, unless the oldest
@@ -93,9 +101,12 @@ struct sbc_server_s {
   std::condition_variable cv;
   bool stopping = false;
   std::vector<std::thread> workers;
+  std::vector<SlotResources> res;  // per slot: arena, staging, streams, events
 };
 
-static void run_job(sbc_server s, sbc_job j) {
+static constexpr size_t kStagingBytes = (size_t)64 << 20;
+
+static void run_job(sbc_server s, int slot, sbc_job j) {
   sbc_status rc = SBC_OK;
   std::string err;
   size_t fp = 0;
@@ -121,6 +132,9 @@ static void run_job(sbc_server s, sbc_job j) {
         reserved = true;
       }
       j->t_start = now_ms();
+      SlotResources& r = s->res[slot];
+      r.reset();
+      BorrowScope borrow(&r);  // outlives the plan: its buffers are the arena's
       PlanOptions opt;
       Plan plan;
       rc = plan.build(s->ctx, *prob, j->mode, opt);
@@ -129,11 +143,20 @@ static void run_job(sbc_server s, sbc_job j) {
       if (rc == SBC_OK) rc = plan.sync(&st);
       if (rc == SBC_OK) {
         j->result.resize(plan.n);
-        hipError_t e = hipMemcpy(j->result.data(), plan.d_out.p, sizeof(double) * plan.n, hipMemcpyDeviceToHost);
+        const size_t bytes = sizeof(double) * plan.n;
+        hipError_t e;
+        if (r.staging_used + bytes <= r.staging_bytes) {  // through the staging memory, on the slot's stream
+          char* h = r.staging + r.staging_used;
+          e = hipMemcpyAsync(h, plan.d_out.p, bytes, hipMemcpyDeviceToHost, r.own);
+          if (e == hipSuccess) e = hipStreamSynchronize(r.own);
+          if (e == hipSuccess) std::memcpy(j->result.data(), h, bytes);
+        } else {
+          e = hipMemcpy(j->result.data(), plan.d_out.p, bytes, hipMemcpyDeviceToHost);
+        }
         if (e != hipSuccess) rc = hip_fail(e, "copy result");
       }
       j->stats.teps = st.teps;
-      j->stats.footprint_bytes = (int64_t)plan.device_bytes();
+      j->stats.footprint_bytes = (int64_t)r.arena_used;
     }
   } catch (const std::bad_alloc&) {
     rc = fail(SBC_E_OOM, "host allocation failed");
@@ -161,7 +184,7 @@ static void run_job(sbc_server s, sbc_job j) {
   j->cv.notify_all();
 }
 
-static void worker_loop(sbc_server s) {
+static void worker_loop(sbc_server s, int slot) {
   (void)hipSetDevice(s->ctx->device);
   while (true) {
     sbc_job j = nullptr;
@@ -180,7 +203,7 @@ static void worker_loop(sbc_server s) {
       j = *pick;
       s->pending.erase(pick);
     }
-    run_job(s, j);
+    run_job(s, slot, j);
     job_unref(j);
   }
 }
@@ -199,7 +222,15 @@ sbc_status sbc_server_create(sbc_context ctx, int slots, size_t hbm_budget_bytes
     s->ctx = ctx;
     s->slots = slots;
     s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(freeb * 0.8);
-    for (int i = 0; i < slots; ++i) s->workers.emplace_back(worker_loop, s.get());
+    s->res.resize(slots);
+    for (int i = 0; i < slots; ++i) {
+      if ((e = s->res[i].create(s->budget / (size_t)slots, kStagingBytes)) != hipSuccess) {
+        for (auto& r : s->res) r.destroy();
+        (void)hipGetLastError();
+        return hip_fail(e, "server slot memory");
+      }
+    }
+    for (int i = 0; i < slots; ++i) s->workers.emplace_back(worker_loop, s.get(), i);
     *out = s.release();
   } catch (...) {
     return fail(SBC_E_OOM, "could not start the server");
@@ -215,6 +246,8 @@ sbc_status sbc_server_destroy(sbc_server s) {
   }
   s->cv.notify_all();
   for (auto& t : s->workers) t.join();
+  (void)hipSetDevice(s->ctx->device);
+  for (auto& r : s->res) r.destroy();
   delete s;
   return SBC_OK;
 }
