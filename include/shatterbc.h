@@ -164,6 +164,12 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "team_local_fences"  1 (default): a team whose workgroups all run on one XCD
  *                        synchronises through that XCD's L2 (L1 invalidation
  *                        only); 0: agent-scope fences always
+ *   "team_cooperative"   1 (default): the team kernel is launched cooperatively (the
+ *                        runtime starts it only when every workgroup is
+ *                        resident); 0: an ordinary launch of the same grid,
+ *                        whose bounded join barrier turns a workgroup that
+ *                        never starts into SBC_E_DEVICE (for tools that do not
+ *                        handle cooperative launches)
  *   "team_split_arcs"    team kernel: rows with more arcs are pulled in slices
  *                        of 256 arcs spread over the team (default 2048)
  *   "team_max_levels"    pieces whose breadth-first depth from their highest-degree

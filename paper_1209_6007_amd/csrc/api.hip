@@ -108,6 +108,7 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "team_waves_per_eu") return &p.team_waves_per_eu;
   if (k == "team_spin_ms") return &p.team_spin_ms;
   if (k == "team_local_fences") return &p.team_local_fences;
+  if (k == "team_cooperative") return &p.team_cooperative;
   if (k == "team_split_arcs") return &p.team_split_arcs;
   if (k == "team_max_levels") return &p.team_max_levels;
   if (k == "sample_items") return &p.sample_items;
@@ -133,6 +134,7 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "batch_pairs") ok = value >= 0 && value <= 64;
   if (k == "team_spin_ms") ok = value <= 600000;
   if (k == "team_local_fences") ok = value == 0 || value == 1;
+  if (k == "team_cooperative") ok = value == 0 || value == 1;
   if (k == "server_order") ok = value == 0 || value == 1;
   if (k == "team_split_arcs") ok = value >= 64 && value <= (1 << 30);
   if (k == "wave_max_vertices") ok = value >= 0 && value <= kWaveMaxVertices;

@@ -134,6 +134,7 @@ struct TeamArgs {
   int64_t spin_ticks;   // bound of one barrier wait, in wall-clock ticks
   int32_t allow_local;  // 1: teams on one XCD release without writing back L2
   int32_t split_arcs;   // rows with more arcs are pulled in slices over the team
+  int32_t cooperative;  // 1: cooperative launch (the runtime guarantees residency); 0: ordinary launch
 };
 
 // Dynamic LDS of the small-piece kernel (one source per wavefront, the piece

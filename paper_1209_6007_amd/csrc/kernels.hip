@@ -117,8 +117,16 @@ hipError_t launch_team_t(const DevPieces& P, const QueueArgs& Q, int grid, const
   MsState s = st;
   TeamArgs t = T;
   DumpOut d = dump;
-  void* args[] = {&p, &q, &s, &t, &d};
   (void)hipGetLastError();
+  if (!T.cooperative) {
+    // An ordinary launch of a grid the device holds at once: the kernel's
+    // bounded join barrier turns a workgroup that never starts into an
+    // aborted run (kFlagTeamTimeout), not a hang.
+    hipLaunchKernelGGL((ms_team_kernel<WAVES, EU, R, I, D>), dim3(grid), dim3(WAVES * 64),
+                       (unsigned)sizeof(TeamShared<WAVES * 64>), stream, p, q, s, t, d);
+    return hipGetLastError();
+  }
+  void* args[] = {&p, &q, &s, &t, &d};
   const hipError_t e = hipLaunchCooperativeKernel(ms_team_kernel<WAVES, EU, R, I, D>, dim3(grid), dim3(WAVES * 64),
                                                   args, (unsigned)sizeof(TeamShared<WAVES * 64>), stream);
   if (e != hipSuccess) (void)hipGetLastError();

@@ -586,7 +586,8 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       (void)hipGetLastError();
       coop = 0;
     }
-    if (!coop) return fail(SBC_E_DEVICE, "the device does not support cooperative launches (team kernel)");
+    if (!coop && pr.team_cooperative)
+      return fail(SBC_E_DEVICE, "the device does not support cooperative launches (team kernel)");
     const int occ = occupancy_team(team_waves, team_eu, opt.dump);
     if (occ <= 0) return fail(SBC_E_INVALID_ARG, "team kernel configuration cannot be resident");
     const int nteams = (int)std::max<int64_t>(1, pr.team_count);
@@ -631,6 +632,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     targs.heavy_max = (int32_t)max_rows;
     targs.allow_local = pr.team_local_fences ? 1 : 0;
     targs.split_arcs = (int32_t)pr.team_split_arcs;
+    targs.cooperative = pr.team_cooperative ? 1 : 0;
     targs.spin_ticks = (int64_t)((double)pr.team_spin_ms * c->wall_khz);
   }
   if (opt.dump) {

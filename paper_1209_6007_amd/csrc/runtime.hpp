@@ -86,6 +86,7 @@ struct Params {
   int64_t team_waves_per_eu = 8;      // occupancy target of the team kernel (0 or 8)
   int64_t team_spin_ms = 20000;       // bound of one team barrier wait
   int64_t team_local_fences = 1;      // 1: teams on one XCD fence through L2 only
+  int64_t team_cooperative = 1;       // 1: cooperative launch of the team kernel; 0: ordinary launch
   int64_t team_split_arcs = 2048;     // team kernel: rows with more arcs are split into slices
   int64_t team_max_levels = 0;        // pieces deeper than this stay off the team kernel (0: no limit)
   int64_t sample_items = 0;           // tuning only: run an evenly spaced sample of this many items per class

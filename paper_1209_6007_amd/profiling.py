@@ -14,6 +14,13 @@ hardware-counter runs, into HBM bytes per kernel launch:
       (sbc_copy_bandwidth run in the same process), and optionally recorded in
       a JSON file keyed by workload and kernel class with the kernel source hash.
 
+  python -m paper_1209_6007_amd.profiling reqs READ_DIR WRITE_DIR --kernel NAME \
+      --workload W --kernel-class K --title T --command C [--json PATH]
+      HBM bytes per dispatch from the L2-to-fabric request counters by size:
+      reads 32*TCC_EA0_RDREQ_32B + 64*TCC_EA0_RDREQ_64B + 128*TCC_EA0_RDREQ_128B,
+      writes 64*TCC_EA0_WRREQ_64B + 32*(TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B);
+      the copy kernel's figures (1 GiB each way) are shown as a check.
+
 FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  On gfx950 FETCH_SIZE counts
 64 bytes per L2-to-fabric read request, so 128-byte requests (a streaming copy)
 read as half their size; the copy-kernel factor corrects for that for streaming
@@ -107,6 +114,62 @@ def pmc_summary(fetch_dir: str, write_dir: str, kernel: str):
     return res
 
 
+READ_COUNTERS = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+WRITE_COUNTERS = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum")
+
+
+def _per_dispatch(vals: dict, kernel: str, counter: str) -> float:
+    xs = [v for n in _match(vals, kernel) for v in vals[n].get(counter, [])]
+    if not xs:
+        raise KeyError(f"no {counter} values for {kernel}")
+    return sum(xs) / len(xs)
+
+
+def reqs_summary(read_dir: str, write_dir: str, kernel: str):
+    """Bytes per dispatch of `kernel` and of the copy kernel from the request counters by size."""
+    r = counter_values(read_dir)
+    w = counter_values(write_dir)
+    out = {}
+    for name in (kernel, COPY_KERNEL):
+        n32, n64, n128 = (_per_dispatch(r, name, c) for c in READ_COUNTERS)
+        wr, wr64 = (_per_dispatch(w, name, c) for c in WRITE_COUNTERS)
+        out[name] = {"rd32": n32, "rd64": n64, "rd128": n128, "wr": wr, "wr64": wr64,
+                     "read_bytes": 32 * n32 + 64 * n64 + 128 * n128, "write_bytes": 64 * wr64 + 32 * (wr - wr64)}
+        out[name]["bytes"] = out[name]["read_bytes"] + out[name]["write_bytes"]
+    return out
+
+
+def _cmd_reqs(a):
+    s = reqs_summary(a.read_dir, a.write_dir, a.kernel)
+    sha = kernel_source_hash()
+    k, c = s[a.kernel], s[COPY_KERNEL]
+    print(f"# {a.title}\n")
+    print("Commands (run from the repository root on one MI355X, one counter pass per run):\n")
+    print("```\n" + a.command + "\n```\n")
+    print(f"Kernel: names containing `{a.kernel}`; kernel source hash `{sha}`.\n")
+    print("L2-to-fabric requests per dispatch by size, and the bytes they carry:\n")
+    print("| kernel | 32 B reads | 64 B reads | 128 B reads | write requests (64 B of them) | read bytes | write bytes |")
+    print("|---|---|---|---|---|---|---|")
+    for name, x in ((a.kernel, k), ("copy_kernel (1 GiB each way)", c)):
+        print(f"| `{name}` | {x['rd32']:.4g} | {x['rd64']:.4g} | {x['rd128']:.4g} | {x['wr']:.4g} ({x['wr64']:.4g}) | "
+              f"{x['read_bytes']:.4e} | {x['write_bytes']:.4e} |")
+    print(f"\nHBM traffic per launch of the kernel (reads + writes): **{k['bytes']:.4e} bytes**; "
+          f"the copy kernel reads {c['read_bytes'] / 2**30:.3f} GiB and writes {c['write_bytes'] / 2**30:.3f} GiB.")
+    if a.json:
+        d = {}
+        if os.path.exists(a.json):
+            with open(a.json) as fh:
+                d = json.load(fh)
+        d.setdefault(a.workload, {})[a.kernel_class] = {
+            "kernel_sha": sha, "bytes_per_launch": k["bytes"], "read_bytes_per_launch": k["read_bytes"],
+            "write_bytes_per_launch": k["write_bytes"], "read_requests": {"32": k["rd32"], "64": k["rd64"],
+                                                                          "128": k["rd128"]},
+            "copy_check_read_gib": c["read_bytes"] / 2**30, "copy_check_write_gib": c["write_bytes"] / 2**30,
+            "kernel": a.kernel, "counters": "TCC_EA0_RDREQ_{32B,64B,128B}, TCC_EA0_WRREQ{,_64B}"}
+        with open(a.json, "w") as fh:
+            json.dump(d, fh, indent=1, sort_keys=True)
+
+
 def _cmd_trace(a):
     rows = kernel_stats(a.dir)
     print(f"# {a.title}\n")
@@ -166,8 +229,17 @@ def main(argv=None):
     p.add_argument("--title", required=True)
     p.add_argument("--command", required=True)
     p.add_argument("--json")
+    q = sub.add_parser("reqs")
+    q.add_argument("read_dir")
+    q.add_argument("write_dir")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--kernel-class", required=True)
+    q.add_argument("--title", required=True)
+    q.add_argument("--command", required=True)
+    q.add_argument("--json")
     a = ap.parse_args(argv)
-    (_cmd_trace if a.cmd == "trace" else _cmd_pmc)(a)
+    {"trace": _cmd_trace, "pmc": _cmd_pmc, "reqs": _cmd_reqs}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -22,6 +22,7 @@
 #include <condition_variable>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <mutex>
@@ -319,7 +320,11 @@ struct emu_event {
   double t_ms = 0;
 };
 
-inline const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "success" : "emulated HIP error"; }
+inline const char* hipGetErrorString(hipError_t e) {
+  static thread_local char buf[48];
+  std::snprintf(buf, sizeof buf, "emulated HIP error %d", (int)e);
+  return e == hipSuccess ? "success" : buf;
+}
 // As in HIP: a failing call leaves its error behind until hipGetLastError()
 // reads it, and successful calls do not clear it.
 inline thread_local hipError_t tl_last_error = hipSuccess;

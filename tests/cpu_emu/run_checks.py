@@ -251,7 +251,7 @@ def main(which):
             # the small-piece kernel: forced on single pieces (few and many
             # levels, a hub, items of a few sources), and by default routing
             # on graphs that shatter into small pieces
-            wctx = sbc.Context(0, {"slots": 2})
+            wctx = sbc.Context(0, {"slots": 2, "batch_wg_waves": 4, "deep_wg_waves": 4})
             cases = [("er3", gg.erdos_renyi(3, 0.9, 1)), ("er5", gg.erdos_renyi(5, 0.9, 2)),
                      ("er65", gg.erdos_renyi(65, 0.1, 3)), ("er130", gg.erdos_renyi(130, 0.05, 4)),
                      ("cycle40", gg.cycle(40)), ("K9", gg.complete(9)), ("K3,70", gg.complete_bipartite(3, 70))]

@@ -209,6 +209,19 @@ def test_deterministic_runs_are_bit_equal(ctx, name):
     assert_bc_close(runs[0], want, RTOL, f"{name} deterministic")
 
 
+def test_team_kernel_without_cooperative_launch():
+    """team_cooperative = 0: the team kernel as an ordinary launch of a grid
+    the device holds at once gives the oracle's result."""
+    g = gg.rmat_decorated(scale=12, seed=81)
+    c = sbc.Context(0, {"team_min_vertices": 64, "team_cooperative": 0})
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    G.preprocess("odai")
+    got, st = sbc.sbc_betweenness(c.h, G.h, sbc.SBC_COMPRESSED, with_stats=True)
+    c.close()
+    assert st["items_class"][4] > 0, st["items_class"]
+    assert_bc_close(got, oracle.bc(g), RTOL, "non-cooperative team launch")
+
+
 def test_unordered_halves(ctx):
     g = gg.ba_pendant_triangles()
     a = run(ctx, g, "compressed")
