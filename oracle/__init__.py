@@ -11,6 +11,11 @@ It shares no code with ``paper_1209_6007_amd`` and never imports it.
 * ``bc_pieces``       ``bc_weighted`` on every piece of a packed set of pieces.
 * ``bc_side``         Algorithm 3 (Bfs-Side, Section 3.3.2) for side vertices
                       removed one after another.
+* ``farness`` / ``farness_pieces``  sum of shortest-path distances (weighted
+                      by a per-vertex weight), one breadth-first search per
+                      vertex, exact int64: the plain definition behind
+                      closeness centrality, the measure the paper names as
+                      the next one to shatter (Sections 1 and 5).
 * ``brute.bc_bruteforce`` Eq. (1) evaluated pair by pair (tiny graphs).
 
 All scores are over ordered pairs, unnormalised (Eq. (1)).
@@ -58,6 +63,9 @@ def _load():
         lib.oracle_bc_pieces.restype = ctypes.c_int
         lib.oracle_bc_side.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int64, i32p, ctypes.c_int, f64p]
         lib.oracle_bc_side.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_farness_pieces.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int, i64p]
+        lib.oracle_farness_pieces.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -158,6 +166,33 @@ def bc_side(n, row_ptr, col, reach, sides, threads: int | None = None) -> np.nda
     if rc != 0:
         raise RuntimeError(f"oracle_bc_side failed: {rc}")
     return out[:n]
+
+
+def farness_pieces(vtx_off, row, col, weight=None, threads: int | None = None) -> np.ndarray:
+    """For every packed vertex x of every piece (layout as in bc_pieces): the
+    sum over the vertices y of x's piece reachable from x of
+    weight[y] * dist(x, y), int64 (weight None: all ones)."""
+    lib = _load()
+    vo, vop = _i32(vtx_off)
+    rw, rwp = _i32(row)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    wt, wtp = _i32(weight)
+    P = len(vo) - 1
+    V = int(vo[-1]) if P > 0 else 0
+    out = np.zeros(max(V, 1), dtype=np.int64)
+    rc = lib.oracle_farness_pieces(int(P), vop, rwp, clp, wtp, threads or default_threads(),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise RuntimeError(f"oracle_farness_pieces failed: {rc}")
+    return out[:V]
+
+
+def farness(n, row_ptr, col, weight=None, threads: int | None = None) -> np.ndarray:
+    """Sum of shortest-path distances from every vertex to the vertices it
+    reaches (weighted by weight[y] when given), int64."""
+    if n == 0:
+        return np.zeros(0, dtype=np.int64)
+    return farness_pieces(np.array([0, n], np.int32), row_ptr, col, weight, threads)
 
 
 def bc(g, sources=None, threads=None) -> np.ndarray:

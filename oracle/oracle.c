@@ -24,6 +24,16 @@
  *                          whole shattered graph piece by piece.
  *   oracle_bc_side      -- Algorithm 3 (Bfs-Side, Section 3.3.2) for a list of
  *                          side vertices removed one after another.
+ *   oracle_farness_pieces -- weighted farness: for every vertex x of every
+ *                          piece, the sum over the vertices y of x's piece
+ *                          that x reaches of weight[y] * dist(x, y) (exact
+ *                          int64).  With one piece and unit weights this is
+ *                          the farness whose reciprocal is closeness
+ *                          centrality, the measure the paper names as the
+ *                          next one to shatter and compress (Sections 1 and
+ *                          5); the paper gives no formulas for it, so the
+ *                          oracle is the plain definition, one breadth-first
+ *                          search per vertex.
  *
  * Threads split the source list into contiguous static blocks; each thread
  * keeps private arrays and the per-thread scores are added in thread order,
@@ -499,5 +509,104 @@ int oracle_bc_side(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
     for (int t = 0; t < nthreads; ++t)
         for (int32_t v = 0; v < n; ++v) bc_out[v] += acc[(size_t)t * (size_t)n + v];
     free(rank); free(jobs); free(tid); free(acc);
+    return rc;
+}
+
+
+/* ---------------------------------------------------------------------------
+ * Weighted farness per piece: one breadth-first search per vertex, summing
+ * weight[y] * level(y) over the vertices it reaches.  int64 throughout, so the
+ * result is exact (the caller keeps weight * distance sums below 2^63).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t P;
+    const int32_t *vtx_off, *row, *col, *weight;
+    int64_t g0, g1; /* packed vertices of this thread */
+    int64_t *out;
+    int status;
+} far_job;
+
+static void *far_worker(void *arg) {
+    far_job *J = (far_job *)arg;
+    int32_t maxn = 0;
+    for (int32_t p = 0; p < J->P; ++p)
+        if (J->vtx_off[p + 1] - J->vtx_off[p] > maxn) maxn = J->vtx_off[p + 1] - J->vtx_off[p];
+    size_t nn = maxn > 0 ? (size_t)maxn : 1;
+    int32_t *Q = malloc(nn * sizeof(int32_t));
+    int32_t *d = malloc(nn * sizeof(int32_t));
+    if (!Q || !d) {
+        free(Q); free(d);
+        J->status = -7;
+        return NULL;
+    }
+    int32_t p = J->g0 < J->g1 ? piece_of(J->vtx_off, J->P, J->g0) : 0;
+    for (int64_t g = J->g0; g < J->g1; ++g) {
+        while (g >= J->vtx_off[p + 1]) ++p;
+        const int32_t vb = J->vtx_off[p], np = J->vtx_off[p + 1] - vb;
+        const int32_t *rp = J->row + vb;
+        for (int32_t v = 0; v < np; ++v) d[v] = -1;
+        const int32_t s = (int32_t)(g - vb);
+        int64_t sum = 0;
+        int32_t qh = 0, qt = 0;
+        Q[qt++] = s;
+        d[s] = 0;
+        while (qh < qt) {
+            const int32_t v = Q[qh++];
+            sum += (int64_t)d[v] * (J->weight ? (int64_t)J->weight[vb + v] : 1);
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+                const int32_t w = J->col[e];
+                if (w < 0 || w >= np) {
+                    free(Q); free(d);
+                    J->status = -5;
+                    return NULL;
+                }
+                if (d[w] < 0) {
+                    d[w] = d[v] + 1;
+                    Q[qt++] = w;
+                }
+            }
+        }
+        J->out[g] = sum;
+    }
+    free(Q); free(d);
+    J->status = 0;
+    return NULL;
+}
+
+int oracle_farness_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row, const int32_t *col,
+                          const int32_t *weight, int nthreads, int64_t *out) {
+    if (P < 0 || (P > 0 && (!vtx_off || !row || !out))) return -1;
+    if (P == 0) return 0;
+    const int64_t V = vtx_off[P];
+    for (int32_t p = 0; p < P; ++p)
+        if (vtx_off[p + 1] < vtx_off[p]) return -1;
+    if (V == 0) return 0;
+    if (!col && row[V] > row[0]) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > V) nthreads = (int)V;
+    far_job *jobs = calloc((size_t)nthreads, sizeof(far_job));
+    pthread_t *tid = calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !tid) {
+        free(jobs); free(tid);
+        return -7;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        far_job *J = &jobs[t];
+        J->P = P; J->vtx_off = vtx_off; J->row = row; J->col = col; J->weight = weight; J->out = out;
+        J->g0 = V * t / nthreads;
+        J->g1 = V * (t + 1) / nthreads;
+        J->status = -1;
+    }
+    for (int t = 1; t < nthreads; ++t)
+        if (pthread_create(&tid[t], NULL, far_worker, &jobs[t]) != 0) jobs[t].status = -99;
+    far_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t)
+        if (jobs[t].status != -99) pthread_join(tid[t], NULL);
+    int rc = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (jobs[t].status == -99) far_worker(&jobs[t]);
+        if (jobs[t].status != 0) rc = jobs[t].status;
+    }
+    free(jobs); free(tid);
     return rc;
 }
