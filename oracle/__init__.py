@@ -66,6 +66,9 @@ def _load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_farness_pieces.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int, i64p]
         lib.oracle_farness_pieces.restype = ctypes.c_int
+        lib.oracle_farness_sources.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int64, i32p, ctypes.c_int,
+                                               i64p]
+        lib.oracle_farness_sources.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -187,12 +190,25 @@ def farness_pieces(vtx_off, row, col, weight=None, threads: int | None = None) -
     return out[:V]
 
 
-def farness(n, row_ptr, col, weight=None, threads: int | None = None) -> np.ndarray:
-    """Sum of shortest-path distances from every vertex to the vertices it
-    reaches (weighted by weight[y] when given), int64."""
-    if n == 0:
-        return np.zeros(0, dtype=np.int64)
-    return farness_pieces(np.array([0, n], np.int32), row_ptr, col, weight, threads)
+def farness(n, row_ptr, col, weight=None, sources=None, threads: int | None = None) -> np.ndarray:
+    """Sum of shortest-path distances from every vertex (or from each of
+    `sources`, in that order) to the vertices it reaches (weighted by
+    weight[y] when given), int64."""
+    if sources is None:
+        if n == 0:
+            return np.zeros(0, dtype=np.int64)
+        return farness_pieces(np.array([0, n], np.int32), row_ptr, col, weight, threads)
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    wt, wtp = _i32(weight)
+    sv, svp = _i32(sources)
+    out = np.zeros(max(len(sv), 1), dtype=np.int64)
+    rc = lib.oracle_farness_sources(int(n), rpp, clp, wtp, len(sv), svp, threads or default_threads(),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise RuntimeError(f"oracle_farness_sources failed: {rc}")
+    return out[:len(sv)]
 
 
 def bc(g, sources=None, threads=None) -> np.ndarray:

@@ -521,7 +521,8 @@ int oracle_bc_side(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
 typedef struct {
     int32_t P;
     const int32_t *vtx_off, *row, *col, *weight;
-    int64_t g0, g1; /* packed vertices of this thread */
+    int64_t g0, g1; /* packed vertices of this thread (indexes into `sources` when it is set) */
+    const int32_t *sources; /* one piece only: the vertices to search from, or NULL for all */
     int64_t *out;
     int status;
 } far_job;
@@ -539,8 +540,9 @@ static void *far_worker(void *arg) {
         J->status = -7;
         return NULL;
     }
-    int32_t p = J->g0 < J->g1 ? piece_of(J->vtx_off, J->P, J->g0) : 0;
-    for (int64_t g = J->g0; g < J->g1; ++g) {
+    int32_t p = (J->g0 < J->g1 && !J->sources) ? piece_of(J->vtx_off, J->P, J->g0) : 0;
+    for (int64_t k = J->g0; k < J->g1; ++k) {
+        const int64_t g = J->sources ? J->sources[k] : k;
         while (g >= J->vtx_off[p + 1]) ++p;
         const int32_t vb = J->vtx_off[p], np = J->vtx_off[p + 1] - vb;
         const int32_t *rp = J->row + vb;
@@ -566,22 +568,26 @@ static void *far_worker(void *arg) {
                 }
             }
         }
-        J->out[g] = sum;
+        J->out[k] = sum;
     }
     free(Q); free(d);
     J->status = 0;
     return NULL;
 }
 
-int oracle_farness_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row, const int32_t *col,
-                          const int32_t *weight, int nthreads, int64_t *out) {
+static int far_run(int32_t P, const int32_t *vtx_off, const int32_t *row, const int32_t *col, const int32_t *weight,
+                   int64_t nsrc, const int32_t *sources, int nthreads, int64_t *out) {
     if (P < 0 || (P > 0 && (!vtx_off || !row || !out))) return -1;
     if (P == 0) return 0;
-    const int64_t V = vtx_off[P];
     for (int32_t p = 0; p < P; ++p)
         if (vtx_off[p + 1] < vtx_off[p]) return -1;
+    if (vtx_off[P] == 0) return 0;
+    if (!col && row[vtx_off[P]] > row[0]) return -1;
+    if (sources)
+        for (int64_t k = 0; k < nsrc; ++k)
+            if (sources[k] < 0 || sources[k] >= vtx_off[P]) return -1;
+    const int64_t V = sources ? nsrc : vtx_off[P];
     if (V == 0) return 0;
-    if (!col && row[V] > row[0]) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > V) nthreads = (int)V;
     far_job *jobs = calloc((size_t)nthreads, sizeof(far_job));
@@ -593,6 +599,7 @@ int oracle_farness_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row,
     for (int t = 0; t < nthreads; ++t) {
         far_job *J = &jobs[t];
         J->P = P; J->vtx_off = vtx_off; J->row = row; J->col = col; J->weight = weight; J->out = out;
+        J->sources = sources;
         J->g0 = V * t / nthreads;
         J->g1 = V * (t + 1) / nthreads;
         J->status = -1;
@@ -609,4 +616,19 @@ int oracle_farness_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row,
     }
     free(jobs); free(tid);
     return rc;
+}
+
+int oracle_farness_pieces(int32_t P, const int32_t *vtx_off, const int32_t *row, const int32_t *col,
+                          const int32_t *weight, int nthreads, int64_t *out) {
+    return far_run(P, vtx_off, row, col, weight, 0, NULL, nthreads, out);
+}
+
+/* One graph (row_ptr[n+1], col), the farness of the listed sources only:
+ * out[k] belongs to sources[k]. */
+int oracle_farness_sources(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *weight,
+                           int64_t nsrc, const int32_t *sources, int nthreads, int64_t *out) {
+    if (n < 0 || nsrc < 0 || (nsrc > 0 && !sources)) return -1;
+    if (n == 0 || nsrc == 0) return 0;
+    const int32_t vtx_off[2] = {0, n};
+    return far_run(1, vtx_off, row_ptr, col, weight, nsrc, sources, nthreads, out);
 }

@@ -133,3 +133,11 @@ def test_threads_agree():
     a = oracle.farness(g.n, g.row_ptr, g.col, threads=1)
     b = oracle.farness(g.n, g.row_ptr, g.col, threads=7)
     assert np.array_equal(a, b)
+
+
+def test_source_subset_is_the_same_searches():
+    g = gg.erdos_renyi(200, 0.02, 9)
+    w = gg.rng(3).integers(1, 6, size=g.n).astype(np.int32)
+    src = np.array([5, 0, 199, 5, 77], np.int32)
+    assert np.array_equal(oracle.farness(g.n, g.row_ptr, g.col, w, sources=src),
+                          brute_farness(g, w)[src])
