@@ -257,6 +257,49 @@ def compressed_leg(sbc, params, name, steps, warmup, ops):
             "roofline": roofline_of(st_c, False, name)}
 
 
+def farness_leg(sbc, params, name, steps, warmup):
+    """Closeness on the same shattered pieces ("oda"): per step, the farness
+    kernel's per-piece sums, their download and the host's block-cut-tree
+    pass.  Roofline of the farness kernel: per (source, piece), the CSR
+    (4 (n_p + 1) + 4 a_p bytes), a level read per arc (4 a_p), a level write
+    and a reach read per vertex (8 n_p): 8 a_p + 12 n_p bytes."""
+    desc, make = WORKLOADS[name]
+    progress(f"farness {name}: generating")
+    g = make()
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    ctx = sbc.Context(0, params)
+    f, pst = sbc.sbc_far_create(G.h, "oda")
+    try:
+        ex = sbc.sbc_far_export(f)
+        npc = np.diff(ex["vtx_off"]).astype(np.float64)
+        apc = np.diff(ex["row"][ex["vtx_off"]]).astype(np.float64)
+        algo_bytes = float(np.sum(npc * (8 * apc + 12 * npc + 4)))
+        for i in range(warmup):
+            sbc.sbc_far_run(ctx.h, f, g.n)
+        runs = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            runs.append(sbc.sbc_far_run(ctx.h, f, g.n)[2])
+            progress(f"farness {name} step {i}: kernel {runs[-1]['ms_kernel']:.1f} ms, total {runs[-1]['ms_total']:.1f} ms")
+        t = (time.perf_counter() - t0) / steps
+    finally:
+        sbc.sbc_far_destroy(f)
+        ctx.close()
+        G.close()
+    ms_k = float(np.mean([r["ms_kernel"] for r in runs]))
+    na = active_sources(g)
+    achieved = algo_bytes / (ms_k * 1e-3) / 1e9 if ms_k > 0 else None
+    return {"workload": f"{name}: {desc}", "ops": "oda", "n": g.n, "m": g.m, "non_isolated": na, "steps": steps,
+            "warmup": warmup, "ms_per_step": t * 1e3, "gteps": na * g.m / t / 1e9,
+            "kernel_ms": ms_k, "raw_gteps": runs[-1]["teps"] / 1e9, "host_prep_ms": pst["ms_prep"],
+            "host_finish_ms": float(np.mean([r["ms_finish"] for r in runs])), "pieces": pst["pieces"],
+            "items": runs[-1]["items"], "grid": runs[-1]["grid"],
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                         "kernel": "far_kernel<WAVES,*>", "launch_ms": ms_k, "algo_bytes_per_launch": algo_bytes,
+                         "timing": "HIP events around the kernel's launch on its stream"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +312,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--legs", default="blocktree20000,grid512",
                     help="comma-separated workloads timed after the main one (compressed only); '' for none")
+    ap.add_argument("--far", default="rmat17",
+                    help="comma-separated workloads whose farness/closeness is timed too ('' for none)")
     ap.add_argument("--leg-steps", type=int, default=3)
     ap.add_argument("--leg-warmup", type=int, default=1)
     ap.add_argument("--graph", action="store_true", help="replay a captured HIP graph")
@@ -384,6 +429,12 @@ def main():
         for w in legs:
             out["legs"][w] = compressed_leg(sbc, params, w, args.leg_steps, args.leg_warmup, args.ops)
             progress(f"leg {w}: {out['legs'][w]['ms_per_step']:.1f} ms per step")
+    fars = [w for w in args.far.split(",") if w]
+    if fars:
+        out["closeness"] = {}
+        for w in fars:
+            out["closeness"][w] = farness_leg(sbc, params, w, args.leg_steps, args.leg_warmup)
+            progress(f"farness {w}: {out['closeness'][w]['ms_per_step']:.1f} ms per step")
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle) starts")
         threads = min(os.cpu_count() or 1, 16)

@@ -175,6 +175,7 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "team_max_levels"    pieces whose breadth-first depth from their highest-degree
  *                        vertex exceeds this stay on the one-workgroup batch
  *                        kernel (0: no limit)
+ *   "far_wg_waves"       wavefronts per workgroup of the farness kernel (4, 8, 16; default 8)
  *   "server_order"       serving: 1 (default) least estimated work first, 0 oldest first
  *   "server_max_wait_ms" serving: a job waiting longer is taken first (default 30000)
  *   "sample_items"       tuning only (0: off): plans run an evenly spaced sample of
@@ -378,6 +379,72 @@ sbc_status sbc_piece_bc_noalloc(sbc_context ctx, int32_t n, int32_t arcs, const 
  * (copy_kernel) for scaling hardware byte counters.
  * Errors: SBC_E_INVALID_ARG, SBC_E_OOM, SBC_E_DEVICE. */
 sbc_status sbc_copy_bandwidth(sbc_context ctx, size_t bytes, int reps, double* gbps);
+
+/* ---------------------------------------------------- farness and closeness
+ *
+ * Closeness centrality on the same shattered pieces: the paper builds its
+ * shattering for betweenness and names closeness as the next measure to
+ * carry it to (Sections 1 and 5), without formulas.  The farness of v is the
+ * sum of hop distances from v to every vertex of its connected component; the
+ * closeness is (component size - 1) / farness (0 for an isolated vertex).
+ * All values are exact (int64).
+ *
+ * The host strips degree-1 vertices (Section 3.3.1) and shatters at
+ * articulation vertices (Section 3.2.1; bridges as two-vertex blocks,
+ * Section 3.2.2), with the reach of every copy as for betweenness.  The
+ * device computes, for every vertex v of every piece B of 3 or more
+ * vertices, W_B(v) = sum over w in B of reach_B(w) * d_B(v, w) (64 sources
+ * per work item, breadth-first only); the host then passes once up and once
+ * down the block-cut tree and the stripped trees:
+ *   farness(v) = W_B(v) + farness(t) - W_B(t)   for v in B below its top t,
+ *   farness(u) = farness(v) + R - 2 s            for u stripped from v with a
+ *                                                subtree of s vertices,
+ * the search root's farness being the sum, over what hangs from it, of the
+ * W and distance sums accumulated on the way up. */
+typedef struct sbc_far_s* sbc_far;
+
+typedef struct {
+  int64_t n, components;
+  int64_t stripped;        /* degree-1 vertices removed */
+  int64_t blocks, bridges; /* blocks of the stripped graph; two-vertex ones among them */
+  int64_t pieces;          /* blocks of >= 3 vertices (or whole components without 'a'): device pieces */
+  int64_t piece_vertices, piece_arcs;
+  double ms_prep;
+} sbc_far_stats;
+
+typedef struct {
+  double ms_kernel;        /* device time of the farness kernel */
+  double ms_device_total;  /* uploads, kernel and downloads */
+  double ms_finish;        /* host pass over the block-cut tree */
+  double ms_total;
+  double teps;             /* sum over pieces of n_p * m_p, per second of kernel time */
+  int64_t items, grid, waves;
+  int32_t flags;           /* device flags (0 on success) */
+} sbc_far_run_stats;
+
+/* Prepare graph g for farness with preprocessing `ops`: any of 'o'
+ * (breadth-first order per piece, Section 4.1), 'd' (degree-1), 'a'
+ * (articulation shattering); "" keeps each component whole.  Host only; the
+ * graph may be used or destroyed afterwards (nothing refers to it).
+ * Errors: SBC_E_INVALID_ARG (NULL, or a letter other than o, d, a), SBC_E_OOM. */
+sbc_status sbc_far_create(sbc_graph g, const char* ops, sbc_far* out, sbc_far_stats* st);
+sbc_status sbc_far_destroy(sbc_far f);
+/* Sizes of the device pieces: P, V = sum of n_p, A = sum of arcs. */
+sbc_status sbc_far_info(sbc_far f, int32_t* pieces, int64_t* vertices, int64_t* arcs);
+/* Copies the device pieces to host buffers (any may be NULL): vtx_off[P+1],
+ * row[V+1] (absolute arc offsets), col[A] (piece-local ids), reach[V] and
+ * orig[V] (the original vertex of each piece vertex). */
+sbc_status sbc_far_export(sbc_far f, int32_t* vtx_off, int32_t* row, int32_t* col, int32_t* reach, int32_t* orig);
+/* Host pass only: farness[n] (and closeness[n] unless NULL) from the per-piece
+ * sums piece_sums[V] (W_B of every piece vertex, in export order), however
+ * they were computed.  Needs no GPU. */
+sbc_status sbc_far_finish(sbc_far f, const int64_t* piece_sums, int64_t* farness, double* closeness);
+/* The whole computation: device sums (written to piece_sums[V] unless NULL),
+ * then the host pass.  Outputs are host buffers.
+ * Errors: SBC_E_DEVICE (launch failure, or a device range check),
+ * SBC_E_OOM, SBC_E_TOO_LARGE. */
+sbc_status sbc_far_run(sbc_context ctx, sbc_far f, int64_t* piece_sums, int64_t* farness, double* closeness,
+                       sbc_far_run_stats* st);
 
 /* ---------------------------------------------------------------- serving */
 

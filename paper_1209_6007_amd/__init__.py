@@ -89,6 +89,22 @@ class JobStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FarStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "components", "stripped", "blocks", "bridges", "pieces",
+                                               "piece_vertices", "piece_arcs")] + [("ms_prep", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FarRunStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("ms_kernel", "ms_device_total", "ms_finish", "ms_total", "teps")] + \
+               [(k, ctypes.c_int64) for k in ("items", "grid", "waves")] + [("flags", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -131,6 +147,12 @@ _SIGS = {
     "sbc_piece_bc_noalloc": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
                              ctypes.c_int32),
     "sbc_copy_bandwidth": ([_vp, ctypes.c_size_t, ctypes.c_int, _f64p], ctypes.c_int32),
+    "sbc_far_create": ([_vp, ctypes.c_char_p, ctypes.POINTER(_vp), ctypes.POINTER(FarStats)], ctypes.c_int32),
+    "sbc_far_destroy": ([_vp], ctypes.c_int32),
+    "sbc_far_info": ([_vp, _i32p, _i64p, _i64p], ctypes.c_int32),
+    "sbc_far_export": ([_vp, _i32p, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
+    "sbc_far_finish": ([_vp, _i64p, _i64p, _f64p], ctypes.c_int32),
+    "sbc_far_run": ([_vp, _vp, _i64p, _i64p, _f64p, ctypes.POINTER(FarRunStats)], ctypes.c_int32),
     "sbc_server_create": ([_vp, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int32),
     "sbc_server_destroy": ([_vp], ctypes.c_int32),
     "sbc_server_submit": ([_vp, _vp, ctypes.c_uint32, ctypes.POINTER(_vp)], ctypes.c_int32),
@@ -447,6 +469,74 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def sbc_far_create(g, ops: str = "oda"):
+    """Prepares graph handle g for farness; returns (handle, stats dict)."""
+    h = _vp()
+    st = FarStats()
+    _check(lib().sbc_far_create(g, ops.encode(), ctypes.byref(h), ctypes.byref(st)))
+    return h, st.as_dict()
+
+
+def sbc_far_destroy(f):
+    _check(lib().sbc_far_destroy(f))
+
+
+def sbc_far_export(f) -> dict:
+    P, V, A = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().sbc_far_info(f, ctypes.byref(P), ctypes.byref(V), ctypes.byref(A)))
+    out = {"vtx_off": np.zeros(P.value + 1, np.int32), "row": np.zeros(V.value + 1, np.int32),
+           "col": np.zeros(max(A.value, 1), np.int32), "reach": np.zeros(max(V.value, 1), np.int32),
+           "orig": np.zeros(max(V.value, 1), np.int32)}
+    _check(lib().sbc_far_export(f, *(out[k].ctypes.data_as(_i32p) for k in ("vtx_off", "row", "col", "reach", "orig"))))
+    out["col"] = out["col"][:A.value]
+    out["reach"] = out["reach"][:V.value]
+    out["orig"] = out["orig"][:V.value]
+    return out
+
+
+def sbc_far_finish(f, n: int, piece_sums):
+    """Host pass only: (farness int64[n], closeness f64[n]) from per-piece sums."""
+    w = np.ascontiguousarray(piece_sums, dtype=np.int64)
+    far = np.zeros(max(n, 1), np.int64)
+    clo = np.zeros(max(n, 1), np.float64)
+    _check(lib().sbc_far_finish(f, w.ctypes.data_as(_i64p) if w.size else None, far.ctypes.data_as(_i64p),
+                                clo.ctypes.data_as(_f64p)))
+    return far[:n], clo[:n]
+
+
+def sbc_far_run(ctx, f, n: int, with_piece_sums: bool = False):
+    """Device sums and host pass: (farness, closeness, stats[, piece_sums])."""
+    P, V, A = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().sbc_far_info(f, ctypes.byref(P), ctypes.byref(V), ctypes.byref(A)))
+    w = np.zeros(max(V.value, 1), np.int64)
+    far = np.zeros(max(n, 1), np.int64)
+    clo = np.zeros(max(n, 1), np.float64)
+    st = FarRunStats()
+    _check(lib().sbc_far_run(ctx, f, w.ctypes.data_as(_i64p) if with_piece_sums else None,
+                             far.ctypes.data_as(_i64p), clo.ctypes.data_as(_f64p), ctypes.byref(st)))
+    if with_piece_sums:
+        return far[:n], clo[:n], st.as_dict(), w[:V.value]
+    return far[:n], clo[:n], st.as_dict()
+
+
+def closeness(n, row_ptr, col, ops: str = "oda", device: int = 0, ctx: Context | None = None):
+    """Farness (int64) and closeness ((component size - 1) / farness) of a CSR graph."""
+    own = ctx is None
+    ctx = ctx or Context(device)
+    g = Graph(n, row_ptr, col)
+    f = None
+    try:
+        f, _ = sbc_far_create(g.h, ops)
+        far, clo, _ = sbc_far_run(ctx.h, f, n)
+        return far, clo
+    finally:
+        if f:
+            sbc_far_destroy(f)
+        g.close()
+        if own:
+            ctx.close()
 
 
 class Graph:

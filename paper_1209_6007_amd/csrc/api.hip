@@ -112,6 +112,7 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "team_split_arcs") return &p.team_split_arcs;
   if (k == "team_max_levels") return &p.team_max_levels;
   if (k == "sample_items") return &p.sample_items;
+  if (k == "far_wg_waves") return &p.far_wg_waves;
   if (k == "server_order") return &p.server_order;
   if (k == "server_max_wait_ms") return &p.server_max_wait_ms;
   return nullptr;
@@ -127,6 +128,7 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "batch_wg_waves") ok = value == 4 || value == 8 || value == 16;
   if (k == "batch_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
   if (k == "deep_wg_waves") ok = value == 4 || value == 8 || value == 16;
+  if (k == "far_wg_waves") ok = value == 4 || value == 8 || value == 16;
   if (k == "deep_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
   if (k == "team_waves_per_eu") ok = value == 0 || value == 8;
   if (k == "team_count") ok = value >= 1 && value <= 1024;

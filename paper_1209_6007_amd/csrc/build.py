@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libshatterbc.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 
-HOST_SOURCES = ["prep.cpp"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "server.hip", "noalloc.hip"]
+HOST_SOURCES = ["prep.cpp", "far.cpp"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "server.hip", "noalloc.hip", "far_api.hip"]
 
 ARCH = "gfx950"
 HIP_FLAGS = [

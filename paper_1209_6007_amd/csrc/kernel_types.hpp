@@ -187,6 +187,17 @@ constexpr WaveLds wave_lds_layout(int64_t np, int64_t arcs, int64_t waves) {
 // Largest piece the small-piece kernel takes (its BFS order is 16-bit).
 constexpr int32_t kWaveMaxVertices = 4096;
 
+// Per-slot state of the farness kernel: the (vertex, lanes) entries of every
+// level (qcap per slot), and per-vertex visit and frontier lane masks.
+struct FarState {
+  int32_t* q;
+  uint64_t* vis;
+  uint64_t* fa;
+  uint64_t* fb;
+  int64_t stride;  // vertices per slot (the largest piece)
+  int64_t qcap;    // entries per slot
+};
+
 struct QueueArgs {
   const WorkItem* items;
   int32_t nitems;

@@ -272,6 +272,52 @@ hipError_t launch_team(const DevPieces& P, const QueueArgs& Q, bool reach, bool 
   }
 }
 
+namespace {
+template <int WAVES>
+hipError_t launch_far_w(const DevPieces& P, const QueueArgs& Q, bool reach, int grid, const FarState& st,
+                        int64_t* out, hipStream_t stream) {
+  (void)hipGetLastError();
+  if (reach)
+    hipLaunchKernelGGL((far_kernel<WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st, out);
+  else
+    hipLaunchKernelGGL((far_kernel<WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st, out);
+  return hipGetLastError();
+}
+template <int WAVES>
+int occ_far_w() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)far_kernel<WAVES, true>, WAVES * 64, 0) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+}  // namespace
+
+hipError_t launch_far(const DevPieces& P, const QueueArgs& Q, bool reach, int waves, int grid, const FarState& st,
+                      int64_t* out, hipStream_t stream) {
+  switch (waves) {
+    case 4: return launch_far_w<4>(P, Q, reach, grid, st, out, stream);
+#ifndef SBC_EMU_FEW_VARIANTS
+    case 8: return launch_far_w<8>(P, Q, reach, grid, st, out, stream);
+    case 16: return launch_far_w<16>(P, Q, reach, grid, st, out, stream);
+#endif
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int occupancy_far(int waves) {
+  switch (waves) {
+    case 4: return occ_far_w<4>();
+#ifndef SBC_EMU_FEW_VARIANTS
+    case 8: return occ_far_w<8>();
+    case 16: return occ_far_w<16>();
+#endif
+    default: return 0;
+  }
+}
+
 hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t* map_off, const int32_t* map_idx,
                           const double* bcp, const double* corr, const double* bcx, double scale, double* out,
                           hipStream_t stream) {

@@ -29,6 +29,12 @@ hipError_t launch_mapback(int32_t n, int32_t nverts, int32_t nmap, const int32_t
 // the item areas (see QueueArgs::item_base).
 hipError_t launch_det_reduce(int32_t nverts, int32_t npieces, const int32_t* vtx_off, const int64_t* area_base,
                              const int32_t* piece_items, const double* item_out, double* bcp, hipStream_t stream);
+// Farness kernel: per-source sums of reach x distance within each piece,
+// sources 64 per item (the item's s0..s1-1 are piece-local ids); waves in
+// {4, 8, 16}.
+hipError_t launch_far(const DevPieces& P, const QueueArgs& Q, bool reach, int waves, int grid, const FarState& st,
+                      int64_t* out, hipStream_t stream);
+int occupancy_far(int waves);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, int grid, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t stream);

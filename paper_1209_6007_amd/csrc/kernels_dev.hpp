@@ -1862,6 +1862,194 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
   }
 }
 
+// ---------------------------------------------------------------------------
+// Weighted farness of 64 sources at a time, for closeness on the shattered
+// pieces: the breadth-first discovery of ms_kernel's forward sweep without
+// path counts.  Lane j runs the piece-local source src_order[vb + s0 + j]
+// (s0 + j when src_order is null).  Every level's new
+// (vertex, lanes) entries add reach[v] x level to their lanes' sums; a wave
+// adds 64 entries into its 64 lanes by visiting the entries in turn (lane j
+// takes an entry's weight when bit j of its mask is set), so the sums need no
+// atomics, and out[] gets each source's exact int64 sum.
+// ---------------------------------------------------------------------------
+template <int WAVES, bool REACH>
+__global__ __launch_bounds__(WAVES * 64) void far_kernel(DevPieces P, QueueArgs Q, FarState st,
+                                                         int64_t* __restrict__ out) {
+  if (Q.magic != kArgMagic) return;
+  constexpr int BLOCK = WAVES * 64;
+  __shared__ int s_item;
+  __shared__ int s_cnt;
+  __shared__ int s_wtot[WAVES];
+  __shared__ int s_scan[BLOCK];
+  __shared__ int s_e0[BLOCK];
+  __shared__ uint64_t s_f[BLOCK];
+  __shared__ long long s_sum[WAVES * 64];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t slot = blockIdx.x;
+  int32_t* q = st.q + slot * (size_t)st.qcap;
+  uint64_t* vis = st.vis + slot * (size_t)st.stride;
+  uint64_t* bufa = st.fa + slot * (size_t)st.stride;
+  uint64_t* bufb = st.fb + slot * (size_t)st.stride;
+  const int64_t qcap = st.qcap;
+  const int32_t narcs = P.narcs;
+
+  while (true) {
+    if (tid == 0) s_item = atomicAdd(Q.head, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it < 0 || it >= Q.nitems) break;
+    const WorkItem W = Q.items[it];
+    int32_t vb, np;
+    if (!(item_ok(P, Q, W, st.stride, &vb, &np) && W.s1 - W.s0 >= 1 && W.s1 - W.s0 <= 64 && qcap >= 64)) {
+      if (tid == 0) {
+        raise_flag(Q.flags, kFlagBadItem);
+        atomicAdd(Q.done, 1);
+      }
+      continue;
+    }
+    const int32_t* rowp = P.row + vb;
+    const int32_t* col = P.col;
+    const int32_t* rch = REACH ? P.reach + vb : nullptr;
+    const int nsrc = W.s1 - W.s0;  // 1..64
+    int32_t s = -1;
+    if (lane < nsrc) s = P.src_order ? P.src_order[vb + W.s0 + lane] : W.s0 + lane;
+    if (__ballot(lane < nsrc && (s < 0 || s >= np)) != 0) {  // same verdict in every wave
+      if (tid == 0) {
+        raise_flag(Q.flags, kFlagBadSource);
+        atomicAdd(Q.done, 1);
+      }
+      continue;
+    }
+    if (wave == 0 && lane < nsrc) {
+      q[lane] = s;
+      bufa[s] = 1ull << lane;
+      vis[s] = 1ull << lane;
+    }
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+
+    uint64_t* fcur = bufa;
+    uint64_t* fnxt = bufb;
+    int qs = 0, qe = nsrc, L = 0;
+    long long sum = 0;  // this wave's part of lane `lane`'s source's sum
+    while (true) {
+      // Discover level L+1: the arcs of level L's entries spread evenly over
+      // the workgroup; a vertex's first new lane bit queues it.
+      for (int cb = qs; cb < qe; cb += BLOCK) {
+        const int i = cb + tid;
+        int e0 = 0, deg = 0;
+        uint64_t fu = 0;
+        if (i < qe) {
+          const int32_t u = q[i];
+          if (u >= 0 && u < np) {
+            e0 = rowp[u];
+            const int32_t e1 = rowp[u + 1];
+            if (e0 >= 0 && e1 >= e0 && e1 <= narcs) {
+              deg = e1 - e0;
+              fu = fcur[u];
+            } else {
+              raise_flag(Q.flags, kFlagBadArc);
+              e0 = 0;
+            }
+          } else {
+            raise_flag(Q.flags, kFlagBadArc);
+          }
+        }
+        int total;
+        const int ex = block_excl_scan<BLOCK>(deg, s_wtot, &total);
+        s_scan[tid] = ex;
+        s_e0[tid] = e0;
+        s_f[tid] = fu;
+        __syncthreads();
+        const int nv = min(BLOCK, qe - cb);
+        for (int t = tid; t < total; t += BLOCK) {
+          int lo = 0, hi = nv - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_scan[mid] <= t) lo = mid;
+            else hi = mid - 1;
+          }
+          const int32_t w = col[s_e0[lo] + (t - s_scan[lo])];
+          if (w < 0 || w >= np) {
+            raise_flag(Q.flags, kFlagBadArc);
+            continue;
+          }
+          const uint64_t nw = s_f[lo] & ~vis[w];
+          if (nw) {
+            const uint64_t old = atomicOr((unsigned long long*)&fnxt[w], (unsigned long long)nw);
+            if (old == 0) {
+              const int pos = atomicAdd(&s_cnt, 1);
+              if (qe + pos < qcap) q[qe + pos] = w;
+              else raise_flag(Q.flags, kFlagQueueOverflow);
+            }
+          }
+        }
+        __syncthreads();
+      }
+      const int nt = (int)min((int64_t)qe + s_cnt, qcap);
+      if (nt == qe) break;
+      // Level L+1's entries: mark their lanes visited and add reach x level
+      // to those lanes, 64 entries per wave at a time.
+      const long long lev = L + 1;
+      for (int base = qe + wave * 64; base < nt; base += BLOCK) {
+        const int i = base + lane;
+        uint64_t m = 0;
+        int wt = 0;
+        if (i < nt) {
+          const int32_t w = q[i];
+          if (w >= 0 && w < np) {
+            m = fnxt[w];
+            vis[w] |= m;
+            wt = REACH ? rch[w] : 1;
+          }
+        }
+        const int cnt = min(64, nt - base);
+        long long acc = 0;
+        for (int k = 0; k < cnt; ++k) {
+          const uint64_t mk = readlane64(m, k);
+          const int wk = __builtin_amdgcn_readlane(wt, k);
+          if ((mk >> lane) & 1) acc += wk;
+        }
+        sum += lev * acc;
+      }
+      // Retire level L's frontier masks; level L+1 becomes current.
+      for (int i = qs + tid; i < qe; i += BLOCK) {
+        const int32_t u = q[i];
+        if (u >= 0 && u < np) fcur[u] = 0;
+      }
+      __syncthreads();
+      if (tid == 0) s_cnt = 0;  // every thread has read it; the next discovery adds after a barrier
+      uint64_t* t = fcur;
+      fcur = fnxt;
+      fnxt = t;
+      qs = qe;
+      qe = nt;
+      ++L;
+    }
+    // Restore the slot: the last level's frontier and every entry's visit mask.
+    for (int i = qs + tid; i < qe; i += BLOCK) {
+      const int32_t u = q[i];
+      if (u >= 0 && u < np) fcur[u] = 0;
+    }
+    for (int i = tid; i < qe; i += BLOCK) {
+      const int32_t u = q[i];
+      if (u >= 0 && u < np) vis[u] = 0;
+    }
+    s_sum[wave * 64 + lane] = sum;
+    __syncthreads();
+    if (wave == 0) {
+      long long tot = 0;
+      for (int w = 0; w < WAVES; ++w) tot += s_sum[w * 64 + lane];
+      if (lane < nsrc) out[(size_t)vb + s] = (int64_t)tot;
+    }
+    __syncthreads();
+    if (tid == 0) atomicAdd(Q.done, 1);
+  }
+}
+
+
 __global__ void mapback_kernel(int32_t n, int32_t nverts, int32_t nmap, const int32_t* __restrict__ map_off,
                                const int32_t* __restrict__ map_idx, const double* __restrict__ bcp,
                                const double* __restrict__ corr, const double* __restrict__ bcx, double scale,

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1209_6007_amd", "csrc")
 OUT_DIR = os.path.join(ROOT, "_build", "emu")
 OUT = os.path.join(OUT_DIR, "libshatterbc_emu.so")
-SOURCES = ["prep.cpp", "kernels.hip", "runtime.hip", "api.hip", "server.hip", "noalloc.hip"]
+SOURCES = ["prep.cpp", "far.cpp", "kernels.hip", "runtime.hip", "api.hip", "server.hip", "noalloc.hip", "far_api.hip"]
 
 
 def build(asan: bool = True) -> str:

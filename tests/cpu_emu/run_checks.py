@@ -333,8 +333,34 @@ def main(which):
                 sbc.sbc_job_release(j)
             sbc.sbc_server_destroy(srv)
         check("server", server)
+    if "far" in which:
+        def far():
+            # farness kernel: per-piece sums equal to the oracle's exactly, and
+            # the whole farness after the host pass; two slots reused by many
+            # items, levels wider than a workgroup, weighted and unweighted pieces
+            fctx = sbc.Context(0, {"far_wg_waves": 4, "slots": 2})
+            cases = [("decorated", gg.decorated_random(60, 0.06, 15, 4, 4, 5)), ("grid", gg.grid2d(9, 11)),
+                     ("blocks", gg.block_tree(n_pieces=10, max_size=80, seed=2)), ("er400", gg.erdos_renyi(400, 0.02, 6)),
+                     ("path3", gg.path(3)), ("K5", gg.complete(5))]
+            for name, g in cases:
+                want = oracle.farness(g.n, g.row_ptr, g.col)
+                for ops in ("oda", ""):
+                    G = sbc.Graph(g.n, g.row_ptr, g.col)
+                    f, _ = sbc.sbc_far_create(G.h, ops)
+                    ex = sbc.sbc_far_export(f)
+                    far, clo, st, W = sbc.sbc_far_run(fctx.h, f, g.n, with_piece_sums=True)
+                    if len(ex["vtx_off"]) > 1:
+                        wantW = oracle.farness_pieces(ex["vtx_off"], ex["row"], ex["col"], ex["reach"])
+                        assert np.array_equal(W, wantW), (name, ops)
+                    assert np.array_equal(far, want), (name, ops)
+                    assert st["flags"] == 0, st
+                    sbc.sbc_far_destroy(f)
+                    G.close()
+                print(f"   {name} ok", flush=True)
+            fctx.close()
+        check("farness kernel", far)
     print("ALL OK", flush=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "wave", "noalloc", "server"])
+    main(sys.argv[1:] or ["single", "pieces", "whole", "hubs", "team", "wave", "noalloc", "server", "far"])

@@ -32,7 +32,7 @@ def emu_lib():
     return build_emu.build(asan=True)
 
 
-CHECKS = ["single", "pieces", "whole", "hubs", "team", "wave", "noalloc", "server"]
+CHECKS = ["single", "pieces", "whole", "hubs", "team", "wave", "noalloc", "server", "far"]
 
 
 @pytest.fixture(scope="module")
