@@ -7,6 +7,9 @@ It shares no code with ``paper_1209_6007_amd`` and never imports it.
 * ``bc_plain``        Algorithm 1 (Bc-Org, Section 2.1) in C, FP64.
 * ``bc_weighted``     Algorithm 2 (Bc-Reach, Section 3.2.1) with the
                       identical-vertex weights of Section 3.3.3, in C, FP64.
+* ``bc_classes``      ``bc_weighted`` for piece vertices standing for ident[v]
+                      identical vertices whose reaches (possibly different)
+                      sum to reach[v].
 * ``single_source``   per-source levels / path counts / dependencies.
 * ``bc_pieces``       ``bc_weighted`` on every piece of a packed set of pieces.
 * ``bc_side``         Algorithm 3 (Bfs-Side, Section 3.3.2) for side vertices
@@ -63,6 +66,8 @@ def _load():
         lib.oracle_bc_pieces.restype = ctypes.c_int
         lib.oracle_bc_side.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int64, i32p, ctypes.c_int, f64p]
         lib.oracle_bc_side.restype = ctypes.c_int
+        lib.oracle_bc_classes.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int, f64p]
+        lib.oracle_bc_classes.restype = ctypes.c_int
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_farness_pieces.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int, i64p]
         lib.oracle_farness_pieces.restype = ctypes.c_int
@@ -113,6 +118,23 @@ def bc_weighted(n, row_ptr, col, reach=None, ident=None, sources=None, threads: 
                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if rc != 0:
         raise RuntimeError(f"oracle_bc_weighted failed: {rc}")
+    return out[:n]
+
+
+def bc_classes(n, row_ptr, col, reach_sum, ident, threads: int | None = None) -> np.ndarray:
+    """Algorithm 2 with identical-vertex weights where piece vertex v stands
+    for ident[v] members whose reaches sum to reach_sum[v]; returns bc' (the
+    members' common part: the dependency starts at their mean reach minus one)."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    re, rep = _i32(reach_sum)
+    idn, idp = _i32(ident)
+    out = np.zeros(max(n, 1), dtype=np.float64)
+    rc = lib.oracle_bc_classes(int(n), rpp, clp, rep, idp, threads or default_threads(),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise RuntimeError(f"oracle_bc_classes failed: {rc}")
     return out[:n]
 
 

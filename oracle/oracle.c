@@ -17,6 +17,14 @@
  *                          the identical-vertex rules of Section 3.3.3 (sigma
  *                          update, dependency update and accumulation weighted
  *                          by ident).  Returns bc' of the attributed graph.
+ *   oracle_bc_classes   -- oracle_bc_weighted for piece vertices that stand for
+ *                          ident[v] identical vertices of possibly different
+ *                          reaches summing to reach[v]: the members' paths are
+ *                          those of Section 3.3.3, each member's hung vertices
+ *                          are sources (weight: the sum) and targets (the
+ *                          dependency starts at the members' mean reach minus
+ *                          one).  Equal reaches r give reach[v] = ident[v] * r
+ *                          and oracle_bc_weighted's result.
  *   oracle_single_source-- one source of the weighted algorithm, returning the
  *                          BFS levels, path counts and dependencies.
  *   oracle_bc_pieces    -- oracle_bc_weighted on every piece of a packed set of
@@ -53,6 +61,7 @@ typedef struct {
     const int32_t *sources; /* NULL => 0..n-1 */
     int64_t src_begin, src_end;
     int weighted;
+    int classes;            /* reach holds the members' reach sum (oracle_bc_classes) */
     double *bc;             /* private accumulator, length n */
     int status;
 } oracle_job;
@@ -129,10 +138,16 @@ static void one_source(const oracle_job *J, oracle_ws *w, int32_t s, double *bc)
         }
     }
     /* Phase 2: back propagation. */
-    for (int32_t v = 0; v < n; ++v)
-        w->delta[v] = (J->weighted && J->reach) ? (double)(J->reach[v] - 1) : 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (J->classes) /* a member's own hung targets: the members' mean reach minus one */
+            w->delta[v] = (double)J->reach[v] / (double)J->ident[v] - 1.0;
+        else
+            w->delta[v] = (J->weighted && J->reach) ? (double)(J->reach[v] - 1) : 0.0;
+    }
     double src_weight = 1.0;
-    if (J->weighted) {
+    if (J->classes) {
+        src_weight = (double)J->reach[s]; /* every member's hung vertices are sources */
+    } else if (J->weighted) {
         if (J->reach) src_weight *= (double)J->reach[s];
         if (J->ident) src_weight *= (double)J->ident[s];
     }
@@ -164,9 +179,19 @@ static void *worker(void *arg) {
     return NULL;
 }
 
+static int run_threads_k(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
+                         const int32_t *ident, int weighted, int classes, int64_t nsrc, const int32_t *sources,
+                         int nthreads, double *bc_out);
+
 static int run_threads(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
                        const int32_t *ident, int weighted, int64_t nsrc, const int32_t *sources,
                        int nthreads, double *bc_out) {
+    return run_threads_k(n, row_ptr, col, reach, ident, weighted, 0, nsrc, sources, nthreads, bc_out);
+}
+
+static int run_threads_k(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
+                         const int32_t *ident, int weighted, int classes, int64_t nsrc, const int32_t *sources,
+                         int nthreads, double *bc_out) {
     if (n < 0 || !row_ptr || (n > 0 && !col) || !bc_out) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nsrc < nthreads) nthreads = nsrc > 0 ? (int)nsrc : 1;
@@ -184,6 +209,7 @@ static int run_threads(int32_t n, const int32_t *row_ptr, const int32_t *col, co
         J->n = n; J->row_ptr = row_ptr; J->col = col;
         J->reach = reach; J->ident = ident; J->sources = sources;
         J->weighted = weighted;
+        J->classes = classes;
         J->src_begin = nsrc * t / nthreads;
         J->src_end = nsrc * (t + 1) / nthreads;
         J->bc = acc + (size_t)t * (size_t)n;
@@ -218,6 +244,16 @@ int oracle_bc_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, co
                        double *bc_out) {
     if (!sources) nsrc = n;
     return run_threads(n, row_ptr, col, reach, ident, 1, nsrc, sources, nthreads, bc_out);
+}
+
+/* oracle_bc_weighted for class vertices: ident[v] members whose reaches sum
+ * to reach[v] (both required, every reach[v] >= ident[v] >= 1). */
+int oracle_bc_classes(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *reach,
+                      const int32_t *ident, int nthreads, double *bc_out) {
+    if (n > 0 && (!reach || !ident)) return -1;
+    for (int32_t v = 0; v < n; ++v)
+        if (ident[v] < 1 || reach[v] < ident[v]) return -1;
+    return run_threads_k(n, row_ptr, col, reach, ident, 1, 1, n, NULL, nthreads, bc_out);
 }
 
 /* Levels (d, -1 when unreachable), path counts and dependencies of source s. */

@@ -51,6 +51,43 @@ def expand_attributed(n, row_ptr, col, reach, ident, twin_type):
     return g, copy_off[:-1]
 
 
+def expand_classes(n, row_ptr, col, members, twin_type):
+    """Like expand_attributed, with members[v] the list of the reaches of v's
+    copies (which may differ): copy j of v gets members[v][j] - 1 pendant
+    leaves.  Returns (Graph, copy_off) with v's copies copy_off[v] ..
+    copy_off[v+1]-1."""
+    ident = np.array([len(m) for m in members], dtype=np.int64)
+    copy_off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(ident, out=copy_off[1:])
+    us, vs = [], []
+    rp = np.asarray(row_ptr)
+    for v in range(n):
+        cv = range(copy_off[v], copy_off[v + 1])
+        for e in range(rp[v], rp[v + 1]):
+            u = int(col[e])
+            if u < v:
+                continue
+            for a in cv:
+                for b in range(copy_off[u], copy_off[u + 1]):
+                    us.append(a)
+                    vs.append(b)
+        if twin_type[v] == 2:
+            cl = list(cv)
+            for i in range(len(cl)):
+                for j in range(i + 1, len(cl)):
+                    us.append(cl[i])
+                    vs.append(cl[j])
+    nxt = int(copy_off[-1])
+    for v in range(n):
+        for j, a in enumerate(range(copy_off[v], copy_off[v + 1])):
+            for _ in range(int(members[v][j]) - 1):
+                us.append(a)
+                vs.append(nxt)
+                nxt += 1
+    g = gg.csr_from_edges(nxt, np.array(us, dtype=np.int64), np.array(vs, dtype=np.int64), "expanded")
+    return g, copy_off
+
+
 def twin_corrections(n, row_ptr, col, reach, ident, twin_type):
     """Per-member score the merged traversal cannot see (derived from Sec. 3.3.3).
 
@@ -129,12 +166,20 @@ def assert_bc_close(got, want, rtol=1e-9, what=""):
                            f"{bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}")
 
 
+def member_reach(ex):
+    """Per-member reach of exported piece vertices whose members all have the
+    same reach (the export carries each piece vertex's members' reach sum)."""
+    r, k = ex["reach"].astype(np.int64), ex["ident"].astype(np.int64)
+    assert np.all(r % k == 0), "a piece vertex merges members of unequal reach"
+    return (r // k).astype(np.int32)
+
+
 def piece_csr(ex, p):
-    """Local CSR (row_ptr, col), reach and ident of exported piece p."""
+    """Local CSR (row_ptr, col), per-member reach and ident of exported piece p."""
     vb, ve = int(ex["vtx_off"][p]), int(ex["vtx_off"][p + 1])
     rp = (ex["row"][vb:ve + 1] - ex["row"][vb]).astype(np.int32)
     cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int32)
-    return rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve]
+    return rp, cl, member_reach(ex)[vb:ve], ex["ident"][vb:ve]
 
 
 def map_back(ex, bcp):

@@ -19,7 +19,7 @@ import pytest
 import graphgen as gg
 import oracle
 from oracle import brute
-from tests.helpers import assert_bc_close, expand_attributed, tree_closed_form, twin_corrections
+from tests.helpers import assert_bc_close, expand_attributed, expand_classes, tree_closed_form, twin_corrections
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -336,3 +336,56 @@ def test_bc_side_threads_agree():
     a = oracle.bc_side(g.n, g.row_ptr, g.col, reach, S, threads=1)
     b = oracle.bc_side(g.n, g.row_ptr, g.col, reach, S, threads=5)
     np.testing.assert_allclose(a, b, rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_classes_with_equal_reach_are_the_weighted_form(seed):
+    """bc_classes with reach sum k*r is bc_weighted with reach r, ident k."""
+    g = gg.erdos_renyi(40, 0.12, 300 + seed)
+    reach, ident = gg.random_attributes(g.n, 800 + seed, rmax=4, kmax=4)
+    np.testing.assert_array_equal(oracle.bc_classes(g.n, g.row_ptr, g.col, reach * ident, ident),
+                                  oracle.bc_weighted(g.n, g.row_ptr, g.col, reach, ident))
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_classes_of_unequal_reach_on_expanded_graph(seed):
+    """A piece vertex standing for k identical vertices with reaches
+    r_1..r_k: on the ordinary graph it stands for (copies, each with its
+    pendant leaves), Algorithm 1 at copy c of class v (reach r_c, class sum R,
+    N vertices in the component) is bc_classes[v] plus the pairs the merged
+    traversal cannot see or sees at the mean reach R/k:
+      (r_c - R/k)(N - R)      sources outside the class, targets below c
+      (R - r_c)(r_c - 1)      class-mates' sides to the targets below c
+      (r_c - 1)(N - 2)        c's own leaves as sources
+      sum over open-twin neighbour classes u of (R_u^2 - sum r^2) / D_u
+    (D_u: original neighbours of a member of u)."""
+    r = gg.rng(seed + 60)
+    n = int(r.integers(2, 9))
+    g = gg.erdos_renyi(n, float(r.uniform(0.35, 0.9)), 5000 + seed)
+    members = []
+    for v in range(n):
+        k = int(r.integers(1, 4)) if r.uniform() < 0.6 else 1
+        if g.row_ptr[v + 1] == g.row_ptr[v]:
+            k = 1  # identical vertices share a neighbour (they lie in one block)
+        members.append([int(x) for x in r.integers(1, 5, size=k)])
+    twin_type = r.integers(1, 3, size=n)
+    x, off = expand_classes(n, g.row_ptr, g.col, members, twin_type)
+    want = oracle.bc(x, threads=2)
+    comp = gg.components(x)
+    ident = np.array([len(m) for m in members], dtype=np.int32)
+    rsum = np.array([sum(m) for m in members], dtype=np.int32)
+    got = oracle.bc_classes(n, g.row_ptr, g.col, rsum, ident, threads=2)
+    share = np.zeros(n)
+    for u in range(n):
+        if ident[u] >= 2 and twin_type[u] == 1:
+            nb = g.col[g.row_ptr[u]:g.row_ptr[u + 1]]
+            D = int(ident[nb].sum())
+            if D > 0:
+                share[nb] += (int(rsum[u]) ** 2 - sum(m * m for m in members[u])) / D
+    for v in range(n):
+        R, k = int(rsum[v]), int(ident[v])
+        for j, c in enumerate(range(off[v], off[v + 1])):
+            N = int(np.sum(comp == comp[c]))
+            rc = members[v][j]
+            pred = got[v] + (rc - R / k) * (N - R) + (R - rc) * (rc - 1) + (rc - 1) * (N - 2) + share[v]
+            assert abs(pred - want[c]) <= 1e-9 * max(1.0, abs(want[c])), (v, j, pred, want[c])
