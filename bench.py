@@ -306,7 +306,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat17", choices=sorted(WORKLOADS))
-    ap.add_argument("--ops", default="odai", help="preprocessing letters (o: per-piece BFS order, Section 4.1)")
+    ap.add_argument("--ops", default="odau",
+                    help="preprocessing letters (o: per-piece BFS order, Section 4.1; u: identical vertices "
+                         "merged whatever their reach)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -215,7 +215,12 @@ sbc_status sbc_graph_info(sbc_graph g, int32_t* n, int64_t* arcs);
  * the same step; Sections 3.2.1, 3.2.2, 3.4), 's' side vertices -- degree 1
  * to 4, neighbours pairwise adjacent (Sections 3.3.2, 3.4) -- removed one
  * after another from each piece, each leaving an Algorithm 3 search on the
- * piece as it was (a side piece), 'i' identical vertices (Section 3.3.3).
+ * piece as it was (a side piece), 'i' identical vertices (Section 3.3.3) of
+ * equal reach, 'u' identical vertices whatever their reach (a generalisation
+ * the paper leaves out: the class's traversal starts every member's
+ * dependency at the members' mean reach minus one and the host adds each
+ * member's difference from the mean, and the terms for pairs between members,
+ * to that member alone; 'u' includes 'i').
  * "" keeps every connected component whole.  st may be NULL.
  * Errors: SBC_E_INVALID_ARG for an unknown letter, SBC_E_TOO_LARGE. */
 sbc_status sbc_graph_preprocess(sbc_graph g, const char* ops, sbc_prep_stats* st);
@@ -227,7 +232,9 @@ sbc_status sbc_graph_export_sizes(sbc_graph g, int64_t* P, int64_t* V, int64_t* 
  * may be NULL to skip it):
  *   vtx_off[P+1]   piece p owns piece vertices [vtx_off[p], vtx_off[p+1])
  *   row[V+1]       absolute arc offsets; col[A] local (piece-relative) ids
- *   reach[V], ident[V]   Section 3.2 / 3.3.3 attributes
+ *   reach[V], ident[V]   Section 3.2 / 3.3.3 attributes of a piece vertex:
+ *                  ident = the identical vertices it stands for, reach = their
+ *                  reaches summed (ident x the common reach when they are equal)
  *   corr[V]        per-member terms added to each piece vertex's bc'
  *   bcx[n]         per-original-vertex terms closed in form on the host
  *   map_off[n+1], map_idx[M]   original v -> piece vertices (Eq. (5))
@@ -349,7 +356,9 @@ sbc_status sbc_single_source(sbc_context ctx, int32_t n, const int32_t* row_ptr,
  *   arcs           entries of col_dev (2 x edges)
  *   row_ptr_dev    device, n+1 int32 arc offsets (row_ptr_dev[0] = 0)
  *   col_dev        device, arcs int32 local neighbour ids (symmetric, loop-free)
- *   reach_dev, ident_dev  device, n int32 each (>= 1), or NULL for all ones
+ *   reach_dev, ident_dev  device, n int32 each (>= 1, reach x ident < 2^31),
+ *                  or NULL for all ones (a value out of range is reported in
+ *                  flags_dev)
  *   bc_dev         device, n doubles: receives bc'
  *   flags_dev      device, one int32 (or NULL): the run's device check flags,
  *                  0 when every check passed and every work item finished

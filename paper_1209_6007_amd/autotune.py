@@ -254,7 +254,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1209_6007_amd.autotune")
     ap.add_argument("--workload", default="rmat17", choices=sorted(gg.WORKLOADS))
     ap.add_argument("--mode", default="compressed", choices=["compressed", "plain"])
-    ap.add_argument("--ops", default="odai")
+    ap.add_argument("--ops", default="odau")
     ap.add_argument("--force", action="store_true")
     ap.add_argument("--cache")
     a = ap.parse_args(argv)

@@ -464,17 +464,17 @@ static sbc_status piece_problem(int32_t n, const int32_t* row_ptr, const int32_t
   if (rc != SBC_OK) return fail(rc, why);
   if (n < 1) return fail(SBC_E_INVALID_ARG, "empty piece");
   plain_problem(hg, out);
+  // Internally a piece vertex carries the reach of its members together:
+  // ident[v] members of reach reach[v] each.
   for (int32_t v = 0; v < n; ++v) {
-    if (reach) {
-      if (reach[v] < 1) return fail(SBC_E_INVALID_ARG, "reach must be >= 1");
-      out->reach[v] = reach[v];
-      if (reach[v] > 1) out->weighted = true;
-    }
-    if (ident) {
-      if (ident[v] < 1) return fail(SBC_E_INVALID_ARG, "ident must be >= 1");
-      out->ident[v] = ident[v];
-      if (ident[v] > 1) out->has_ident = true;
-    }
+    const int64_t r = reach ? reach[v] : 1, k = ident ? ident[v] : 1;
+    if (r < 1) return fail(SBC_E_INVALID_ARG, "reach must be >= 1");
+    if (k < 1) return fail(SBC_E_INVALID_ARG, "ident must be >= 1");
+    if (r * k > INT32_MAX) return fail(SBC_E_TOO_LARGE, "reach x ident exceeds 2^31 - 1");
+    out->reach[v] = (int32_t)(r * k);
+    out->ident[v] = (int32_t)k;
+    if (r > 1) out->weighted = true;
+    if (k > 1) out->has_ident = true;
   }
   return SBC_OK;
 }

@@ -539,6 +539,27 @@ __device__ __forceinline__ void pull_list(const int first, const int step, const
 // What the backward finish of entry (v, level) reads besides the pulled sum:
 // the lane's sigma of v (lanes outside the entry get 1), reach[v]-1 and
 // ident[v].
+//
+// Piece-vertex attributes: ident[v] members (identical vertices merged into
+// one, Section 3.3.3) whose reaches sum to reach[v].  A source's weight is
+// that sum (every member's hung vertices are sources alike), and the
+// dependency of v starts at the members' mean reach minus one (the targets
+// hung below a member): with equal reaches, reach[s] * ident[s] and
+// reach[v] - 1 of the per-member form; with unequal ones the host adds each
+// member's difference from the mean.
+template <bool REACH, bool IDENT>
+__device__ __forceinline__ double src_weight(const int32_t* __restrict__ rch, const int32_t* __restrict__ idn,
+                                             int32_t s) {
+  return REACH ? (double)rch[s] : (IDENT ? (double)idn[s] : 1.0);
+}
+template <bool REACH, bool IDENT>
+__device__ __forceinline__ double reach_m1(const int32_t* __restrict__ rch, const int32_t* __restrict__ idn,
+                                           int32_t v) {
+  if constexpr (!REACH) return 0.0;
+  else if constexpr (IDENT) return (double)rch[v] / (double)idn[v] - 1.0;
+  else return (double)(rch[v] - 1);
+}
+
 struct BackEarly {
   double sv, rm1, id;
 };
@@ -549,7 +570,7 @@ __device__ __forceinline__ BackEarly back_early(const double* __restrict__ sg, c
                                                 int lane) {
   BackEarly r;
   r.sv = ((amask >> lane) & 1) ? sg[(size_t)v * 64 + lane] : 1.0;
-  r.rm1 = REACH ? (double)(rch[v] - 1) : 0.0;
+  r.rm1 = reach_m1<REACH, IDENT>(rch, idn, v);
   r.id = IDENT ? (double)idn[v] : 1.0;
   return r;
 }
@@ -685,9 +706,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
     const bool side_item = P.nside && P.nside[W.piece] > 0;
     const int32_t srank = (side_item && lane < nsrc) ? s : -1;  // Algorithm 3 items: the source's removal rank
     if (lane < nsrc) {
-      wsrc = 1.0;
-      if (REACH) wsrc *= (double)rch[s];
-      if (IDENT) wsrc *= (double)idn[s];
+      wsrc = src_weight<REACH, IDENT>(rch, idn, s);
       if (wave == 0) {
         q[lane] = s;
         qm[lane] = 1ull << lane;
@@ -938,7 +957,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       // to bc'[v], summed per entry in LDS.
       auto pair_b = [&](int k, int, int32_t v, int32_t e0, int32_t e1, int j) {
         const double sv = sg[(size_t)v * 64 + j];
-        const double rm1 = REACH ? (double)(rch[v] - 1) : 0.0;
+        const double rm1 = reach_m1<REACH, IDENT>(rch, idn, v);
         const double id = IDENT ? (double)idn[v] : 1.0;
         const double acc = pair_sum<1>(col, e0, e1, np, br, sg, idn, false, j, Q.flags);
         const double dv = rm1 + sv * acc;
@@ -1226,9 +1245,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
     double wsrc = 0.0;
     const int32_t srank = (P.nside && P.nside[W.piece] > 0 && lane < nsrc) ? s : -1;  // Algorithm 3 items
     if (lane < nsrc) {
-      wsrc = 1.0;
-      if (REACH) wsrc *= (double)rch[s];
-      if (IDENT) wsrc *= (double)idn[s];
+      wsrc = src_weight<REACH, IDENT>(rch, idn, s);
       if (rank == 0 && wave == 0) {
         q[lane] = s;
         qm[lane] = 1ull << lane;
@@ -1739,7 +1756,7 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
         if (lane == 0) raise_flag(Q.flags, kFlagBadSource);
         continue;
       }
-      const double wsrc = (REACH ? (double)s_rch[s] : 1.0) * (IDENT ? (double)s_idn[s] : 1.0);
+      const double wsrc = src_weight<REACH, IDENT>(s_rch, s_idn, s);
       const int32_t srank = (P.nside && P.nside[W.piece] > 0) ? s : -1;  // Algorithm 3 items
       if (lane == 0) {
         d[s] = 0;
@@ -1831,7 +1848,7 @@ __global__ __launch_bounds__(WAVES * 64) void wave_kernel(DevPieces P, QueueArgs
             if (d[w] == l + 1) acc += sig[w];
           }
           const double sv = sig[v];
-          const double rm1 = REACH ? (double)(s_rch[v] - 1) : 0.0;
+          const double rm1 = reach_m1<REACH, IDENT>(s_rch, s_idn, v);
           const double dv = rm1 + sv * acc;
           if (side_absent(v, srank)) {
             sig[v] = 0.0;

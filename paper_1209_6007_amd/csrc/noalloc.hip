@@ -50,6 +50,23 @@ __global__ void noalloc_setup_kernel(int32_t n, int32_t nitems, WorkItem* items,
   }
 }
 
+// The traversal takes a piece vertex's reach as that of all its members
+// together: reach x ident when both are given.  A product beyond 2^31 - 1
+// (or a value below 1) is a bad item.
+__global__ void noalloc_reach_kernel(int32_t n, const int32_t* reach, const int32_t* ident, int32_t* out,
+                                     NoAllocCtl* ctl) {
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t r = reach[v], k = ident[v];
+    if (r < 1 || k < 1 || r * k > INT32_MAX) {
+      atomicOr(&ctl->flags, kFlagBadItem);
+      out[v] = 1;
+    } else {
+      out[v] = (int32_t)(r * k);
+    }
+  }
+}
+
 // The run's device flags for the caller; an item that never finished counts
 // as a bad item.
 __global__ void noalloc_finish_kernel(NoAllocCtl* ctl, int32_t nitems, int32_t* flags_out) {
@@ -109,6 +126,7 @@ extern "C" sbc_status sbc_piece_bc_noalloc(sbc_context ctx, int32_t n, int32_t a
   WorkItem* items = reinterpret_cast<WorkItem*>(take(sizeof(WorkItem) * (size_t)nitems));
   int32_t* vtx_off = reinterpret_cast<int32_t*>(take(2 * sizeof(int32_t)));
   int32_t* src_order = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n));
+  int32_t* reach_sum = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n));
   const size_t per_slot = align256((size_t)stride * 64 * 8) * 2 + align256((size_t)stride * 64 * 4) +
                           5 * align256((size_t)stride * 8) + align256((size_t)(stride + 3) * 4) +
                           align256((size_t)part_cap * 64 * 8);
@@ -146,10 +164,17 @@ extern "C" sbc_status sbc_piece_bc_noalloc(sbc_context ctx, int32_t n, int32_t a
   hipLaunchKernelGGL(noalloc_setup_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s,
                      n, nitems, items, vtx_off, src_order, ctl);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch setup");
+  const int32_t* reach_used = reach_dev;
+  if (reach_dev && ident_dev) {
+    hipLaunchKernelGGL(noalloc_reach_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0,
+                       s, n, reach_dev, ident_dev, reach_sum, ctl);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch reach");
+    reach_used = reach_sum;
+  }
   for (uint64_t* p : {ms.vis, ms.fa, ms.fb, ms.ba, ms.bb})
     if ((e = launch_fill_u64(p, 0, (int64_t)g * stride, s)) != hipSuccess) return hip_fail(e, "fill masks");
   if ((e = launch_fill_f64(bc_dev, 0.0, n, s)) != hipSuccess) return hip_fail(e, "fill output");
-  DevPieces dp{vtx_off, row_ptr_dev, col_dev, reach_dev, ident_dev, src_order, nullptr, bc_dev, 1, n, arcs, 0};
+  DevPieces dp{vtx_off, row_ptr_dev, col_dev, reach_used, ident_dev, src_order, nullptr, bc_dev, 1, n, arcs, 0};
   QueueArgs qa{items, nitems, kArgMagic, &ctl->head, &ctl->flags, &ctl->done};
   e = launch_ms(dp, qa, reach_dev != nullptr, ident_dev != nullptr, waves, eu, (int)g, ms, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "launch traversal");

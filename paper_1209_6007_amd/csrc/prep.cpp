@@ -149,6 +149,7 @@ struct OutPiece {
 struct Builder {
   const HostGraph& g;
   bool opi, op_side;
+  bool any_reach = false;  // identical vertices merge whatever their reach ('u')
   std::vector<double>& bcx;
   PrepStats* st;
   std::vector<OutPiece> out;
@@ -313,14 +314,14 @@ struct Builder {
           uint64_t ka = key(a), kb = key(b);
           if (ka != kb) return ka < kb;
           if (deg(a) != deg(b)) return deg(a) < deg(b);
-          if (p.reach[a] != p.reach[b]) return p.reach[a] < p.reach[b];
+          if (!any_reach && p.reach[a] != p.reach[b]) return p.reach[a] < p.reach[b];
           return a < b;
         });
         size_t i = 0;
         while (i < order.size()) {
           size_t j = i + 1;
           while (j < order.size() && key(order[j]) == key(order[i]) && deg(order[j]) == deg(order[i]) &&
-                 p.reach[order[j]] == p.reach[order[i]])
+                 (any_reach || p.reach[order[j]] == p.reach[order[i]]))
             ++j;
           if (j - i >= 2) {
             std::vector<int32_t> reps;
@@ -378,20 +379,29 @@ struct Builder {
       C = np;
       ctype.assign(np, 0);
     }
+    // A class stands for its members: ident = their number, reach = the sum
+    // of their reaches (k x r when all have reach r).
     OutPiece q;
     q.ident.assign(C, 0);
     q.reach.assign(C, 0);
     q.corr.assign(C, 0.0);
     std::vector<int32_t> rep(C, -1);
+    std::vector<int64_t> rsum(C, 0), rsq(C, 0), rlo(C, INT64_MAX), rhi(C, 0);
+    int64_t rtot = 0;  // the piece's sources weigh this much together
     for (int32_t v = 0; v < np; ++v) {
-      int32_t c = cls[v];
+      const int32_t c = cls[v];
+      const int64_t r = p.reach[v];
       q.ident[c]++;
-      q.reach[c] = (int32_t)p.reach[v];
+      rsum[c] += r;
+      rsq[c] += r * r;
+      rlo[c] = std::min(rlo[c], r);
+      rhi[c] = std::max(rhi[c], r);
+      rtot += r;
       if (rep[c] < 0) rep[c] = v;
     }
+    for (int32_t c = 0; c < C; ++c) q.reach[c] = (int32_t)rsum[c];
     // quotient CSR from the representatives' rows
     q.rp.assign(C + 1, 0);
-    std::vector<int32_t> tmp;
     for (int32_t c = 0; c < C; ++c) {
       int32_t v = rep[c];
       size_t base = q.cl.size();
@@ -403,34 +413,80 @@ struct Builder {
       q.cl.erase(std::unique(q.cl.begin() + base, q.cl.end()), q.cl.end());
       q.rp[c + 1] = (int32_t)q.cl.size();
     }
+    // Pairs the merged traversal no longer sees, per class of k >= 2 members
+    // a, b with reaches r_a, r_b (R = their sum):
+    //  (i) sources on member a's side (r_a of them) to targets hung strictly
+    //      below another member b pass b: b gets (R - r_b)(r_b - 1), which is
+    //      (k - 1) r (r - 1) when all reaches are r;
+    //  (ii) open-neighbourhood twins: the sum over a != b of r_a r_b pairs run
+    //      through the class's common neighbours, split evenly over the D
+    //      original neighbours of a member: each gets (R^2 - sum r^2) / D.
+    // With unequal reaches the traversal starts every member's dependency at
+    // the class's mean reach R/k minus one, so member b also gets
+    // (r_b - R/k) times the weight of every other source of the piece,
+    // (rtot - R), when the piece is traversed at all.
+    const bool traversed = C > 2;
+    std::vector<double> member_extra(np, 0.0);  // per-member terms of unequal classes
     for (int32_t c = 0; c < C; ++c) {
-      const double k = q.ident[c], r = q.reach[c];
+      const int32_t k = q.ident[c];
       if (k < 2) continue;
       st->twin_classes++;
       st->twins_merged += (int64_t)k - 1;
-      q.corr[c] += (k - 1) * r * (r - 1);
+      if (rlo[c] == rhi[c]) {
+        const double kk = k, r = (double)rlo[c];
+        q.corr[c] += (kk - 1) * r * (r - 1);
+      }
       if (ctype[c] == 1) {
         double D = 0;
         for (int32_t e = q.rp[c]; e < q.rp[c + 1]; ++e) D += q.ident[q.cl[e]];
         if (D > 0) {
-          const double share = k * (k - 1) * r * r / D;
+          double share;
+          if (rlo[c] == rhi[c]) {
+            const double kk = k, r = (double)rlo[c];
+            share = kk * (kk - 1) * r * r / D;
+          } else {
+            share = (double)(rsum[c] * rsum[c] - rsq[c]) / D;
+          }
           for (int32_t e = q.rp[c]; e < q.rp[c + 1]; ++e) q.corr[q.cl[e]] += share;
         }
       }
     }
+    for (int32_t v = 0; v < np; ++v) {
+      const int32_t c = cls[v];
+      if (q.ident[c] < 2 || rlo[c] == rhi[c]) continue;
+      const int64_t rb = p.reach[v], R = rsum[c];
+      member_extra[v] += (double)((R - rb) * (rb - 1));
+      if (traversed) member_extra[v] += ((double)rb - (double)R / (double)q.ident[c]) * (double)(rtot - R);
+    }
     q.member_orig = p.verts;
     q.member_cls = cls;
     if (C <= 2) {
-      // closed form of Algorithm 2 with ident weights on one or two vertices
+      // closed form of Algorithm 2 with ident weights on one or two vertices:
+      // the other class's sources (its reach sum) to the targets hung
+      // strictly below each member
       if (C == 2) {
-        const double kA = q.ident[0], rA = q.reach[0], kB = q.ident[1], rB = q.reach[1];
-        q.corr[1] += kA * rA * (rB - 1);
-        q.corr[0] += kB * rB * (rA - 1);
+        for (int32_t v = 0; v < np; ++v) {
+          const int32_t c = cls[v], o = 1 - c;
+          if (rlo[c] == rhi[c]) continue;
+          member_extra[v] += (double)rsum[o] * (double)(p.reach[v] - 1);
+        }
+        for (int32_t c = 0; c < 2; ++c) {
+          if (rlo[c] != rhi[c]) continue;
+          const int32_t o = 1 - c;
+          if (rlo[o] == rhi[o]) {
+            const double ko = q.ident[o], ro = (double)rlo[o];
+            q.corr[c] += ko * ro * ((double)rlo[c] - 1);
+          } else {
+            q.corr[c] += (double)rsum[o] * ((double)rlo[c] - 1);
+          }
+        }
       }
-      for (int32_t v = 0; v < np; ++v) bcx[p.verts[v]] += q.corr[cls[v]];
+      for (int32_t v = 0; v < np; ++v) bcx[p.verts[v]] += q.corr[cls[v]] + member_extra[v];
       st->tiny_pieces++;
       return;
     }
+    for (int32_t v = 0; v < np; ++v)
+      if (member_extra[v] != 0.0) bcx[p.verts[v]] += member_extra[v];
     out.push_back(std::move(q));
   }
 };
@@ -438,15 +494,16 @@ struct Builder {
 }  // namespace
 
 int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStats* st, std::string* why) {
-  bool opd = false, opa = false, opi = false, opo = false, op_side = false;
+  bool opd = false, opa = false, opi = false, opo = false, op_side = false, opu = false;
   for (char c : ops) {
     if (c == 'o') opo = true;
     else if (c == 'd') opd = true;
     else if (c == 'a' || c == 'b') opa = true;
     else if (c == 'i') opi = true;
+    else if (c == 'u') opi = opu = true;
     else if (c == 's') op_side = true;
     else {
-      *why = std::string("unknown preprocessing letter '") + c + "' (known: o, d, a, b, s, i)";
+      *why = std::string("unknown preprocessing letter '") + c + "' (known: o, d, a, b, s, i, u)";
       return SBC_E_INVALID_ARG;
     }
   }
@@ -523,6 +580,7 @@ int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStat
   st->ms_degree1 = t1 - t0;
 
   Builder B(g, opi, op_side, bcx, st);
+  B.any_reach = opu;
   std::vector<int32_t> eu, ev;
 
   if (opa) {
@@ -700,7 +758,7 @@ int preprocess(const HostGraph& g, const std::string& ops, Prepared* P, PrepStat
     st->piece_arcs += (int64_t)q.cl.size();
     st->work_teps += (double)(q.nside > 0 ? q.nside : C) * (double)q.cl.size() * 0.5;
     for (int32_t c = 0; c < C; ++c) {
-      if (q.reach[c] > 1) Q.weighted = true;
+      if (q.reach[c] > q.ident[c]) Q.weighted = true;  // some member hangs more than itself
       if (q.ident[c] > 1) Q.has_ident = true;
     }
   }

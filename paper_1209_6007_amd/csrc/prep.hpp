@@ -52,8 +52,8 @@ struct Prepared {
   std::vector<int32_t> vtx_off;  // P+1: piece p owns global piece vertices [vtx_off[p], vtx_off[p+1])
   std::vector<int32_t> row;      // V+1: absolute arc offsets into col
   std::vector<int32_t> col;      // A: local (piece-relative) neighbour ids
-  std::vector<int32_t> reach;    // V
-  std::vector<int32_t> ident;    // V
+  std::vector<int32_t> reach;    // V: reach of the piece vertex's members together (their sum)
+  std::vector<int32_t> ident;    // V: members (identical vertices merged into the piece vertex)
   std::vector<double> corr;      // V: per-member terms added to bc' of each piece vertex
   std::vector<double> bcx;       // n: per-original-vertex terms closed in form on the host
   std::vector<int32_t> map_off;  // n+1: original v maps to piece vertices map_idx[map_off[v]..]
@@ -71,7 +71,8 @@ struct Prepared {
 };
 
 // ops: any of 'd' (degree-1), 'a' (articulation / biconnected shattering),
-// 's' (side vertices), 'i' (identical vertices), applied in that order.  ""
+// 's' (side vertices), 'i' (identical vertices of equal reach), 'u'
+// (identical vertices whatever their reach), applied in that order.  ""
 // keeps each connected component whole.
 int preprocess(const HostGraph& g, const std::string& ops, Prepared* out, PrepStats* st, std::string* why);
 

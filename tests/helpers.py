@@ -150,16 +150,26 @@ def tree_closed_form(g: gg.Graph) -> np.ndarray:
     return out
 
 
-def assert_bc_close(got, want, rtol=1e-9, what=""):
-    """Per-vertex |g - o| <= rtol*|o|, and g == 0 exactly where o == 0."""
+def unequal_atol(n: int) -> float:
+    """Absolute slack for results with identical vertices of unequal reach
+    merged ('u'): a member's score is its class's traversal value (dependency
+    started at the members' mean reach) plus a signed per-member term, both of
+    magnitude up to n^2, so an exact 0 comes out within rounding of 0.  About
+    4 ulps of n^2; a wrong term is off by at least a fraction of one pair."""
+    return 1e-15 * float(n) * float(n)
+
+
+def assert_bc_close(got, want, rtol=1e-9, what="", atol=0.0):
+    """Per-vertex |g - o| <= rtol*|o| + atol; with atol = 0 (every term of a
+    score non-negative), g == 0 exactly where o == 0."""
     got = np.asarray(got, dtype=np.float64)
     want = np.asarray(want, dtype=np.float64)
     assert got.shape == want.shape, (got.shape, want.shape)
     zero = want == 0
-    bad_zero = np.flatnonzero(zero & (got != 0))
+    bad_zero = np.flatnonzero(zero & (np.abs(got) > atol))
     assert bad_zero.size == 0, f"{what}: nonzero where exact value is 0 at {bad_zero[:10]} -> {got[bad_zero[:10]]}"
     err = np.abs(got - want)
-    tol = rtol * np.abs(want)
+    tol = rtol * np.abs(want) + atol
     bad = np.flatnonzero(err > tol)
     assert bad.size == 0, (f"{what}: {bad.size} vertices off; worst rel "
                            f"{np.max(err[~zero] / np.abs(want[~zero])) if (~zero).any() else 0:.3e} at "
@@ -172,6 +182,24 @@ def member_reach(ex):
     r, k = ex["reach"].astype(np.int64), ex["ident"].astype(np.int64)
     assert np.all(r % k == 0), "a piece vertex merges members of unequal reach"
     return (r // k).astype(np.int32)
+
+
+def oracle_pieces(ex, threads=None):
+    """bc' of every exported piece by the oracle: Algorithm 2 with ident
+    weights (oracle.bc_pieces) where every class has members of one reach,
+    oracle.bc_classes for the pieces holding a class of unequal reaches."""
+    import oracle
+
+    r, k = ex["reach"].astype(np.int64), ex["ident"].astype(np.int64)
+    even = r % k == 0
+    bcp = oracle.bc_pieces(ex["vtx_off"], ex["row"], ex["col"], np.where(even, r // k, 1).astype(np.int32),
+                           ex["ident"], threads=threads)
+    for p in np.unique(np.searchsorted(ex["vtx_off"], np.flatnonzero(~even), side="right") - 1):
+        vb, ve = int(ex["vtx_off"][p]), int(ex["vtx_off"][p + 1])
+        rp = (ex["row"][vb:ve + 1] - ex["row"][vb]).astype(np.int32)
+        cl = ex["col"][ex["row"][vb]:ex["row"][ve]].astype(np.int32)
+        bcp[vb:ve] = oracle.bc_classes(ve - vb, rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve], threads=threads)
+    return bcp
 
 
 def piece_csr(ex, p):

@@ -9,7 +9,7 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_1209_6007_amd as sbc
-from tests.helpers import assert_bc_close
+from tests.helpers import assert_bc_close, unequal_atol
 
 pytestmark = pytest.mark.gpu
 RTOL = 1e-9
@@ -167,14 +167,22 @@ SMALL = {
 
 
 @pytest.mark.parametrize("name", list(SMALL))
-@pytest.mark.parametrize("mode", ["plain", "compressed", "compressed-side"])
+@pytest.mark.parametrize("mode", ["plain", "compressed", "compressed-side", "compressed-unequal"])
 def test_whole_graph(ctx, name, mode):
-    """Plain, compressed ("dai") and compressed with side vertices ("odasi":
-    Algorithm 3 items beside Algorithm 2 items) against the oracle."""
+    """Plain, compressed ("dai"), compressed with side vertices ("odasi":
+    Algorithm 3 items beside Algorithm 2 items) and with identical vertices
+    merged whatever their reach ("odau") against the oracle."""
     g = SMALL[name]()
     print(f"graph {name} n={g.n} m={g.m} mode={mode}", flush=True)
     want = oracle.bc(g)
-    got = run(ctx, g, "compressed", "odasi") if mode == "compressed-side" else run(ctx, g, mode)
+    if mode == "compressed-side":
+        got = run(ctx, g, "compressed", "odasi")
+    elif mode == "compressed-unequal":
+        got = run(ctx, g, "compressed", "odau")
+        assert_bc_close(got, want, RTOL, f"{name}/{mode}", atol=unequal_atol(g.n))
+        return
+    else:
+        got = run(ctx, g, mode)
     assert_bc_close(got, want, RTOL, f"{name}/{mode}")
 
 
@@ -241,6 +249,7 @@ def test_decorated_random(ctx, seed):
         assert_bc_close(run(ctx, g, mode), want, RTOL, f"seed={seed}/{mode}")
     assert_bc_close(run(ctx, g, "compressed", "odasi"), want, RTOL, f"seed={seed}/odasi")
     assert_bc_close(run(ctx, g, "compressed+deterministic", "odasi"), want, RTOL, f"seed={seed}/odasi deterministic")
+    assert_bc_close(run(ctx, g, "compressed", "odasu"), want, RTOL, f"seed={seed}/odasu", atol=unequal_atol(g.n))
 
 
 def test_source_subset(ctx):

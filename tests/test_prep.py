@@ -15,10 +15,11 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_1209_6007_amd as sbc
-from tests.helpers import assert_bc_close, map_back
+from tests.helpers import assert_bc_close, map_back, member_reach
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-OPS = ["", "d", "a", "i", "da", "di", "ai", "dai", "o", "odai", "s", "ds", "as", "si", "dasi", "odasi"]
+OPS = ["", "d", "a", "i", "da", "di", "ai", "dai", "o", "odai", "s", "ds", "as", "si", "dasi", "odasi",
+       "u", "du", "dau", "odau", "dasu"]
 
 
 def setup_module(_m):
@@ -119,22 +120,22 @@ def compressed_via_oracle(g, ops, check_invariants=True):
         if k > 0:  # a side piece: Algorithm 3 for its side vertices 0..k-1, in that order
             assert "s" in ops and np.all(ex["ident"][vb:ve] == 1)
             bcp[vb:ve] = oracle.bc_side(np_, rp, cl, ex["reach"][vb:ve], np.arange(k, dtype=np.int32), threads=2)
-        else:
-            bcp[vb:ve] = oracle.bc_weighted(np_, rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve], threads=2)
+        else:  # reach: the members' reach sum
+            bcp[vb:ve] = oracle.bc_classes(np_, rp, cl, ex["reach"][vb:ve], ex["ident"][vb:ve], threads=2)
     out = ex["bcx"].copy()
     for v in range(g.n):
         for j in range(ex["map_off"][v], ex["map_off"][v + 1]):
             x = ex["map_idx"][j]
             out[v] += bcp[x] + ex["corr"][x]
     if check_invariants and len(ex["vtx_off"]) > 1 and "s" not in ops:
-        # every piece represents its whole component: sum of reach*ident = component size
+        # every piece represents its whole component: its reach sums = component size
         owner = {}
         for v in range(g.n):
             for j in range(ex["map_off"][v], ex["map_off"][v + 1]):
                 owner[int(ex["map_idx"][j])] = v
         for p in range(len(ex["vtx_off"]) - 1):
             vb, ve = ex["vtx_off"][p], ex["vtx_off"][p + 1]
-            tot = int(np.sum(ex["reach"][vb:ve].astype(np.int64) * ex["ident"][vb:ve]))
+            tot = int(np.sum(ex["reach"][vb:ve].astype(np.int64)))
             some = owner[int(vb)]
             assert tot == int(np.sum(comp == comp[some])), (p, tot)
     return out, st
@@ -144,7 +145,7 @@ def compressed_via_oracle(g, ops, check_invariants=True):
 def test_exhaustive_six_vertex_graphs_every_ops(ops):
     """Every labelled graph on 6 vertices (sampled 1 in 4 for the full sweep)."""
     pairs = [(i, j) for i in range(6) for j in range(i + 1, 6)]
-    step = 1 if ops in ("dai", "dasi") else 4
+    step = 1 if ops in ("dai", "dasi", "dau") else 4
     for mask in range(0, 1 << 15, step):
         es = [pairs[b] for b in range(15) if (mask >> b) & 1]
         u = np.array([e[0] for e in es], dtype=np.int64)
@@ -207,9 +208,37 @@ def test_workload_shapes_small(name):
     else:
         g = gg.random_tree(300, 8)
     want = oracle.bc(g)
-    for ops in ("d", "da", "dai", "ai", "odai", "odasi", "s"):
+    for ops in ("d", "da", "dai", "ai", "odai", "odasi", "s", "odau", "dasu"):
         got, st = compressed_via_oracle(g, ops)
         assert_bc_close(got, want, 1e-9, f"{name} ops={ops}")
+
+
+def test_unequal_reach_twins_merge_more():
+    """'u' merges the identical vertices that stripping left with different
+    reach, which 'i' keeps apart: fewer piece vertices, the same result."""
+    g = gg.rmat_decorated(scale=10, seed=12)
+    want = oracle.bc(g)
+    got_i, st_i = compressed_via_oracle(g, "odai")
+    got_u, st_u = compressed_via_oracle(g, "odau")
+    assert st_u["twins_merged"] > st_i["twins_merged"] and st_u["piece_vertices"] < st_i["piece_vertices"]
+    assert_bc_close(got_u, want, 1e-9, "odau")
+    assert_bc_close(got_i, want, 1e-9, "odai")
+
+
+def test_worked_example_twins_of_unequal_reach():
+    """C4 a-x-b-y with two pendants p, q on x: after stripping, x and y are
+    open twins of reach 3 and 1, merged by 'u' only.  Pair by pair (ordered):
+    x = 15 (p and q to each other and to a, b, y, both ways: 14; half of
+    a<->b: 1), y = 1 (the other half), a = b = 3 (half of the pairs between
+    y and x, p, q, both ways)."""
+    # a=0, x=1, b=2, y=3, pendants 4, 5 on x
+    g = gg.csr_from_edges(6, np.array([0, 1, 2, 3, 1, 1]), np.array([1, 2, 3, 0, 4, 5]))
+    want = oracle.bc(g)
+    got_u, st_u = compressed_via_oracle(g, "dau")
+    got_i, st_i = compressed_via_oracle(g, "dai")
+    assert st_u["twin_classes"] >= 1 and st_i["twin_classes"] < st_u["twin_classes"]
+    np.testing.assert_array_equal(want, [3, 15, 3, 1, 0, 0])
+    assert_bc_close(got_u, want, 1e-12, "dau")
 
 
 @pytest.mark.parametrize("name", ["blocks", "rmat"])
@@ -224,7 +253,7 @@ def test_bc_pieces_mapped_back_is_the_oracle(name):
         ex = sbc.sbc_graph_export(h)
     finally:
         sbc.sbc_graph_destroy(h)
-    bcp = oracle.bc_pieces(ex["vtx_off"], ex["row"], ex["col"], ex["reach"], ex["ident"], threads=4)
+    bcp = oracle.bc_pieces(ex["vtx_off"], ex["row"], ex["col"], member_reach(ex), ex["ident"], threads=4)
     assert_bc_close(map_back(ex, bcp), oracle.bc(g), 1e-9, name)
 
 
