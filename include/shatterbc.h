@@ -147,6 +147,10 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        at most this many of the batch's sources as (entry,
  *                        source) pairs, one per lane (default 16, 0..64; 0: one
  *                        wave per entry always)
+ *   "batch_compact"      1 (default): the batch kernel keeps an entry's path counts and
+ *                        coefficients together, one value per lane the entry holds,
+ *                        so a pull of a few-lane entry reads one sector; 0: one
+ *                        64-value row per vertex (the team kernel's layout)
  *   "deep_min_levels"    pieces whose breadth-first depth from their highest-degree
  *                        vertex exceeds this (default 64; 0: never) run on the
  *                        batch kernel in a launch of their own (class 3)

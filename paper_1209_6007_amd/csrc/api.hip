@@ -97,6 +97,7 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "slots") return &p.slots;
   if (k == "cluster_sources") return &p.cluster_sources;
   if (k == "batch_pairs") return &p.batch_pairs;
+  if (k == "batch_compact") return &p.batch_compact;
   if (k == "deep_min_levels") return &p.deep_min_levels;
   if (k == "deep_wg_waves") return &p.deep_wg_waves;
   if (k == "deep_waves_per_eu") return &p.deep_waves_per_eu;
@@ -134,6 +135,7 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "team_count") ok = value >= 1 && value <= 1024;
   if (k == "cluster_sources") ok = value >= 0 && value <= 2;
   if (k == "batch_pairs") ok = value >= 0 && value <= 64;
+  if (k == "batch_compact") ok = value == 0 || value == 1;
   if (k == "team_spin_ms") ok = value <= 600000;
   if (k == "team_local_fences") ok = value == 0 || value == 1;
   if (k == "team_cooperative") ok = value == 0 || value == 1;

@@ -82,6 +82,12 @@ struct MsState {
   int32_t* lvl;    // [slots][stride+3]   level starts in q
   double* part;    // [slots][part_cap*64] partial sums of split high-degree rows
   uint64_t* prof;  // [slots][kProfCounters] phase timers, or null
+  // Compact value layout of the batch kernel (null: sg holds 64-lane rows):
+  // an entry's values, one per lane of its mask, lie together in sg at
+  // eoff[entry], and ob holds per vertex the offset of its entry on the level
+  // of each parity that is being read.
+  int32_t* eoff;   // [slots][stride*64]  per entry: offset of its values in sg
+  int32_t* ob;     // [slots][2*stride]   per level parity and vertex: offset of the vertex's entry
   int64_t stride;
   int32_t part_cap;
   int32_t pairs;   // batch kernel: entries with short rows and at most this many lanes are pulled as

@@ -74,22 +74,31 @@ int occ_wave_w(size_t dyn) {
   return nb;
 }
 
-template <int WAVES, int EU, bool D>
-hipError_t launch_ms_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
+template <int WAVES, int EU, bool D, bool C>
+hipError_t launch_ms_c(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
                        const DumpOut& dump, hipStream_t stream) {
   (void)hipGetLastError();
   if (r && i)
-    hipLaunchKernelGGL((ms_kernel<WAVES, EU, true, true, D>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st, dump);
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, true, true, D, C>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
+                       dump);
   else if (r)
-    hipLaunchKernelGGL((ms_kernel<WAVES, EU, true, false, D>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, true, false, D, C>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
                        dump);
   else if (i)
-    hipLaunchKernelGGL((ms_kernel<WAVES, EU, false, true, D>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, false, true, D, C>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
                        dump);
   else
-    hipLaunchKernelGGL((ms_kernel<WAVES, EU, false, false, D>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
+    hipLaunchKernelGGL((ms_kernel<WAVES, EU, false, false, D, C>), dim3(grid), dim3(WAVES * 64), 0, stream, P, Q, st,
                        dump);
   return hipGetLastError();
+}
+
+// The compact value layout runs when the state carries its offset arrays.
+template <int WAVES, int EU, bool D>
+hipError_t launch_ms_w(const DevPieces& P, const QueueArgs& Q, bool r, bool i, int grid, const MsState& st,
+                       const DumpOut& dump, hipStream_t stream) {
+  if (st.eoff && st.ob) return launch_ms_c<WAVES, EU, D, true>(P, Q, r, i, grid, st, dump, stream);
+  return launch_ms_c<WAVES, EU, D, false>(P, Q, r, i, grid, st, dump, stream);
 }
 
 // The dump variants are built at the compiler's default occupancy only.

@@ -309,6 +309,96 @@ __device__ __forceinline__ void pull_group(const int32_t* __restrict__ col, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compact value layout (batch kernel).  Deep and sparse pieces give a batch
+// many (vertex, level) entries per vertex with a few lanes each; in 64-lane
+// rows every such lane's value costs its own memory sector.  In the compact
+// layout entry e's values lie together, lane j of mask m at
+// eoff[e] + lane_rank(m, j), and a neighbour u on the level being read is
+// found through ob[u], the offset of u's entry on that level.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_rank(uint64_t m, int j) { return __builtin_popcountll(m & ((1ull << j) - 1)); }
+
+// pull_group<1> / pull_row for the compact layout: the neighbour's full
+// lane mask and its entry offset are gathered together, and lane j of the
+// wave reads value rank_j of the neighbour's entry.
+// The sum continues from acc in the order pull_group and pull_row use (four
+// neighbours' values added pairwise, then to the running sum), so both
+// layouts give the same bits.
+__device__ __forceinline__ double pull_short_c(const int32_t* __restrict__ col, int32_t e0, int32_t deg, int32_t np,
+                                               uint64_t* __restrict__ mk, const int32_t* __restrict__ ob,
+                                               const uint64_t need, const double* __restrict__ sg,
+                                               const int32_t* __restrict__ idn, const bool scale, const int lane,
+                                               int32_t* flags, double acc) {
+  int32_t c = -1, o = 0;
+  uint64_t mf = 0;
+  if (lane < deg) {
+    c = col_load(&col[e0 + lane]);
+    if (c < 0 || c >= np) {
+      raise_flag(flags, kFlagBadArc);
+      c = -1;
+    } else {
+      mf = group_load(&mk[c]);
+      o = ob[c];
+    }
+  }
+  uint64_t act = __ballot((mf & need) != 0);
+  constexpr int kPer = 4;  // rows in flight
+  static_assert(kPer == kPullUnroll, "the row layout's pull adds four at a time");
+  while (act) {  // wave-uniform
+    double x[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      x[j] = 0.0;
+      if (act) {  // wave-uniform
+        const int k = __builtin_ctzll(act);
+        act &= act - 1;
+        const int32_t u = __builtin_amdgcn_readlane(c, k);
+        const uint64_t mu = readlane64(mf, k);
+        const int32_t ou = __builtin_amdgcn_readlane(o, k);
+        if (((mu & need) >> lane) & 1) x[j] = row_load(&sg[(size_t)ou + lane_rank(mu, lane)]);
+        if (scale) x[j] *= (double)idn[u];
+      }
+    }
+    acc += (x[0] + x[1]) + (x[2] + x[3]);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double pull_row_c(const int32_t* __restrict__ col, int32_t e0, int32_t e1, int32_t np,
+                                             uint64_t* __restrict__ mk, const int32_t* __restrict__ ob,
+                                             const uint64_t need, const double* __restrict__ sg,
+                                             const int32_t* __restrict__ idn, const bool scale, const int lane,
+                                             int32_t* flags) {
+  double acc = 0.0;
+  for (int32_t eb = e0; eb < e1; eb += 64)
+    acc = pull_short_c(col, eb, min(64, e1 - eb), np, mk, ob, need, sg, idn, scale, lane, flags, acc);
+  return acc;
+}
+
+// pair_sum for the compact layout.
+__device__ __forceinline__ double pair_sum_c(const int32_t* __restrict__ col, int32_t e0, int32_t e1, int32_t np,
+                                             uint64_t* __restrict__ mk, const int32_t* __restrict__ ob,
+                                             const double* __restrict__ sg, const int32_t* __restrict__ idn,
+                                             bool scale, int j, int32_t* flags) {
+  double acc = 0.0;
+  for (int32_t e = e0; e < e1; ++e) {
+    int32_t u = col_load(&col[e]);
+    if (u < 0 || u >= np) {
+      raise_flag(flags, kFlagBadArc);
+      continue;
+    }
+    const uint64_t m = group_load(&mk[u]);
+    const int32_t o = ob[u];
+    if ((m >> j) & 1) {
+      double x = row_load(&sg[(size_t)o + lane_rank(m, j)]);
+      if (scale) x *= (double)idn[u];
+      acc += x;
+    }
+  }
+  return acc;
+}
+
 // One wave's pull of the entries [i0, min(i0 + G, iend)) of the queue q.
 // need_of(i, v) gives an entry's lanes; defer(i, v, e0, e1, need) takes a row
 // the caller splits over many waves and returns true (it must be
@@ -440,6 +530,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 // first + (n-1)*step of the queue q, with the callbacks of pull_entries and
 // early(i, v, need), whose result finish gets as a fifth argument: the loads
 // an entry's finish needs are issued before its pull, not after it.
+// pull(e0, e1, need) is the wave's sum over the row for the entry's lanes.
 // Lane k first gathers entry k's vertex, row bounds and lanes into the
 // wave's slots: one round of loads for all n entries, where an entry alone
 // costs three dependent rounds (queue slot, then row bounds, then lanes).
@@ -451,14 +542,13 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 // lane counts), lane t takes pairs t, t+64, ..., finds its entry by binary
 // search and its lane j as the entry's r-th lane, and calls pair(k, i, v, e0,
 // e1, j).  Then lane k calls pair_done(k, i, v, need) for each such entry k.
-template <typename NeedOf, typename Defer, typename Early, typename Finish, typename Pair, typename PairDone>
+template <typename NeedOf, typename Defer, typename Early, typename Finish, typename Pair, typename PairDone,
+          typename Pull>
 __device__ __forceinline__ void pull_list(const int first, const int step, const int n, const EntrySlots& sl,
                                           const int32_t* __restrict__ q, const int32_t* __restrict__ rowp,
-                                          const int32_t np, const int32_t narcs, const int32_t* __restrict__ col,
-                                          uint64_t* __restrict__ mk, const double* __restrict__ sg,
-                                          const int32_t* __restrict__ idn, const bool scale, const int lane,
-                                          int32_t* flags, NeedOf need_of, Defer defer, Early early,
-                                          Finish finish, const int pairs, Pair pair, PairDone pair_done) {
+                                          const int32_t np, const int32_t narcs, const int lane, int32_t* flags,
+                                          NeedOf need_of, Defer defer, Early early, Finish finish, const int pairs,
+                                          Pair pair, PairDone pair_done, Pull pull) {
   if (lane < n) {
     const int i = first + lane * step;
     int32_t v = q[i], e0 = 0, e1 = 0;
@@ -521,16 +611,7 @@ __device__ __forceinline__ void pull_list(const int first, const int step, const
     if (pairs > 0 && pair_entry(e0, e1, need, pairs)) continue;  // done as pairs
     if (defer(i, v, e0, e1, need)) continue;
     const auto pre = early(i, v, need);
-    double acc;
-    if (e1 - e0 <= 64) {
-      const int32_t a[1] = {e0}, d[1] = {e1 - e0};
-      const uint64_t nd[1] = {need};
-      double r[1];
-      pull_group<1>(col, a, d, np, mk, nd, sg, idn, scale, lane, flags, r);
-      acc = r[0];
-    } else {
-      acc = pull_row(col, e0, e1, np, mk, need, sg, idn, scale, lane, flags);
-    }
+    const double acc = pull(e0, e1, need);
     finish(i, v, need, acc, pre);
   }
   wave_sync();  // every lane has read the slots before the wave's next list fills them
@@ -564,6 +645,18 @@ struct BackEarly {
   double sv, rm1, id;
 };
 
+// idx: where the lane's value of the entry lies in sg.
+template <bool REACH, bool IDENT>
+__device__ __forceinline__ BackEarly back_early_at(const double* __restrict__ sg, size_t idx,
+                                                   const int32_t* __restrict__ rch, const int32_t* __restrict__ idn,
+                                                   int32_t v, uint64_t amask, int lane) {
+  BackEarly r;
+  r.sv = ((amask >> lane) & 1) ? sg[idx] : 1.0;
+  r.rm1 = reach_m1<REACH, IDENT>(rch, idn, v);
+  r.id = IDENT ? (double)idn[v] : 1.0;
+  return r;
+}
+
 template <bool REACH, bool IDENT>
 __device__ __forceinline__ BackEarly back_early(const double* __restrict__ sg, const int32_t* __restrict__ rch,
                                                 const int32_t* __restrict__ idn, int32_t v, uint64_t amask,
@@ -592,6 +685,29 @@ __device__ __forceinline__ double side_contrib(double wsrc, double dv, double rm
 // wave's contribution to bc'[v] (weighted by ident[s]*reach[s] in wsrc) and
 // the level's backward mask.  drow, when not null, is the lane's row of the
 // dependency dump; srank is the lane's side rank (-1 outside side pieces).
+__device__ __forceinline__ void back_finish_at(double* __restrict__ sg, size_t idx, double* __restrict__ bcp,
+                                               uint64_t* __restrict__ bw, int32_t v, uint64_t amask, double acc,
+                                               const BackEarly& pre, double wsrc, int lane, int32_t* flags,
+                                               double* drow, int32_t srank) {
+  double contrib = 0.0;
+  if ((amask >> lane) & 1) {
+    const double dv = pre.rm1 + pre.sv * acc;
+    if (side_absent(v, srank)) {
+      sg[idx] = 0.0;
+    } else {
+      sg[idx] = pre.id * (1.0 + dv) / pre.sv;
+      contrib = side_contrib(wsrc, dv, pre.rm1, srank);
+    }
+    if (drow) drow[v] = dv;
+    if (!(pre.sv <= DBL_MAX) || !(dv <= DBL_MAX)) raise_flag(flags, kFlagSigmaOverflow);
+  }
+  contrib = wave_sum(contrib);
+  if (lane == 0) {
+    atomicAdd(&bcp[v], contrib);
+    bw[v] = amask;
+  }
+}
+
 __device__ __forceinline__ void back_finish(double* __restrict__ sg, double* __restrict__ bcp,
                                             uint64_t* __restrict__ bw, int32_t v, uint64_t amask, double acc,
                                             const BackEarly& pre, double wsrc, int lane, int32_t* flags,
@@ -620,7 +736,7 @@ __device__ __forceinline__ void back_finish(double* __restrict__ sg, double* __r
 // waves in flight can matter more than registers.
 // DUMP builds the verification variant: it also writes every source's
 // levels, path counts and dependencies to `dump` (null otherwise).
-template <int WAVES, int EU, bool REACH, bool IDENT, bool DUMP = false>
+template <int WAVES, int EU, bool REACH, bool IDENT, bool DUMP = false, bool CMP = false>
 __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueArgs Q, MsState st, DumpOut dump) {
   if (Q.magic != kArgMagic) return;
   constexpr int BLOCK = WAVES * 64;
@@ -656,6 +772,16 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
   int32_t* lvl = st.lvl + slot * (size_t)(st.stride + 3);
   double* part = st.part + slot * (size_t)st.part_cap * 64;
   const int64_t qcap = st.stride * 64;
+  // Compact layout (CMP): per-entry value offsets, and per level parity and
+  // vertex the offset of the vertex's entry on the level being read.
+  int32_t* eoff = CMP ? st.eoff + slot * (size_t)st.stride * 64 : nullptr;
+  int32_t* ob2 = CMP ? st.ob + slot * (size_t)st.stride * 2 : nullptr;
+  auto obp = [&](int lev) -> int32_t* { return ob2 + (size_t)(lev & 1) * st.stride; };
+  // Where entry i's (vertex v, lanes m) value for lane j lies in sg.
+  auto own = [&](int i, int32_t v, uint64_t m, int j) -> size_t {
+    if constexpr (CMP) return (size_t)eoff[i] + lane_rank(m, j);
+    else return (size_t)v * 64 + j;
+  };
   const int32_t narcs = P.narcs;
   // Phase timers: thread 0 charges the wall-clock time since its last mark to
   // one counter of this slot.
@@ -712,7 +838,13 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         qm[lane] = 1ull << lane;
         bufa[s] = 1ull << lane;
         vis[s] = 1ull << lane;
-        sg[(size_t)s * 64 + lane] = 1.0;
+        if constexpr (CMP) {  // level 0: entry j holds lane j alone
+          eoff[lane] = lane;
+          obp(0)[s] = lane;
+          sg[lane] = 1.0;
+        } else {
+          sg[(size_t)s * 64 + lane] = 1.0;
+        }
       }
     }
     if (wave == 0) {
@@ -730,6 +862,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
     uint64_t* fcur = bufa;
     uint64_t* fnxt = bufb;
     int qs = 0, qe = nsrc, L = 0;
+    int64_t cbase = nsrc;  // compact layout: values placed so far
     // ---------------- forward sweep ----------------
     while (true) {
       if (tid == 0) {
@@ -793,6 +926,33 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       const int nt = (int)min((int64_t)(qe + s_cnt[L % 3]), qcap);
       mark(kProfPhaseA);
       if (nt == qe) break;
+      if constexpr (CMP) {
+        // Level L+1's entries get their value offsets: their lane counts, scanned.
+        int32_t* obn = obp(L + 1);
+        for (int cb = qe; cb < nt; cb += BLOCK) {
+          const int i = cb + tid;
+          int cnt = 0;
+          int32_t w = -1;
+          if (i < nt) {
+            w = q[i];
+            if (w >= 0 && w < np) cnt = __builtin_popcountll(group_load(&fnxt[w]));
+            else w = -1;
+          }
+          int total;
+          const int ex = block_excl_scan<BLOCK>(cnt, s_wtot, &total);
+          if (i < nt) {
+            // Each (vertex, lane) is reached once, so the values of a batch
+            // fit the slot's stride*64; a run that would not is reported.
+            const int64_t o = cbase + ex;
+            const int32_t at = o + cnt <= qcap ? (int32_t)o : 0;
+            if (o + cnt > qcap) raise_flag(Q.flags, kFlagQueueOverflow);
+            eoff[i] = at;
+            if (w >= 0) obn[w] = at;
+          }
+          cbase += total;
+        }
+        __syncthreads();
+      }
       // Phase B: sigma of the new lanes, one wave per vertex, pulling from the
       // neighbours on level L (their frontier masks); long rows are deferred.
       const bool scale = IDENT && L > 0;
@@ -817,18 +977,32 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       // The new lanes are marked visited in phase C, all entries at once.
       auto early_f = [](int, int32_t, uint64_t) { return 0; };
       auto finish_f = [&](int i, int32_t w, uint64_t need, double acc, int) {
-        if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+        if ((need >> lane) & 1) sg[own(i, w, need, lane)] = acc;
         if (lane == 0) qm[i] = need;
       };
+      const int32_t* obL = CMP ? obp(L) : nullptr;  // compact: offsets of level L's entries
       // Pair (w, lane j): sigma of w for source j from the neighbours on level L.
-      auto pair_f = [&](int, int, int32_t w, int32_t e0, int32_t e1, int j) {
-        const double acc = pair_sum<1>(col, e0, e1, np, fcur, sg, idn, scale, j, Q.flags);
-        sg[(size_t)w * 64 + j] = acc;
+      auto pair_f = [&](int k, int i, int32_t w, int32_t e0, int32_t e1, int j) {
+        double acc;
+        if constexpr (CMP) acc = pair_sum_c(col, e0, e1, np, fcur, obL, sg, idn, scale, j, Q.flags);
+        else acc = pair_sum<1>(col, e0, e1, np, fcur, sg, idn, scale, j, Q.flags);
+        sg[own(i, w, slots.need[k], j)] = acc;
       };
       auto pair_done_f = [&](int, int i, int32_t, uint64_t need) { qm[i] = need; };
+      auto pull_f = [&](int32_t e0, int32_t e1, uint64_t need) -> double {
+        if constexpr (CMP) return pull_row_c(col, e0, e1, np, fcur, obL, need, sg, idn, scale, lane, Q.flags);
+        if (e1 - e0 <= 64) {
+          const int32_t a[1] = {e0}, d[1] = {e1 - e0};
+          const uint64_t nd[1] = {need};
+          double r[1];
+          pull_group<1>(col, a, d, np, fcur, nd, sg, idn, scale, lane, Q.flags, r);
+          return r[0];
+        }
+        return pull_row(col, e0, e1, np, fcur, need, sg, idn, scale, lane, Q.flags);
+      };
       for (int first = qe + wave; first < nt; first += WAVES * 64)
-        pull_list(first, WAVES, min(64, (nt - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, fcur, sg,
-                  idn, scale, lane, Q.flags, need_f, defer_long, early_f, finish_f, pairs, pair_f, pair_done_f);
+        pull_list(first, WAVES, min(64, (nt - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, lane, Q.flags,
+                  need_f, defer_long, early_f, finish_f, pairs, pair_f, pair_done_f, pull_f);
       __syncthreads();
       mark(kProfPhaseB);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -845,7 +1019,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
             const int32_t a = e0 + sl * kSliceArcs;
             const int32_t b = min(e1, a + kSliceArcs);
             part[(size_t)(s_hoff[h] + sl) * 64 + lane] =
-                pull_row(col, a, b, np, fcur, need, sg, idn, scale, lane, Q.flags);
+                CMP ? pull_row_c(col, a, b, np, fcur, obL, need, sg, idn, scale, lane, Q.flags)
+                    : pull_row(col, a, b, np, fcur, need, sg, idn, scale, lane, Q.flags);
           }
         }
         __syncthreads();
@@ -859,7 +1034,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
-          if ((need >> lane) & 1) sg[(size_t)w * 64 + lane] = acc;
+          if ((need >> lane) & 1) sg[own(i, w, need, lane)] = acc;
           if (lane == 0) qm[i] = need;
         }
         __syncthreads();
@@ -906,7 +1081,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           if (v >= 0 && v < np && lane < nsrc && ((m >> lane) & 1)) {
             const size_t o = (size_t)(W.s0 + lane) * dump.np + v;
             dump.dist[o] = l;
-            dump.sigma[o] = sg[(size_t)v * 64 + lane];
+            dump.sigma[o] = sg[own(i, v, m, lane)];
           }
         }
       __syncthreads();
@@ -921,6 +1096,16 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           const int32_t u = q[i];
           if (u >= 0 && u < np) bw[u] = 0;
         }
+      const int32_t* obR = CMP ? obp(l + 1) : nullptr;  // compact: offsets of level l+1's entries
+      if constexpr (CMP) {
+        if (l + 1 <= Lmax) {
+          int32_t* obw = obp(l + 1);
+          for (int i = lvl[l + 1] + tid; i < lvl[l + 2]; i += BLOCK) {
+            const int32_t u = q[i];
+            if (u >= 0 && u < np) obw[u] = eoff[i];
+          }
+        }
+      }
       if (tid == 0) {
         s_nheavy = 0;
         s_nslices = 0;
@@ -945,27 +1130,30 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         return __builtin_amdgcn_readfirstlane(reg) != 0;
       };
       auto need_b = [&](int i, int32_t) { return qm[i]; };
-      auto early_b = [&](int, int32_t v, uint64_t amask) {
-        return back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
+      auto early_b = [&](int i, int32_t v, uint64_t amask) {
+        return back_early_at<REACH, IDENT>(sg, own(i, v, amask, lane), rch, idn, v, amask, lane);
       };
-      auto finish_b = [&](int, int32_t v, uint64_t amask, double acc, const BackEarly& pre) {
-        back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
+      auto finish_b = [&](int i, int32_t v, uint64_t amask, double acc, const BackEarly& pre) {
+        back_finish_at(sg, own(i, v, amask, lane), bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
       };
       // Pair (v, lane j): the dependency of v for source j from the
       // coefficients of its neighbours on level l+1 (Eq. (3) in pull form),
       // the coefficient that replaces sigma, and the weighted contribution
       // to bc'[v], summed per entry in LDS.
-      auto pair_b = [&](int k, int, int32_t v, int32_t e0, int32_t e1, int j) {
-        const double sv = sg[(size_t)v * 64 + j];
+      auto pair_b = [&](int k, int i, int32_t v, int32_t e0, int32_t e1, int j) {
+        const size_t at = own(i, v, slots.need[k], j);
+        const double sv = sg[at];
         const double rm1 = reach_m1<REACH, IDENT>(rch, idn, v);
         const double id = IDENT ? (double)idn[v] : 1.0;
-        const double acc = pair_sum<1>(col, e0, e1, np, br, sg, idn, false, j, Q.flags);
+        double acc;
+        if constexpr (CMP) acc = pair_sum_c(col, e0, e1, np, br, obR, sg, idn, false, j, Q.flags);
+        else acc = pair_sum<1>(col, e0, e1, np, br, sg, idn, false, j, Q.flags);
         const double dv = rm1 + sv * acc;
         const int32_t sr = s_srank[j];
         if (side_absent(v, sr)) {
-          sg[(size_t)v * 64 + j] = 0.0;
+          sg[at] = 0.0;
         } else {
-          sg[(size_t)v * 64 + j] = id * (1.0 + dv) / sv;
+          sg[at] = id * (1.0 + dv) / sv;
           atomicAdd(&s_pacc[wave * 64 + k], side_contrib(s_wsrc[j], dv, rm1, sr));  // LDS (the array itself)
         }
         if constexpr (DUMP) dump.delta[(size_t)(W.s0 + j) * dump.np + v] = dv;
@@ -975,9 +1163,20 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         atomicAdd(&bcp[v], s_pacc[wave * 64 + k]);
         bw[v] = amask;
       };
+      auto pull_b = [&](int32_t e0, int32_t e1, uint64_t need) -> double {
+        if constexpr (CMP) return pull_row_c(col, e0, e1, np, br, obR, need, sg, idn, false, lane, Q.flags);
+        if (e1 - e0 <= 64) {
+          const int32_t a[1] = {e0}, d[1] = {e1 - e0};
+          const uint64_t nd[1] = {need};
+          double r[1];
+          pull_group<1>(col, a, d, np, br, nd, sg, idn, false, lane, Q.flags, r);
+          return r[0];
+        }
+        return pull_row(col, e0, e1, np, br, need, sg, idn, false, lane, Q.flags);
+      };
       for (int first = b + wave; first < e; first += WAVES * 64)
-        pull_list(first, WAVES, min(64, (e - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, col, br, sg, idn,
-                  false, lane, Q.flags, need_b, defer_long_b, early_b, finish_b, pairs, pair_b, pair_done_b);
+        pull_list(first, WAVES, min(64, (e - first + WAVES - 1) / WAVES), slots, q, rowp, np, narcs, lane, Q.flags,
+                  need_b, defer_long_b, early_b, finish_b, pairs, pair_b, pair_done_b, pull_b);
       __syncthreads();
       mark(kProfBackward);
       const int nh = min(s_nheavy, kHeavyMax);
@@ -994,7 +1193,8 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
             const int32_t a = e0 + sl * kSliceArcs;
             const int32_t bnd = min(e1, a + kSliceArcs);
             part[(size_t)(s_hoff[h] + sl) * 64 + lane] =
-                pull_row(col, a, bnd, np, br, amask, sg, idn, false, lane, Q.flags);
+                CMP ? pull_row_c(col, a, bnd, np, br, obR, amask, sg, idn, false, lane, Q.flags)
+                    : pull_row(col, a, bnd, np, br, amask, sg, idn, false, lane, Q.flags);
           }
         }
         __syncthreads();
@@ -1006,10 +1206,11 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
           if (!wave_row(rowp, v, np, narcs, &e0, &e1, Q.flags, lane)) continue;
           const uint64_t amask = qm[i];
           const int ns = (e1 - e0 + kSliceArcs - 1) / kSliceArcs;
-          const BackEarly pre = back_early<REACH, IDENT>(sg, rch, idn, v, amask, lane);
+          const size_t at = own(i, v, amask, lane);
+          const BackEarly pre = back_early_at<REACH, IDENT>(sg, at, rch, idn, v, amask, lane);
           double acc = 0.0;
           for (int sl = 0; sl < ns; ++sl) acc += part[(size_t)(s_hoff[h] + sl) * 64 + lane];
-          back_finish(sg, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
+          back_finish_at(sg, at, bcp, bw, v, amask, acc, pre, wsrc, lane, Q.flags, drow, srank);
         }
         __syncthreads();
         mark(kProfBackHeavy);

@@ -264,7 +264,9 @@ size_t estimate_plan_bytes(sbc_context c, const Prepared& prob) {
       max_team_slices = std::max<int64_t>(max_team_slices, slices);
     }
   }
-  if (max_batch) t += ms_slot_bytes(max_batch, max_batch_arcs / kMsSliceArcs + 2 * kMsHeavyMax) * 4;
+  if (max_batch)
+    t += (ms_slot_bytes(max_batch, max_batch_arcs / kMsSliceArcs + 2 * kMsHeavyMax) +
+          (size_t)max_batch * (64 * 4 + 2 * 4)) * 4;  // with the compact layout's offsets
   if (max_team)
     t += (ms_slot_bytes(max_team, max_team_slices) + (size_t)max_team * 16) *
          std::max<int64_t>(1, c->params.team_count);
@@ -531,7 +533,8 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     const int occ = occupancy_ms(B.waves, B.eu);
     int g = cus * occ;
     if (pr.slots > 0) g = (int)pr.slots;
-    const size_t per = ms_slot_bytes(stride, part_cap);
+    const bool compact = pr.batch_compact != 0;
+    const size_t per = ms_slot_bytes(stride, part_cap) + (compact ? (size_t)stride * (64 * 4 + 2 * 4) : 0);
     g = std::min<int64_t>(g, std::max<int64_t>(1, (int64_t)(budget / per)));
     g = std::max(1, std::min(g, nitems[k]));
     grid[k] = g;
@@ -561,6 +564,14 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
     if (pr.profile_phases) {
       if ((e = B.prof.alloc(G * kProfCounters * 8)) != hipSuccess) return hip_fail(e, "alloc ms prof");
       ms.prof = B.prof.as<uint64_t>();
+    }
+    ms.eoff = nullptr;
+    ms.ob = nullptr;
+    if (compact) {  // written before every read: no clearing
+      if ((e = B.eoff.alloc(G * stride * 64 * 4)) != hipSuccess) return hip_fail(e, "alloc ms eoff");
+      if ((e = B.ob.alloc(G * stride * 2 * 4)) != hipSuccess) return hip_fail(e, "alloc ms ob");
+      ms.eoff = B.eoff.as<int32_t>();
+      ms.ob = B.ob.as<int32_t>();
     }
     for (uint64_t* p : {ms.vis, ms.fa, ms.fb, ms.ba, ms.bb})
       if ((e = launch_fill_u64(p, 0, (int64_t)G * stride, own)) != hipSuccess) return hip_fail(e, "fill ms");

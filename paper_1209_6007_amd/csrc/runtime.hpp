@@ -75,6 +75,7 @@ struct Params {
   int64_t slots = 0;                  // resident workgroups per kernel (0: from occupancy)
   int64_t cluster_sources = 2;        // batch source order: 0 as is, 1 balls, 2 common-hub groups then balls
   int64_t batch_pairs = 16;           // batch kernel: rows of <= 32 arcs with at most this many lanes pulled as pairs
+  int64_t batch_compact = 1;          // batch kernel: 1 an entry's values lie together (compact), 0 64-lane rows
   int64_t deep_min_levels = 64;       // pieces deeper than this (BFS from the highest-degree vertex): deep class
   int64_t deep_wg_waves = 16;         // wavefronts per workgroup of the deep class's batch kernel
   int64_t deep_waves_per_eu = 0;      // occupancy target of the deep class's batch kernel
@@ -126,7 +127,7 @@ enum KernelClass { KC_WAVE = 0, KC_BATCH = 2, KC_DEEP = 3, KC_TEAM = 4, KC_COUNT
 
 // Per-slot state of one launch of the 64-source batch kernel.
 struct BatchState {
-  DevBuf sg, q, qm, vis, fa, fb, ba, bb, lvl, part, prof;
+  DevBuf sg, q, qm, vis, fa, fb, ba, bb, lvl, part, prof, eoff, ob;
   MsState ms{};
   int waves = 8, eu = 8;  // workgroup shape of the launch
 };

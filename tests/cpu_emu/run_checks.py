@@ -78,6 +78,15 @@ def main(which):
                     got = sbc.sbc_piece_bc(ctx.h, g.n, g.row_ptr, g.col, rr, kk, kernel=kernel)
                     assert_bc_close(got, want, 1e-9, f"piece n={n} kernel={kernel}")
                 print(f"   n={n} kernel={kernel} ok", flush=True)
+            # the batch kernel's 64-lane row layout (the compact layout is the default)
+            rctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4, "batch_compact": 0})
+            g = gg.erdos_renyi(130, 0.05, 77)
+            reach, ident = gg.random_attributes(g.n, 78, rmax=5, kmax=3)
+            want = oracle.bc_weighted(g.n, g.row_ptr, g.col, reach, ident)
+            assert_bc_close(sbc.sbc_piece_bc(rctx.h, g.n, g.row_ptr, g.col, reach, ident, kernel=3), want, 1e-9,
+                            "row layout")
+            rctx.close()
+            print("   n=130 kernel=3 row layout ok", flush=True)
         check("piece kernels", pieces)
     if "whole" in which:
         def whole():
