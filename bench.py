@@ -46,16 +46,17 @@ WORKLOADS = {
 }
 
 
-def load_traffic(workload: str, kclass: int):
+def load_traffic(workload: str, kclass):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+    taken on the current kernel source (kclass: a traversal class index, or a
+    name such as "far64" for the farness kernel)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        e = d.get(workload, {}).get(CLASS_NAMES[kclass])
+        e = d.get(workload, {}).get(kclass if isinstance(kclass, str) else CLASS_NAMES[kclass])
         from paper_1209_6007_amd import kernel_source_hash
 
         if not e or e.get("kernel_sha") != kernel_source_hash():
@@ -295,7 +296,8 @@ def farness_leg(sbc, params, name, steps, warmup):
             "host_finish_ms": float(np.mean([r["ms_finish"] for r in runs])), "pieces": pst["pieces"],
             "items": runs[-1]["items"], "grid": runs[-1]["grid"],
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                         "frac": achieved / PEAK_HBM_GBS if achieved else None,
+                         "traffic": load_traffic(name, "far64"), "kernel_class": "far64",
                          "kernel": "far_kernel<WAVES,*>", "launch_ms": ms_k, "algo_bytes_per_launch": algo_bytes,
                          "timing": "HIP events around the kernel's launch on its stream"}}
 

@@ -106,6 +106,7 @@ static int64_t* param_slot(Params& p, const char* key) {
   if (k == "order_plain") return &p.order_plain;
   if (k == "team_min_vertices") return &p.team_min_vertices;
   if (k == "team_count") return &p.team_count;
+  if (k == "team_wg_waves") return &p.team_wg_waves;
   if (k == "team_waves_per_eu") return &p.team_waves_per_eu;
   if (k == "team_spin_ms") return &p.team_spin_ms;
   if (k == "team_local_fences") return &p.team_local_fences;
@@ -132,6 +133,7 @@ sbc_status sbc_context_set_param(sbc_context ctx, const char* key, int64_t value
   if (k == "far_wg_waves") ok = value == 4 || value == 8 || value == 16;
   if (k == "deep_waves_per_eu") ok = value == 0 || value == 6 || value == 8;
   if (k == "team_waves_per_eu") ok = value == 0 || value == 8;
+  if (k == "team_wg_waves") ok = value == 4 || value == 8 || value == 16;
   if (k == "team_count") ok = value >= 1 && value <= 1024;
   if (k == "cluster_sources") ok = value >= 0 && value <= 2;
   if (k == "batch_pairs") ok = value >= 0 && value <= 64;

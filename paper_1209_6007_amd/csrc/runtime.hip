@@ -589,7 +589,7 @@ sbc_status Plan::build_impl(sbc_context c, const Prepared& prob_in, uint32_t mod
       max_rows = std::max(max_rows, rows);
       max_slices = std::max(max_slices, slices);
     }
-    team_waves = (int)pr.batch_wg_waves;
+    team_waves = (int)pr.team_wg_waves;
     team_eu = (pr.team_waves_per_eu > 0 && !opt.dump) ? 8 : 0;
     block[KC_TEAM] = team_waves * 64;
     int coop = 0;

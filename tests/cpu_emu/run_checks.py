@@ -34,14 +34,14 @@ def main(which):
     use_emulated(os.path.join(ROOT, "_build", "emu", "libshatterbc_emu.so"))
     # one resident block per launch and 4-wave batch blocks keep the
     # thread-per-lane emulation fast; the kernels' logic is the same
-    ctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4})
+    ctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 1, "batch_wg_waves": 4})
     if "single" in which:
         def single():
             # per-source levels, path counts and dependencies written by the
             # dump variant of each traversal kernel
             g = gg.decorated_random(40, 0.08, 10, 6, 3, 2000)
             reach, ident = gg.random_attributes(g.n, 3000)
-            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2})
+            tctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 0, "batch_wg_waves": 4, "team_count": 2})
             for r, k in ((None, None), (reach, ident)):
                 for s in (0, g.n // 2, g.n - 1):
                     d, sg, dl = sbc.sbc_single_source(ctx.h, g.n, g.row_ptr, g.col, s, r, k)
@@ -79,7 +79,7 @@ def main(which):
                     assert_bc_close(got, want, 1e-9, f"piece n={n} kernel={kernel}")
                 print(f"   n={n} kernel={kernel} ok", flush=True)
             # the batch kernel's 64-lane row layout (the compact layout is the default)
-            rctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4, "batch_compact": 0})
+            rctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 1, "batch_wg_waves": 4, "batch_compact": 0})
             g = gg.erdos_renyi(130, 0.05, 77)
             reach, ident = gg.random_attributes(g.n, 78, rmax=5, kmax=3)
             want = oracle.bc_weighted(g.n, g.row_ptr, g.col, reach, ident)
@@ -141,7 +141,7 @@ def main(which):
 
         def phases():
             g = gg.rmat_decorated(scale=7, seed=3)
-            pctx = sbc.Context(0, {"slots": 1, "batch_wg_waves": 4, "profile_phases": 1, "wave_max_vertices": 0})
+            pctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 1, "batch_wg_waves": 4, "profile_phases": 1, "wave_max_vertices": 0})
             G = sbc.Graph(g.n, g.row_ptr, g.col)
             G.preprocess("dai")
             plan = sbc.sbc_plan_create(pctx.h, G.h, sbc.SBC_COMPRESSED)
@@ -174,7 +174,7 @@ def main(which):
             # two XCDs (uneven ranks, agent-scope fences); 8 teams by XCD, of
             # which 6 stay empty
             for tc, slots in ((2, 0), (1, 3), (8, 0)):
-                tctx = sbc.Context(0, {"slots": slots, "batch_wg_waves": 4, "team_count": tc,
+                tctx = sbc.Context(0, {"team_wg_waves": 4, "slots": slots, "batch_wg_waves": 4, "team_count": tc,
                                        "team_min_vertices": 3})
                 sizes = (5, 65, 130) if tc == 2 or full else (65,)
                 for n in sizes:
@@ -206,14 +206,14 @@ def main(which):
             g2 = gg.csr_from_edges(n, u, v)
             src = np.arange(0, 16, dtype=np.int32)
             want = oracle.bc_plain(g2.n, g2.row_ptr, g2.col, sources=src)
-            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 64,
+            tctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 64,
                                    "team_split_arcs": 512})
             G = sbc.Graph(g2.n, g2.row_ptr, g2.col)
             got = sbc.sbc_betweenness_sources(tctx.h, G.h, src)
             assert_bc_close(got, want, 1e-9, "team hub rows")
             tctx.close()
             # a low split threshold: many rows of every level are pulled in slices
-            tctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
+            tctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
                                    "team_split_arcs": 64})
             for g in (gg.rmat_decorated(scale=7, seed=5), gg.complete_bipartite(40, 80)):
                 want = oracle.bc(g)
@@ -225,7 +225,7 @@ def main(which):
 
         def team_phases():
             g = gg.rmat_decorated(scale=7, seed=3)
-            pctx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
+            pctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 0, "batch_wg_waves": 4, "team_count": 2, "team_min_vertices": 3,
                                    "profile_phases": 1})
             G = sbc.Graph(g.n, g.row_ptr, g.col)
             G.preprocess("dai")
@@ -245,7 +245,7 @@ def main(which):
             # no barrier waiting allowed: the team aborts, every wave leaves the
             # kernel, and the run reports a device error instead of hanging
             g = gg.rmat_decorated(scale=6, seed=3)
-            actx = sbc.Context(0, {"slots": 0, "batch_wg_waves": 4, "team_count": 1, "team_min_vertices": 3,
+            actx = sbc.Context(0, {"team_wg_waves": 4, "slots": 0, "batch_wg_waves": 4, "team_count": 1, "team_min_vertices": 3,
                                    "team_spin_ms": 0})
             try:
                 sbc.betweenness(g.n, g.row_ptr, g.col, mode="compressed", ctx=actx)
@@ -260,7 +260,7 @@ def main(which):
             # the small-piece kernel: forced on single pieces (few and many
             # levels, a hub, items of a few sources), and by default routing
             # on graphs that shatter into small pieces
-            wctx = sbc.Context(0, {"slots": 2, "batch_wg_waves": 4, "deep_wg_waves": 4})
+            wctx = sbc.Context(0, {"team_wg_waves": 4, "slots": 2, "batch_wg_waves": 4, "deep_wg_waves": 4})
             cases = [("er3", gg.erdos_renyi(3, 0.9, 1)), ("er5", gg.erdos_renyi(5, 0.9, 2)),
                      ("er65", gg.erdos_renyi(65, 0.1, 3)), ("er130", gg.erdos_renyi(130, 0.05, 4)),
                      ("cycle40", gg.cycle(40)), ("K9", gg.complete(9)), ("K3,70", gg.complete_bipartite(3, 70))]
@@ -347,7 +347,7 @@ def main(which):
             # farness kernel: per-piece sums equal to the oracle's exactly, and
             # the whole farness after the host pass; two slots reused by many
             # items, levels wider than a workgroup, weighted and unweighted pieces
-            fctx = sbc.Context(0, {"far_wg_waves": 4, "slots": 2})
+            fctx = sbc.Context(0, {"team_wg_waves": 4, "far_wg_waves": 4, "slots": 2})
             cases = [("decorated", gg.decorated_random(60, 0.06, 15, 4, 4, 5)), ("grid", gg.grid2d(9, 11)),
                      ("blocks", gg.block_tree(n_pieces=10, max_size=80, seed=2)), ("er400", gg.erdos_renyi(400, 0.02, 6)),
                      ("path3", gg.path(3)), ("K5", gg.complete(5))]
