@@ -66,99 +66,111 @@ typedef struct {
     int status;
 } oracle_job;
 
-/* Workspace of one traversal: queue Q, stack S, predecessor lists P, and the
- * arrays sigma, d, delta of Algorithm 1. */
+/* Workspace of one source: the vertices in order of distance from the source
+ * (and where each distance starts), and per vertex its distance d, path
+ * count sigma and dependency delta. */
 typedef struct {
-    int32_t *Q, *S, *Pcnt, *Pbuf, *d;
+    int32_t *order, *start, *d;
     double *sigma, *delta;
 } oracle_ws;
 
 static int ws_alloc(oracle_ws *w, int32_t n, int64_t arcs) {
+    (void)arcs;
     size_t nn = n > 0 ? (size_t)n : 1;
-    w->Q = malloc(nn * sizeof(int32_t));
-    w->S = malloc(nn * sizeof(int32_t));
-    w->Pcnt = malloc(nn * sizeof(int32_t));
-    w->Pbuf = malloc((arcs > 0 ? (size_t)arcs : 1) * sizeof(int32_t));
+    w->order = malloc(nn * sizeof(int32_t));
+    w->start = malloc((nn + 2) * sizeof(int32_t));
     w->d = malloc(nn * sizeof(int32_t));
     w->sigma = malloc(nn * sizeof(double));
     w->delta = malloc(nn * sizeof(double));
-    return w->Q && w->S && w->Pcnt && w->Pbuf && w->d && w->sigma && w->delta;
+    return w->order && w->start && w->d && w->sigma && w->delta;
 }
 
 static void ws_free(oracle_ws *w) {
-    free(w->Q); free(w->S); free(w->Pcnt); free(w->Pbuf); free(w->d);
-    free(w->sigma); free(w->delta);
+    free(w->order); free(w->start); free(w->d); free(w->sigma); free(w->delta);
 }
 
 /*
- * One source s.  Phase 1 is the BFS of Algorithm 1: every vertex popped from
- * Q is pushed on S; a neighbour w seen for the first time gets d[w] = d[v]+1
- * and is queued; when d[w] = d[v]+1, v is a predecessor of w and sigma[w]
- * grows by the number of shortest paths through v.  With identical-vertex
- * weights that number is sigma[v]*ident[v] for v != s (Section 3.3.3).
+ * One source s, distance by distance.
  *
- * Phase 2 pops S (non-increasing distance) and pushes dependencies to the
- * predecessors, Eq. (3):
- *   delta[v] += sigma[v]/sigma[w] * (1 + delta[w])               (Alg. 1)
- *   delta[v] += sigma[v]/sigma[w] * ident[w] * (1 + delta[w])     (Sec. 3.3.3)
- * starting from delta[v] = reach[v]-1 (Alg. 2, initialisation line) or 0.
- * A popped w != s adds delta[w] to bc[w], scaled by reach[s] (Alg. 2,
- * accumulation line) and ident[s] (Sec. 3.3.3).
+ * Distances: a breadth-first search lists the vertices reachable from s in
+ * non-decreasing distance (order[], with distance k occupying
+ * order[start[k] .. start[k+1])).
  *
- * The arrays d/sigma/delta are left holding this source's values.
+ * Path counts (Section 2.1), nearest first: sigma[s] = 1 and for every other
+ * reached w, sigma[w] is the sum over its neighbours v one step closer to s
+ * of the paths that reach v and can be continued through it: sigma[v], times
+ * ident[v] when v != s stands for identical vertices (Section 3.3.3).
+ *
+ * Dependencies, farthest first, Eq. (3): delta[v] starts at the targets v
+ * stands for besides itself -- reach[v]-1 in Algorithm 2 (Section 3.2.1), 0
+ * in Algorithm 1 -- and adds, for every neighbour w one step farther from s,
+ * sigma[v]/sigma[w] * ident[w] * (1 + delta[w]) (ident[w] = 1 without
+ * identical vertices).  Every reached v != s then adds delta[v] to bc[v],
+ * times the weight of the source: reach[s]*ident[s] (Algorithm 2 with
+ * Section 3.3.3), or for oracle_bc_classes the members' reach sum reach[s],
+ * the dependency then starting at the members' mean reach minus one.
+ *
+ * The arrays d/sigma/delta are left holding this source's values (d = -1 and
+ * sigma = delta = 0 where s does not reach).
  */
 static void one_source(const oracle_job *J, oracle_ws *w, int32_t s, double *bc) {
     const int32_t n = J->n;
     const int32_t *rp = J->row_ptr, *col = J->col;
+    const int weighted = J->weighted;
     for (int32_t v = 0; v < n; ++v) {
-        w->Pcnt[v] = 0;
-        w->sigma[v] = 0.0;
         w->d[v] = -1;
+        w->sigma[v] = 0.0;
+        w->delta[v] = 0.0;
     }
-    int32_t qh = 0, qt = 0, sp = 0;
-    w->Q[qt++] = s;
-    w->sigma[s] = 1.0;
+    /* distances */
+    int32_t cnt = 0, levels = 0;
+    w->order[cnt++] = s;
     w->d[s] = 0;
-    /* Phase 1: BFS from s. */
-    while (qh < qt) {
-        int32_t v = w->Q[qh++];
-        w->S[sp++] = v;
-        double paths_via_v = w->sigma[v];
-        if (J->weighted && J->ident && v != s) paths_via_v *= (double)J->ident[v];
+    w->start[0] = 0;
+    for (int32_t lo = 0; lo < cnt; ++levels) {
+        const int32_t hi = cnt;
+        w->start[levels + 1] = hi;
+        for (int32_t k = lo; k < hi; ++k) {
+            const int32_t v = w->order[k];
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+                if (w->d[col[e]] < 0) {
+                    w->d[col[e]] = w->d[v] + 1;
+                    w->order[cnt++] = col[e];
+                }
+        }
+        lo = hi;
+    }
+    /* path counts, nearest first */
+    w->sigma[s] = 1.0;
+    for (int32_t k = 1; k < cnt; ++k) {
+        const int32_t x = w->order[k];
+        double paths = 0.0;
+        for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+            const int32_t v = col[e];
+            if (w->d[v] != w->d[x] - 1) continue;
+            double through = w->sigma[v];
+            if (weighted && J->ident && v != s) through *= (double)J->ident[v];
+            paths += through;
+        }
+        w->sigma[x] = paths;
+    }
+    /* dependencies, farthest first, and the source's weight */
+    double weight = 1.0;
+    if (J->classes) weight = (double)J->reach[s];
+    else if (weighted) weight = (J->reach ? (double)J->reach[s] : 1.0) * (J->ident ? (double)J->ident[s] : 1.0);
+    for (int32_t k = cnt - 1; k >= 0; --k) {
+        const int32_t v = w->order[k];
+        double dv = 0.0;
+        if (J->classes) dv = (double)J->reach[v] / (double)J->ident[v] - 1.0;
+        else if (weighted && J->reach) dv = (double)(J->reach[v] - 1);
         for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-            int32_t x = col[e];
-            if (w->d[x] < 0) {
-                w->Q[qt++] = x;
-                w->d[x] = w->d[v] + 1;
-            }
-            if (w->d[x] == w->d[v] + 1) {
-                w->sigma[x] += paths_via_v;
-                w->Pbuf[rp[x] + w->Pcnt[x]++] = v;
-            }
+            const int32_t x = col[e];
+            if (w->d[x] != w->d[v] + 1) continue;
+            const double kx = (weighted && J->ident) ? (double)J->ident[x] : 1.0;
+            dv += w->sigma[v] / w->sigma[x] * kx * (1.0 + w->delta[x]);
         }
-    }
-    /* Phase 2: back propagation. */
-    for (int32_t v = 0; v < n; ++v) {
-        if (J->classes) /* a member's own hung targets: the members' mean reach minus one */
-            w->delta[v] = (double)J->reach[v] / (double)J->ident[v] - 1.0;
-        else
-            w->delta[v] = (J->weighted && J->reach) ? (double)(J->reach[v] - 1) : 0.0;
-    }
-    double src_weight = 1.0;
-    if (J->classes) {
-        src_weight = (double)J->reach[s]; /* every member's hung vertices are sources */
-    } else if (J->weighted) {
-        if (J->reach) src_weight *= (double)J->reach[s];
-        if (J->ident) src_weight *= (double)J->ident[s];
-    }
-    while (sp > 0) {
-        int32_t x = w->S[--sp];
-        double kx = (J->weighted && J->ident) ? (double)J->ident[x] : 1.0;
-        for (int32_t i = 0; i < w->Pcnt[x]; ++i) {
-            int32_t v = w->Pbuf[rp[x] + i];
-            w->delta[v] += w->sigma[v] / w->sigma[x] * kx * (1.0 + w->delta[x]);
-        }
-        if (x != s && bc) bc[x] += src_weight * w->delta[x];
+        w->delta[v] = dv;
+        if (v != s && bc) bc[v] += weight * dv;
     }
 }
 
