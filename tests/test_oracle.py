@@ -389,3 +389,19 @@ def test_classes_of_unequal_reach_on_expanded_graph(seed):
             rc = members[v][j]
             pred = got[v] + (rc - R / k) * (N - R) + (R - rc) * (rc - 1) + (rc - 1) * (N - 2) + share[v]
             assert abs(pred - want[c]) <= 1e-9 * max(1.0, abs(want[c])), (v, j, pred, want[c])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_brute_distance_sum_against_farness_and_scores(seed):
+    """brute.distance_sum_ordered (matrix powers) equals the farness sum (one
+    breadth-first search per vertex, in C) minus the ordered connected pairs,
+    and the sum of Eq. (1) scores (every interior vertex of a shortest path
+    counts once per pair)."""
+    r = gg.rng(seed + 40)
+    n = int(r.integers(2, 12))
+    g = gg.erdos_renyi(n, float(r.uniform(0.1, 0.7)), 600 + seed)
+    comp = gg.components(g)
+    pairs = int(sum(c * (c - 1) for c in np.bincount(comp)))
+    got = brute.distance_sum_ordered(g.n, g.row_ptr, g.col)
+    assert got == int(oracle.farness(g.n, g.row_ptr, g.col).sum()) - pairs
+    assert abs(got - float(brute.bc_bruteforce(g.n, g.row_ptr, g.col).sum())) <= 1e-9 * max(1, got)
