@@ -243,7 +243,7 @@ def test_worked_example_twins_of_unequal_reach():
 
 @pytest.mark.parametrize("name", ["blocks", "rmat"])
 def test_bc_pieces_mapped_back_is_the_oracle(name):
-    """The check the full-size block tree uses on the GPU machine: the oracle's
+    """The check the full-size block tree uses on the GPU: the oracle's
     bc' of every exported piece (oracle.bc_pieces), mapped back with Eq. (5),
     equals Algorithm 1 on the original graph (Theorem 1)."""
     g = gg.block_tree(n_pieces=80, max_size=300, seed=15) if name == "blocks" else gg.rmat_decorated(scale=9, seed=8)
