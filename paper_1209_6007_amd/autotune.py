@@ -10,7 +10,9 @@ keeps the fastest:
   XCD share one 64-source batch) or one workgroup per batch, i.e. the
   small/large threshold ``team_min_vertices``, and ``team_max_levels``, which
   keeps deep pieces off the team kernel;
-* the workgroup shape (``batch_wg_waves``) and the number of teams;
+* the workgroup shape of one-workgroup batches (``batch_wg_waves``) and the
+  number of teams (the team kernel keeps ``team_wg_waves``, whose 8 and 16
+  waves measured within 1% of each other);
 * then, with that choice fixed, whether small pieces run on the small-piece
   kernel (one source per wavefront, the piece in LDS) and its workgroup
   shape (``wave_max_vertices``, ``wave_wg_waves``), when the workload has
