@@ -217,6 +217,28 @@ def test_deterministic_runs_are_bit_equal(ctx, name):
     assert_bc_close(runs[0], want, RTOL, f"{name} deterministic")
 
 
+def test_deterministic_runs_with_unequal_reach_twins(ctx):
+    """SBC_DETERMINISTIC with identical vertices merged whatever their reach
+    ("odau"): the batch kernel (compact layout), the batch kernel with 64-lane
+    rows and the team kernel give the same bits; the result matches the
+    oracle within the slack a signed per-member term needs."""
+    g = gg.rmat_decorated(scale=12, seed=71)
+    want = oracle.bc(g)
+    G = sbc.Graph(g.n, g.row_ptr, g.col)
+    st = G.preprocess("odau")
+    assert st["twin_classes"] > 0
+    mode = sbc.SBC_COMPRESSED | sbc.SBC_DETERMINISTIC
+    runs = []
+    for params in ({"team_min_vertices": 0}, {"team_min_vertices": 0, "batch_compact": 0, "slots": 29},
+                   {"team_min_vertices": 64, "team_count": 16}):
+        c = sbc.Context(0, params)
+        runs.append(sbc.sbc_betweenness(c.h, G.h, mode))
+        c.close()
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r, runs[0])
+    assert_bc_close(runs[0], want, RTOL, "odau deterministic", atol=unequal_atol(g.n))
+
+
 def test_team_kernel_without_cooperative_launch():
     """team_cooperative = 0: the team kernel as an ordinary launch of a grid
     the device holds at once gives the oracle's result."""
