@@ -180,7 +180,7 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *   "team_max_levels"    pieces whose breadth-first depth from their highest-degree
  *                        vertex exceeds this stay on the one-workgroup batch
  *                        kernel (0: no limit)
- *   "far_wg_waves"       wavefronts per workgroup of the farness kernel (4, 8, 16; default 8)
+ *   "far_wg_waves"       wavefronts per workgroup of the farness kernel (4, 8, 16; default 16)
  *   "server_order"       serving: 1 (default) least estimated work first, 0 oldest first
  *   "server_max_wait_ms" serving: a job waiting longer is taken first (default 30000)
  *   "sample_items"       tuning only (0: off): plans run an evenly spaced sample of

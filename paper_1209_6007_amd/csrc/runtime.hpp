@@ -92,7 +92,7 @@ struct Params {
   int64_t team_split_arcs = 2048;     // team kernel: rows with more arcs are split into slices
   int64_t team_max_levels = 0;        // pieces deeper than this stay off the team kernel (0: no limit)
   int64_t sample_items = 0;           // tuning only: run an evenly spaced sample of this many items per class
-  int64_t far_wg_waves = 8;           // wavefronts per workgroup of the farness kernel
+  int64_t far_wg_waves = 16;          // wavefronts per workgroup of the farness kernel
   int64_t server_order = 1;           // serving: 0 oldest job first, 1 least estimated work first
   int64_t server_max_wait_ms = 30000; // serving, order 1: a job waiting longer is taken first
 };
