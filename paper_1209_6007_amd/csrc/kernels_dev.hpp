@@ -376,25 +376,52 @@ __device__ __forceinline__ double pull_row_c(const int32_t* __restrict__ col, in
   return acc;
 }
 
-// pair_sum for the compact layout.
+// pair_sum for the compact layout.  With U > 1 the arcs go U at a time:
+// their neighbour ids, then masks and entry offsets, then values are loaded
+// together, so a lane waits for three round trips per U arcs instead of per
+// arc.  The values are added one by one in arc order, as with U = 1, so the
+// bits do not depend on U.
+template <int U>
 __device__ __forceinline__ double pair_sum_c(const int32_t* __restrict__ col, int32_t e0, int32_t e1, int32_t np,
                                              uint64_t* __restrict__ mk, const int32_t* __restrict__ ob,
                                              const double* __restrict__ sg, const int32_t* __restrict__ idn,
                                              bool scale, int j, int32_t* flags) {
   double acc = 0.0;
-  for (int32_t e = e0; e < e1; ++e) {
-    int32_t u = col_load(&col[e]);
-    if (u < 0 || u >= np) {
-      raise_flag(flags, kFlagBadArc);
-      continue;
+  for (int32_t e = e0; e < e1; e += U) {
+    int32_t u[U], o[U];
+    uint64_t m[U];
+    double x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      u[k] = -1;
+      if (e + k < e1) {
+        u[k] = col_load(&col[e + k]);
+        if (u[k] < 0 || u[k] >= np) {
+          raise_flag(flags, kFlagBadArc);
+          u[k] = -1;
+        }
+      }
     }
-    const uint64_t m = group_load(&mk[u]);
-    const int32_t o = ob[u];
-    if ((m >> j) & 1) {
-      double x = row_load(&sg[(size_t)o + lane_rank(m, j)]);
-      if (scale) x *= (double)idn[u];
-      acc += x;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      m[k] = 0;
+      o[k] = 0;
+      if (u[k] >= 0) {
+        m[k] = group_load(&mk[u[k]]);
+        o[k] = ob[u[k]];
+      }
     }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      x[k] = 0.0;
+      if ((m[k] >> j) & 1) {
+        x[k] = row_load(&sg[(size_t)o[k] + lane_rank(m[k], j)]);
+        if (scale) x[k] *= (double)idn[u[k]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if ((m[k] >> j) & 1) acc += x[k];
   }
   return acc;
 }
@@ -740,6 +767,9 @@ template <int WAVES, int EU, bool REACH, bool IDENT, bool DUMP = false, bool CMP
 __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueArgs Q, MsState st, DumpOut dump) {
   if (Q.magic != kArgMagic) return;
   constexpr int BLOCK = WAVES * 64;
+  // Arcs a pair loads together (compact layout): four where the compiler
+  // chooses the register count, one under an occupancy target's budget.
+  constexpr int kPairU = EU == 0 ? 4 : 1;
   __shared__ int s_item;
   __shared__ int s_cnt[3];
   __shared__ int s_wtot[WAVES];
@@ -984,7 +1014,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       // Pair (w, lane j): sigma of w for source j from the neighbours on level L.
       auto pair_f = [&](int k, int i, int32_t w, int32_t e0, int32_t e1, int j) {
         double acc;
-        if constexpr (CMP) acc = pair_sum_c(col, e0, e1, np, fcur, obL, sg, idn, scale, j, Q.flags);
+        if constexpr (CMP) acc = pair_sum_c<kPairU>(col, e0, e1, np, fcur, obL, sg, idn, scale, j, Q.flags);
         else acc = pair_sum<1>(col, e0, e1, np, fcur, sg, idn, scale, j, Q.flags);
         sg[own(i, w, slots.need[k], j)] = acc;
       };
@@ -1146,7 +1176,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
         const double rm1 = reach_m1<REACH, IDENT>(rch, idn, v);
         const double id = IDENT ? (double)idn[v] : 1.0;
         double acc;
-        if constexpr (CMP) acc = pair_sum_c(col, e0, e1, np, br, obR, sg, idn, false, j, Q.flags);
+        if constexpr (CMP) acc = pair_sum_c<kPairU>(col, e0, e1, np, br, obR, sg, idn, false, j, Q.flags);
         else acc = pair_sum<1>(col, e0, e1, np, br, sg, idn, false, j, Q.flags);
         const double dv = rm1 + sv * acc;
         const int32_t sr = s_srank[j];

@@ -91,6 +91,21 @@ def test_rmat17_equal_reach_twins_vs_oracle(ctx):
     assert_bc_close(got, want, RTOL, "rmat17 odai vs oracle")
 
 
+def test_rmat17_other_team_shapes_vs_oracle(ctx):
+    """Other team shapes (32 teams; 16 teams of 16-wave workgroups) sum in
+    other orders: the result stays within the same bound of the oracle."""
+    g = gg.rmat_decorated()
+    want = oracle_in_chunks(g, "rmat17")
+    for params in ({"team_count": 32}, {"team_count": 16, "team_wg_waves": 16}):
+        c = sbc.Context(0, params)
+        try:
+            _, got, st = bench_run(c, g)
+        finally:
+            c.close()
+        print(f"rmat17 {params}: {st['ms_device']:.1f} ms, items {st['items_class']}", flush=True)
+        assert_bc_close(got, want, RTOL, f"rmat17 {params} vs oracle", atol=unequal_atol(g.n))
+
+
 def test_grid512_compressed_vs_oracle(ctx):
     """512x512 grid with 12% of edges deleted (about 800 levels): the whole
     compressed result against Algorithm 1 on the original graph."""
