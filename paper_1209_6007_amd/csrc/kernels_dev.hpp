@@ -785,7 +785,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
   __shared__ int s_heavy[kHeavyMax];
   __shared__ int s_hoff[kHeavyMax];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar registers
   // The pull phases gather entries in the phase-A scratch arrays (free then).
   const EntrySlots slots{s_scan + wave * 64, s_e0 + wave * 64, s_e1 + wave * 64,
                          s_f + wave * 64,    s_poff + wave * 64, s_pacc + wave * 64};
@@ -1321,7 +1321,7 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
   constexpr int BLOCK = WAVES * 64;
   SBC_DYNAMIC_LDS(lds_raw);
   TeamShared<BLOCK>& S = *reinterpret_cast<TeamShared<BLOCK>*>(lds_raw);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar registers
   const int nteams = T.nteams;
   if (nteams < 1 || T.heavy_max < 1) return;  // every workgroup takes this exit together
   // Join a team by XCD: with nteams a multiple of 8, XCD x hosts teams
