@@ -553,6 +553,13 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// A work item every lane read alike, in scalar registers (so are the piece
+// bounds and pointers derived from it).
+__device__ __forceinline__ WorkItem uniform_item(const WorkItem& w) {
+  return {__builtin_amdgcn_readfirstlane(w.piece), __builtin_amdgcn_readfirstlane(w.s0),
+          __builtin_amdgcn_readfirstlane(w.s1), __builtin_amdgcn_readfirstlane(w.kind)};
+}
+
 // One wave's pull of the n <= 64 entries first, first + step, ...,
 // first + (n-1)*step of the queue q, with the callbacks of pull_entries and
 // early(i, v, need), whose result finish gets as a fifth argument: the loads
@@ -828,10 +835,10 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
   while (true) {
     if (tid == 0) s_item = atomicAdd(Q.head, 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it < 0 || it >= Q.nitems) break;
-    const WorkItem W = Q.items[it];
+    const WorkItem W = uniform_item(Q.items[it]);
     int32_t vb, np;
     const bool item_good = item_ok(P, Q, W, st.stride, &vb, &np) && W.s1 - W.s0 >= 1 && W.s1 - W.s0 <= 64;
     if (!item_good) {
@@ -841,11 +848,14 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_kernel(DevPieces P, QueueAr
       }
       continue;
     }
+    vb = __builtin_amdgcn_readfirstlane(vb);
+    np = __builtin_amdgcn_readfirstlane(np);
     const int32_t* rowp = P.row + vb;
     const int32_t* col = P.col;
     const int32_t* rch = REACH ? P.reach + vb : nullptr;
     const int32_t* idn = IDENT ? P.ident + vb : nullptr;
-    double* bcp = Q.item_base ? Q.item_out + Q.item_base[it] : P.bcp + vb;  // the item's own area when deterministic
+    // the item's own area when deterministic
+    double* bcp = Q.item_base ? Q.item_out + (int64_t)uniform64((uint64_t)Q.item_base[it]) : P.bcp + vb;
     const int nsrc = W.s1 - W.s0;  // 1..64
 
     // Lane j runs source src_order[vb + s0 + j].
@@ -1444,9 +1454,9 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
   for (int iter = 0;; ++iter) {
     if (leader) ctl_store(&ctl->item[iter & 1], atomicAdd(Q.head, 1));
     if (!team_sync(kProfFetch)) break;
-    const int it = ctl_load(&ctl->item[iter & 1]);
+    const int it = __builtin_amdgcn_readfirstlane(ctl_load(&ctl->item[iter & 1]));
     if (it < 0 || it >= Q.nitems) break;  // the same verdict in the whole team
-    const WorkItem W = Q.items[it];
+    const WorkItem W = uniform_item(Q.items[it]);
     int32_t vb, np;
     const bool item_good = item_ok(P, Q, W, st.stride, &vb, &np) && W.s1 - W.s0 >= 1 && W.s1 - W.s0 <= 64;
     if (!item_good) {
@@ -1456,11 +1466,14 @@ __global__ SBC_KERNEL_BOUNDS(WAVES * 64, EU) void ms_team_kernel(DevPieces P, Qu
       }
       continue;
     }
+    vb = __builtin_amdgcn_readfirstlane(vb);
+    np = __builtin_amdgcn_readfirstlane(np);
     const int32_t* rowp = P.row + vb;
     const int32_t* col = P.col;
     const int32_t* rch = REACH ? P.reach + vb : nullptr;
     const int32_t* idn = IDENT ? P.ident + vb : nullptr;
-    double* bcp = Q.item_base ? Q.item_out + Q.item_base[it] : P.bcp + vb;  // the item's own area when deterministic
+    // the item's own area when deterministic
+    double* bcp = Q.item_base ? Q.item_out + (int64_t)uniform64((uint64_t)Q.item_base[it]) : P.bcp + vb;
     const int nsrc = W.s1 - W.s0;
 
     // Lane j runs source src_order[vb + s0 + j].
