@@ -164,7 +164,7 @@ sbc_status sbc_context_destroy(sbc_context ctx);
  *                        workgroups of one XCD share one 64-source batch
  *   "team_count"         teams of the team kernel (default 64; a multiple of 8
  *                        puts team_count/8 teams on each of the 8 XCDs)
- *   "team_wg_waves"      wavefronts per workgroup of the team kernel (4, 8, 16; default 8)
+ *   "team_wg_waves"      wavefronts per workgroup of the team kernel (4, 8, 16; default 16)
  *   "team_waves_per_eu"  occupancy target of the team kernel: 0 or 8
  *   "team_local_fences"  1 (default): a team whose workgroups all run on one XCD
  *                        synchronises through that XCD's L2 (L1 invalidation

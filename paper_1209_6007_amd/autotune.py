@@ -11,8 +11,8 @@ keeps the fastest:
   small/large threshold ``team_min_vertices``, and ``team_max_levels``, which
   keeps deep pieces off the team kernel;
 * the workgroup shape of one-workgroup batches (``batch_wg_waves``) and the
-  number of teams (the team kernel keeps ``team_wg_waves``, whose 8 and 16
-  waves measured within 1% of each other);
+  number of teams (the team kernel keeps ``team_wg_waves``, whose 16 and 8
+  waves measured within 2% of each other);
 * then, with that choice fixed, whether small pieces run on the small-piece
   kernel (one source per wavefront, the piece in LDS) and its workgroup
   shape (``wave_max_vertices``, ``wave_wg_waves``), when the workload has

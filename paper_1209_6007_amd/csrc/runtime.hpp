@@ -84,7 +84,7 @@ struct Params {
   int64_t order_plain = 0;            // 1: plain problems renumbered breadth-first
   int64_t team_min_vertices = 16384;  // pieces from this size: team kernel (0: never)
   int64_t team_count = 64;            // teams of the team kernel (a multiple of 8: that many per XCD / 8)
-  int64_t team_wg_waves = 8;          // wavefronts per workgroup of the team kernel (4, 8 or 16)
+  int64_t team_wg_waves = 16;         // wavefronts per workgroup of the team kernel (4, 8 or 16)
   int64_t team_waves_per_eu = 8;      // occupancy target of the team kernel (0 or 8)
   int64_t team_spin_ms = 20000;       // bound of one team barrier wait
   int64_t team_local_fences = 1;      // 1: teams on one XCD fence through L2 only
